@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Benchmark of the BEC-preconditioned all-at-once heat solve on one MI355X.
+
+One step = assemble the all-at-once right-hand side from (f, u0) and solve
+L u = f by right-preconditioned FGMRES with P_eps to rel.res 1e-8 (FP64 unless
+--precision says otherwise).  Inputs are seeded synthetic arrays already in
+HBM when the timed region starts.  Prints ONE JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "space-time unknowns/s to rel.res 1e-8 + GMRES iters; FP64 vs mixed vs learned"
+PEAKS = {  # MI355X published dense peaks
+    "hbm_GBs": 8000.0,
+    "fp64_TFs": 78.6,
+    "fp32_TFs": 157.3,
+    "bf16_TFs": 2500.0,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="heat2d_255x256")
+    ap.add_argument("--precision", default=None, help="fp64 | fp32 (default: the workload's)")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--restart", type=int, default=50)
+    ap.add_argument("--variants", default="fp32", help="comma list of extra precisions to time")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=32)
+    return ap.parse_args()
+
+
+def dst_flops_per_launch(w):
+    """Algorithmic flops of one DST-I mode product: every real plane of the
+    n/2+1 kept frequency blocks (2 planes each) gets an m_d x m_d product along
+    one axis: 2 * (n/2+1) * (m / m_d) * m_d^2 * 2 = 4 (n/2+1) m m_d."""
+    return 4.0 * (w.n // 2 + 1) * w.m * w.m1
+
+
+def time_solver(s, fd, u0d, tol, restart, steps, warmup, prof_classes):
+    import torch
+    rhs = s.new()
+    u = s.new()
+    info = None
+
+    def step():
+        s.build_rhs(fd, u0d, out=rhs)
+        return s.solve(rhs, tol=tol, maxit=200, restart=restart, u=u)[1]
+
+    for _ in range(warmup):
+        info = step()
+    torch.cuda.synchronize()
+    s.profile(prof_classes)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = s.profile_read()
+    s.profile(None)
+    return dt / steps, info, prof, u, rhs
+
+
+def cpu_baseline(w, f, u0, sample_steps):
+    """The oracle's GMRES-BEC on the first `sample_steps` time levels of the
+    same workload (same grid, tau, eps, source and u0), single BLAS thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import heat
+    ns = min(sample_steps, w.n)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        p = heat.Problem(w.m1, w.dim, ns, T=w.tau * ns, eps=w.epsilon)
+        rhs = p.rhs(f[:ns], u0)
+        x, it, hist = p.gmres(rhs, tol=1e-8)
+        dt = time.perf_counter() - t0
+    dof = ns * w.m
+    return {"value": dof / dt, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": f"{w.name}: first {ns} of {w.n} time steps (same grid, tau, eps, "
+                      f"source, u0), oracle GMRES-BEC (naive DFT + sparse LU per frequency, "
+                      f"factorisations included) to rel.res 1e-8, {it} iterations, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the method runs on one MI355X here); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    from paper_2002_01108_amd import Solver
+
+    w = W.WORKLOADS[args.workload]
+    prec = args.precision or w.precision
+    if w.coefficient != "const":
+        raise SystemExit("variable-coefficient workloads are benchmarked separately")
+    f, u0, _ = W.make(w)
+    fd = torch.from_numpy(f).cuda()
+    u0d = torch.from_numpy(u0).cuda()
+    restart = args.restart if w.dim < 3 else min(args.restart, 10)
+
+    s = Solver(w.dim, w.m1, w.n, T=w.T, eps=w.epsilon, precision=prec)
+    t_step, info, prof, u, rhs = time_solver(s, fd, u0d, args.tol, restart, args.steps,
+                                             args.warmup, ["dst"])
+    dof = w.dof
+    value = dof / t_step
+
+    dst_ms, dst_n = prof["dst"]
+    flops = dst_flops_per_launch(w)
+    avg_s = dst_ms / 1e3 / max(dst_n, 1)
+    peak = {"fp64": PEAKS["fp64_TFs"], "fp32": PEAKS["fp32_TFs"],
+            "bf16x3": PEAKS["bf16_TFs"]}[prec]
+    achieved = flops / avg_s / 1e12 if dst_n else None
+    roofline = {"kernel": f"dst_gemm_{prec} (one DST-I mode product)", "bound": "mfma",
+                "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak if achieved else None, "traffic": None,
+                "avg_launch_us": avg_s * 1e6, "launches": dst_n,
+                "flops_per_launch": flops}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "unknowns/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_step * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else f"f64 outer / {prec} preconditioner",
+        "data": "synthetic",
+        "config": {"workload": w.name, "dim": w.dim, "m1": w.m1, "n": w.n, "T": w.T,
+                   "eps": w.epsilon, "tol": args.tol, "precision": prec,
+                   "restart": restart, "dof": dof},
+        "gmres_iters": info["iters"], "rel_res": info["final_res"],
+        "roofline": roofline,
+    }
+
+    if not args.no_oracle_check:
+        from oracle import heat
+        p = heat.Problem(w.m1, w.dim, w.n, eps=w.epsilon)
+        exact = p.exact(p.rhs(f, u0))
+        got = u.cpu().numpy()
+        out["rel_err_vs_oracle"] = float(np.linalg.norm(got - exact) / np.linalg.norm(exact))
+
+    variants = {}
+    for vp in [v for v in args.variants.split(",") if v and v != prec]:
+        try:
+            s.set_precision(vp)
+        except Exception as e:     # precision not available in this build
+            variants[vp] = {"error": str(e)}
+            continue
+        tv, iv, _, uv, _ = time_solver(s, fd, u0d, args.tol, restart, max(1, args.steps // 2),
+                                       1, [])
+        rec = {"value": dof / tv, "ms_per_step": tv * 1e3, "gmres_iters": iv["iters"],
+               "rel_res": iv["final_res"]}
+        if "rel_err_vs_oracle" in out:
+            rec["rel_err_vs_oracle"] = float(np.linalg.norm(uv.cpu().numpy() - exact)
+                                             / np.linalg.norm(exact))
+        variants[vp] = rec
+    if variants:
+        out["variants"] = variants
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, f, u0, args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,169 @@
+/*
+ * aao.h - C ABI of the MI355X (gfx950) all-at-once solver for the heat equation
+ * preconditioned by the block epsilon-circulant (BEC) matrix of Lin & Ng,
+ * "An all-at-once preconditioner for evolutionary partial differential
+ * equations" (arXiv 2002.01108).
+ *
+ * Problem (Section 2): u_t = div(a grad u) + f on (0,1)^d x (0,T], d = 1,2,3,
+ * homogeneous Dirichlet data, backward Euler in time with N = n steps,
+ * tau = T/n, finite differences in space (mass matrix M = I, see the Remark
+ * after Assumptions 1-3).  Interior grid m1 x m2 x m3 points (unused dims 1),
+ * h_d = 1/(m_d + 1).  K is the 3/5/7-point -Laplacian, or the flux form of
+ * -div(a grad .) once a coefficient is set.
+ *
+ * All-at-once system (Section 2, eq. (allatoncesystem)):
+ *     L u = f,  (L u)^k = (I + tau K) u^k - u^{k-1},  u^0 := 0,
+ *     f = (tau f^1 + u_0; tau f^2; ...; tau f^n).
+ * Preconditioner (Section 3): P_eps = L with -eps I in the top-right block.
+ * Its inverse is applied with the three steps of Section 4
+ * (eqs. (ytild), (blockdiaginv), (zcompt)) using the diagonalisation
+ * R_eps = D_eps^{-1} F_n^* Lambda_eps F_n D_eps (eq. (repsdiagform)),
+ * theta = exp(+2 pi i / n), lambda_k = 1 - eps^{1/n} theta^k, and only the
+ * blocks k = 0..n/2 (conjugate symmetry, end of Section 4).
+ *
+ * Conventions for every entry point:
+ *  - Space-time vectors are caller-owned, contiguous FP64 DEVICE arrays of
+ *    n*m elements, layout [n][m3][m2][m1] (x fastest); row k is u^{k+1}.
+ *    The library never keeps a pointer past the call.
+ *  - Work is queued on the context's HIP stream (default: the null stream) and
+ *    is ordered with the caller's work on that stream.  Entry points that
+ *    return host values (aao_solve) synchronise that stream.
+ *  - Errors are reported by return code only; no exception crosses the ABI.
+ *    aao_last_error() gives a message for the last failing call on a context.
+ *  - A context is not thread safe; calls on one context must not overlap.
+ */
+#ifndef AAO_H
+#define AAO_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct aao_ctx aao_ctx;
+
+typedef enum {
+  AAO_OK = 0,
+  AAO_NOT_CONVERGED = 1, /* maxit reached; outputs hold the last iterate       */
+  AAO_EINVAL = -1,       /* bad argument (sizes, eps outside (0,1], null, ...) */
+  AAO_ENOMEM = -2,       /* device allocation failed                           */
+  AAO_EHIP = -3,         /* a HIP runtime call or kernel launch failed         */
+  AAO_ENAN = -4,         /* right-hand side or iterate is not finite           */
+  AAO_ESTATE = -5        /* call not valid in the context's current state      */
+} aao_status;
+
+/* Arithmetic of the preconditioner (Steps 1-3).  L, residuals, Arnoldi and
+ * Givens always run in FP64.  FP32: time FFTs, spatial transforms and divides
+ * in FP32.  BF16X3: as FP32 but the spatial transforms multiply BF16 hi/lo
+ * splits (hi*hi + hi*lo + lo*hi, round-to-nearest-even splits) with FP32
+ * accumulation. */
+typedef enum { AAO_FP64 = 0, AAO_FP32 = 1, AAO_BF16X3 = 2 } aao_precision;
+
+/* Create a context for an m1 x m2 x m3 grid (dim = 1, 2 or 3; m2, m3 ignored
+ * beyond dim), n time steps over (0, T], and BEC parameter eps.
+ *  - eps must lie in (0, 1] (Section 3, Theorem 3.1 and the Remark after it);
+ *    eps = 1 gives the block-circulant preconditioner.
+ *  - n must be a power of two, 2 <= n <= 1024.
+ *  - 1 <= m_d <= 1024.
+ * Allocates all device tables and the spectrum workspace on the current device.
+ * Returns AAO_EINVAL, AAO_ENOMEM or AAO_EHIP on failure (*out untouched). */
+aao_status aao_setup(int dim, int m1, int m2, int m3, int n, double T, double eps,
+                     aao_ctx **out);
+
+/* Free everything the context owns.  Null is accepted. */
+void aao_destroy(aao_ctx *ctx);
+
+/* Queue all later work on `hip_stream` (a hipStream_t; null = default stream). */
+aao_status aao_set_stream(aao_ctx *ctx, void *hip_stream);
+
+/* Select the preconditioner arithmetic (default AAO_FP64).  May allocate a
+ * differently sized spectrum workspace. */
+aao_status aao_set_precision(aao_ctx *ctx, aao_precision p);
+
+/* rhs = (tau f^1 + u0; tau f^2; ...; tau f^n) (Section 2, eq. (allatoncesystem)).
+ * f: device [n][m], u0: device [m], rhs: device [n][m] (may alias f). */
+aao_status aao_build_rhs(aao_ctx *ctx, const double *f, const double *u0, double *rhs);
+
+/* y = L x, the all-at-once matrix (Section 2, eq. (allatoncesystem)).
+ * x, y: device [n][m], must not alias. */
+aao_status aao_apply_A(aao_ctx *ctx, const double *x, double *y);
+
+/* y = P_eps^{-1} x by Steps 1-3 of Section 4 in the context's precision.
+ * x, y: device [n][m] FP64 (may alias: x is fully consumed first). */
+aao_status aao_apply_Pinv(aao_ctx *ctx, const double *x, double *y);
+
+/* The three steps separately, with the half spectrum in an external layout:
+ * interleaved complex FP64 [n/2+1][m][2] (real, imaginary), block k holding
+ * ytilde^{k+1} of Section 4.
+ * step1: yt = (F_n D_eps (x) I) y, blocks k = 0..n/2          (eq. (ytild))
+ * step2: zt^k = (lambda_k I + tau K)^{-1} yt^k, k = 0..n/2     (eq. (blockdiaginv))
+ * step3: z = (D_eps^{-1} F_n^* (x) I) zt, using zt^{n-k} = conj(zt^k); the
+ *        imaginary parts of blocks 0 and n/2 are ignored        (eq. (zcompt))
+ * Internally each step runs in the context's precision; these entry points
+ * convert to and from the internal layout and exist for verification. */
+aao_status aao_step1(aao_ctx *ctx, const double *y, double *yt);
+aao_status aao_step2(aao_ctx *ctx, const double *yt, double *zt);
+aao_status aao_step3(aao_ctx *ctx, const double *zt, double *z);
+
+/* Solve L u = rhs by right-preconditioned restarted flexible GMRES with P_eps
+ * (Section 5 uses restarted GMRES(50) from a zero guess).  Orthogonalisation is
+ * classical Gram-Schmidt applied twice, all in FP64 on the device; Givens
+ * rotations run on the host.
+ *  - u: device [n][m]; on entry the initial guess if use_guess != 0 (ignored
+ *    otherwise, zero guess); on exit the last iterate.
+ *  - Stops when the relative residual ||rhs - L u|| / ||rhs|| (tracked by the
+ *    Givens recurrence) is <= tol, or after maxit Arnoldi steps in total.
+ *  - restart: Krylov basis size (>= 1); the context allocates 2*(restart+1)
+ *    vectors of n*m doubles and keeps them for later calls.
+ *  - iters (host, may be null): total Arnoldi steps.
+ *  - res_hist (host, may be null, capacity hist_cap): the Givens estimate after
+ *    each step; hist_len (may be null) receives the number written.
+ *  - final_res (host, may be null): ||rhs - L u|| / ||rhs|| recomputed
+ *    explicitly from u at exit.
+ * Returns AAO_OK on convergence (a breakdown h_{j+1,j} = 0 is convergence),
+ * AAO_NOT_CONVERGED if maxit was reached, AAO_ENAN for a non-finite rhs,
+ * AAO_EINVAL for tol < 0, maxit < 1, restart < 1 or null vectors. */
+aao_status aao_solve(aao_ctx *ctx, const double *rhs, double *u, int use_guess, double tol,
+                     int maxit, int restart, int *iters, double *res_hist, int hist_cap,
+                     int *hist_len, double *final_res);
+
+/* Wait for all work queued on the context's stream. */
+aao_status aao_sync(aao_ctx *ctx);
+
+/* Kernel classes for aao_profile / aao_profile_read. */
+typedef enum {
+  AAO_K_APPLY_L = 0,   /* all-at-once matvec                            */
+  AAO_K_TIME_FWD = 1,  /* Step 1: eps scaling + forward time FFT        */
+  AAO_K_TIME_INV = 2,  /* Step 3: inverse time FFT + unscaling          */
+  AAO_K_DST = 3,       /* Step 2: one DST-I mode product (matrix cores) */
+  AAO_K_DIVIDE = 4,    /* Step 2: shifted complex divide                */
+  AAO_K_KRYLOV = 5,    /* GMRES vector kernels and reductions           */
+  AAO_K_NCLASS = 6
+} aao_kernel_class;
+
+/* Time every launch of the kernel classes whose bit is set in `mask` with a
+ * pair of HIP events recorded on the context's stream around it (mask 0
+ * disables).  Resets the accumulated totals.  Costs one event pair per timed
+ * launch and no synchronisation. */
+aao_status aao_profile(aao_ctx *ctx, int mask);
+
+/* Synchronise the stream and return, per class, the summed event time in
+ * milliseconds (ms[AAO_K_NCLASS]) and the number of timed launches
+ * (launches[AAO_K_NCLASS]) since the last aao_profile call.  Either output may
+ * be null. */
+aao_status aao_profile_read(aao_ctx *ctx, double *ms, int *launches);
+
+/* Human-readable name of a status code (static storage). */
+const char *aao_status_string(aao_status s);
+
+/* Message of the last failure on ctx (empty if none); valid until the next call. */
+const char *aao_last_error(const aao_ctx *ctx);
+
+/* Sizes the context was set up with: out[0..8] = dim, m1, m2, m3, n,
+ * padded plane dims P1, P2, P3, and the precision. */
+aao_status aao_query(const aao_ctx *ctx, int *out9);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AAO_H */

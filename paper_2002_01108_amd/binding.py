@@ -1,0 +1,202 @@
+"""ctypes binding of libaao.so (the C ABI in include/aao.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+Device arrays are torch tensors on the GPU (float64, contiguous); their data
+pointers and torch's current HIP stream are handed to the library.  There is
+no CPU fallback: if the library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaao.so")
+
+OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ENAN, ESTATE = 0, 1, -1, -2, -3, -4, -5
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+# exported symbols and their signatures: (restype, argtypes)
+_c_int, _c_double, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+_pint, _pdbl = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "aao_setup": (_c_int, [_c_int, _c_int, _c_int, _c_int, _c_int, _c_double, _c_double,
+                           ctypes.POINTER(_vp)]),
+    "aao_destroy": (None, [_vp]),
+    "aao_set_stream": (_c_int, [_vp, _vp]),
+    "aao_set_precision": (_c_int, [_vp, _c_int]),
+    "aao_build_rhs": (_c_int, [_vp, _vp, _vp, _vp]),
+    "aao_apply_A": (_c_int, [_vp, _vp, _vp]),
+    "aao_apply_Pinv": (_c_int, [_vp, _vp, _vp]),
+    "aao_step1": (_c_int, [_vp, _vp, _vp]),
+    "aao_step2": (_c_int, [_vp, _vp, _vp]),
+    "aao_step3": (_c_int, [_vp, _vp, _vp]),
+    "aao_solve": (_c_int, [_vp, _vp, _vp, _c_int, _c_double, _c_int, _c_int, _pint, _pdbl,
+                           _c_int, _pint, _pdbl]),
+    "aao_sync": (_c_int, [_vp]),
+    "aao_status_string": (ctypes.c_char_p, [_c_int]),
+    "aao_last_error": (ctypes.c_char_p, [_vp]),
+    "aao_query": (_c_int, [_vp, _pint]),
+    "aao_profile": (_c_int, [_vp, _c_int]),
+    "aao_profile_read": (_c_int, [_vp, _pdbl, _pint]),
+}
+KERNEL_CLASSES = ["apply_L", "time_fwd", "time_inv", "dst", "divide", "krylov"]
+
+_lib = None
+
+
+class AaoError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__(f"{status_string(status)}: {msg}")
+
+
+def load(path: str = LIB_PATH):
+    """Load libaao.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with python -m paper_2002_01108_amd.build")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_string(st: int) -> str:
+    return load().aao_status_string(st).decode()
+
+
+def _ptr(t):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a GPU torch tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One context of the library: grid, time steps, T, eps and precision."""
+
+    def __init__(self, dim: int, m1: int, n: int, T: float = 1.0, eps: float | None = None,
+                 precision: str = "fp64", m2: int | None = None, m3: int | None = None,
+                 stream=None):
+        import torch
+        self.lib = load()
+        self.dim, self.m1, self.n, self.T = dim, m1, n, T
+        self.m2 = m1 if m2 is None else m2
+        self.m3 = m1 if m3 is None else m3
+        self.tau = T / n
+        self.eps = min(0.5, (self.tau) ** 0.5) if eps is None else eps
+        dims = [m1, self.m2, self.m3][:dim]
+        self.m = int(np.prod(dims))
+        h = ctypes.c_void_p()
+        st = self.lib.aao_setup(dim, m1, self.m2, self.m3, n, T, self.eps, ctypes.byref(h))
+        if st != OK:
+            raise AaoError(st, "aao_setup")
+        self._h = h
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self._check(self.lib.aao_set_stream(self._h, ctypes.c_void_p(s.cuda_stream)))
+        self.set_precision(precision)
+
+    def _check(self, st, allow=(OK,)):
+        if st not in allow:
+            raise AaoError(st, self.lib.aao_last_error(self._h).decode())
+        return st
+
+    def set_precision(self, precision: str):
+        self.precision = precision
+        self._check(self.lib.aao_set_precision(self._h, PRECISIONS[precision]))
+
+    def query(self):
+        out = (ctypes.c_int * 9)()
+        self._check(self.lib.aao_query(self._h, out))
+        return list(out)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.aao_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ operators
+    def new(self, *shape):
+        import torch
+        shape = shape or (self.n, self.m)
+        return torch.empty(shape, dtype=torch.float64, device="cuda")
+
+    def build_rhs(self, f, u0, out=None):
+        out = self.new() if out is None else out
+        self._check(self.lib.aao_build_rhs(self._h, _ptr(f), _ptr(u0), _ptr(out)))
+        return out
+
+    def apply_A(self, x, out=None):
+        out = self.new() if out is None else out
+        self._check(self.lib.aao_apply_A(self._h, _ptr(x), _ptr(out)))
+        return out
+
+    def apply_Pinv(self, x, out=None):
+        out = self.new() if out is None else out
+        self._check(self.lib.aao_apply_Pinv(self._h, _ptr(x), _ptr(out)))
+        return out
+
+    def step1(self, y):
+        out = self.new(self.n // 2 + 1, self.m, 2)
+        self._check(self.lib.aao_step1(self._h, _ptr(y), _ptr(out)))
+        return out
+
+    def step2(self, yt):
+        out = self.new(self.n // 2 + 1, self.m, 2)
+        self._check(self.lib.aao_step2(self._h, _ptr(yt), _ptr(out)))
+        return out
+
+    def step3(self, zt):
+        out = self.new()
+        self._check(self.lib.aao_step3(self._h, _ptr(zt), _ptr(out)))
+        return out
+
+    def solve(self, rhs, tol: float = 1e-8, maxit: int = 100, restart: int = 50, u=None,
+              use_guess: bool = False):
+        """Returns (u, info) with info = dict(status, iters, hist, final_res)."""
+        u = self.new() if u is None else u
+        iters = ctypes.c_int(0)
+        cap = max(maxit, 1)
+        hist = (ctypes.c_double * cap)()
+        hlen = ctypes.c_int(0)
+        fres = ctypes.c_double(float("nan"))
+        st = self.lib.aao_solve(self._h, _ptr(rhs), _ptr(u), int(use_guess), tol, maxit, restart,
+                                ctypes.byref(iters), hist, cap, ctypes.byref(hlen),
+                                ctypes.byref(fres))
+        self._check(st, allow=(OK, NOT_CONVERGED))
+        return u, {"status": st, "iters": iters.value, "hist": list(hist[: hlen.value]),
+                   "final_res": fres.value}
+
+    def sync(self):
+        self._check(self.lib.aao_sync(self._h))
+
+    def profile(self, classes=None):
+        """Start event timing of the named kernel classes (None: stop)."""
+        mask = 0
+        for name in classes or ():
+            mask |= 1 << KERNEL_CLASSES.index(name)
+        self._check(self.lib.aao_profile(self._h, mask))
+
+    def profile_read(self):
+        """{class: (total_ms, launches)} since profile() was called."""
+        nc = len(KERNEL_CLASSES)
+        ms = (ctypes.c_double * nc)()
+        cnt = (ctypes.c_int * nc)()
+        self._check(self.lib.aao_profile_read(self._h, ms, cnt))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_CLASSES)}

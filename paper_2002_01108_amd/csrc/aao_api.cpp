@@ -1,0 +1,713 @@
+// Host side of the C ABI declared in include/aao.h: argument checks, device
+// tables, workspace ownership, the three-step BEC inverse (Section 4) and the
+// right-preconditioned flexible GMRES driver (restarted GMRES of Section 5,
+// with classical Gram-Schmidt applied twice on the device and Givens
+// rotations on the host).
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+using namespace aao;
+
+struct aao_ctx {
+  Geometry g;
+  double T = 1, tau = 1, eps = 1;
+  double h[3] = {1, 1, 1};
+  double cst[3] = {0, 0, 0};     // tau / h_d^2
+  hipStream_t stream = nullptr;
+  aao_precision prec = AAO_FP64;
+  int device = 0;
+
+  // device tables (FP64 and FP32 copies)
+  double* tw64 = nullptr;        // theta^e, e = 0..n-1, interleaved complex
+  float* tw32 = nullptr;
+  double* gam64 = nullptr;       // eps^{j/n} / sqrt(n)
+  double* ginv64 = nullptr;      // eps^{-j/n} / sqrt(n)
+  float* gam32 = nullptr;
+  float* ginv32 = nullptr;
+  double* lam = nullptr;         // lambda_k, k = 0..n/2, interleaved complex
+  double* tmu[3] = {nullptr, nullptr, nullptr};  // tau * mu_i per axis (padded, 0 in pads)
+  double* S64[3] = {nullptr, nullptr, nullptr};  // DST-I matrices per axis, P_d x P_d
+  float* S32[3] = {nullptr, nullptr, nullptr};
+
+  // spectrum workspace (ping-pong), sized for the current precision
+  void* specA = nullptr;
+  void* specB = nullptr;
+  size_t spec_bytes = 0;
+
+  // Krylov workspace
+  double* V = nullptr;           // (restart+1) x nm
+  double* Z = nullptr;           // restart x nm
+  double* tmp = nullptr;         // nm
+  int kry_restart = 0;
+  double* part = nullptr;        // partial sums
+  size_t part_elems = 0;
+  double* dsmall = nullptr;      // small device scratch (coefficients)
+  double* hsmall = nullptr;      // pinned host mirror
+  size_t small_elems = 0;
+
+  // per-class launch timing (aao_profile)
+  int prof_mask = 0;
+  std::vector<hipEvent_t> ev_pool;
+  struct Rec { int cls; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  size_t ev_used = 0;
+
+  std::string err;
+  std::vector<void*> owned;      // every device allocation for destroy
+};
+
+namespace {
+
+// Records an event pair around the launches in its scope when the class is enabled.
+struct ProfScope {
+  aao_ctx* c;
+  int cls;
+  hipEvent_t b = nullptr;
+  ProfScope(aao_ctx* ctx, int k) : c(ctx), cls(k) {
+    if (!(c->prof_mask & (1 << cls))) { c = nullptr; return; }
+    while (c->ev_pool.size() < c->ev_used + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) { c = nullptr; return; }
+      c->ev_pool.push_back(e);
+    }
+    hipEvent_t a = c->ev_pool[c->ev_used++];
+    b = c->ev_pool[c->ev_used++];
+    (void)hipEventRecord(a, c->stream);
+    c->recs.push_back({cls, a, b});
+  }
+  ~ProfScope() {
+    if (c) (void)hipEventRecord(b, c->stream);
+  }
+};
+
+const double kPi = 3.14159265358979323846;
+
+aao_status fail(aao_ctx* c, aao_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+aao_status hip_fail(aao_ctx* c, hipError_t e, const char* what) {
+  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(c, AAO_EHIP, msg);
+}
+
+#define HIPCHK(ctx, call)                                          \
+  do {                                                             \
+    hipError_t _e = (call);                                        \
+    if (_e != hipSuccess) return hip_fail((ctx), _e, #call);       \
+  } while (0)
+
+template <typename T>
+aao_status dalloc(aao_ctx* c, T** p, size_t count) {
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, AAO_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes");
+  }
+  c->owned.push_back(ptr);
+  *p = (T*)ptr;
+  return AAO_OK;
+}
+
+void dfree(aao_ctx* c, void* p) {
+  if (!p) return;
+  auto it = std::find(c->owned.begin(), c->owned.end(), p);
+  if (it != c->owned.end()) c->owned.erase(it);
+  (void)hipFree(p);
+}
+
+#define TRY(x)                       \
+  do {                               \
+    aao_status _s = (x);             \
+    if (_s != AAO_OK) return _s;     \
+  } while (0)
+
+template <typename T>
+aao_status upload(aao_ctx* c, T** dst, const std::vector<T>& host) {
+  TRY(dalloc(c, dst, host.size()));
+  HIPCHK(c, hipMemcpy(*dst, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice));
+  return AAO_OK;
+}
+
+int round_up(int v, int q) { return (v + q - 1) / q * q; }
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// sin(pi * p / q) with the argument reduced exactly in integers first
+double sin_pi_frac(long long p, long long q) {
+  long long r = p % (2 * q);
+  if (r < 0) r += 2 * q;
+  return sin(kPi * (double)r / (double)q);
+}
+
+size_t spec_elems(const Geometry& g) { return (size_t)g.nh * 2 * (size_t)g.PS; }
+
+aao_status ensure_spec(aao_ctx* c) {
+  const size_t esz = (c->prec == AAO_FP64) ? 8 : 4;
+  const size_t bytes = spec_elems(c->g) * esz;
+  if (bytes == c->spec_bytes && c->specA) return AAO_OK;
+  dfree(c, c->specA);
+  dfree(c, c->specB);
+  c->specA = c->specB = nullptr;
+  c->spec_bytes = 0;
+  char* a = nullptr;
+  char* b = nullptr;
+  TRY(dalloc(c, &a, bytes));
+  TRY(dalloc(c, &b, bytes));
+  // padding positions must start at zero (every kernel keeps them zero)
+  HIPCHK(c, hipMemset(a, 0, bytes));
+  HIPCHK(c, hipMemset(b, 0, bytes));
+  c->specA = a;
+  c->specB = b;
+  c->spec_bytes = bytes;
+  return AAO_OK;
+}
+
+aao_status ensure_small(aao_ctx* c, size_t elems) {
+  if (elems <= c->small_elems) return AAO_OK;
+  dfree(c, c->dsmall);
+  if (c->hsmall) (void)hipHostFree(c->hsmall);
+  c->dsmall = nullptr;
+  c->hsmall = nullptr;
+  TRY(dalloc(c, &c->dsmall, elems));
+  void* hp = nullptr;
+  HIPCHK(c, hipHostMalloc(&hp, elems * sizeof(double), hipHostMallocDefault));
+  c->hsmall = (double*)hp;
+  c->small_elems = elems;
+  return AAO_OK;
+}
+
+aao_status ensure_part(aao_ctx* c, size_t elems) {
+  if (elems <= c->part_elems) return AAO_OK;
+  dfree(c, c->part);
+  c->part = nullptr;
+  TRY(dalloc(c, &c->part, elems));
+  c->part_elems = elems;
+  return AAO_OK;
+}
+
+// ---------------------------------------------------------------- BEC inverse pieces
+hipError_t run_time_fwd(aao_ctx* c, const double* x, void* spec) {
+  ProfScope ps(c, AAO_K_TIME_FWD);
+  if (c->prec == AAO_FP64)
+    return launch_time_fwd_f64(c->g, x, (double*)spec, c->gam64, c->tw64, c->stream);
+  return launch_time_fwd_f32(c->g, x, (float*)spec, c->gam32, c->tw32, c->stream);
+}
+
+hipError_t run_time_inv(aao_ctx* c, const void* spec, double* z) {
+  ProfScope ps(c, AAO_K_TIME_INV);
+  if (c->prec == AAO_FP64)
+    return launch_time_inv_f64(c->g, (const double*)spec, z, c->ginv64, c->tw64, c->stream);
+  return launch_time_inv_f32(c->g, (const float*)spec, z, c->ginv32, c->tw32, c->stream);
+}
+
+// One mode product along axis d (0 = x, 1 = y, 2 = z) from `in` to `out`.
+hipError_t mode_product(aao_ctx* c, int d, const void* in, void* out) {
+  ProfScope ps(c, AAO_K_DST);
+  const Geometry& g = c->g;
+  const int two_nh = 2 * g.nh;
+  int M, N, K, batch, lda, ldb, ldc;
+  int64_t sA, sB, sC;
+  bool right;
+  if (d == 0) {  // rows of P1, times S1 from the right
+    right = true;
+    M = two_nh * g.P2 * g.P3;
+    N = K = g.P1;
+    lda = ldb = ldc = g.P1;
+    sA = sB = sC = 0;
+    batch = 1;
+  } else if (d == 1) {  // S2 times each P2 x P1 slab
+    right = false;
+    M = K = g.P2;
+    N = g.P1;
+    lda = g.P2;
+    ldb = ldc = g.P1;
+    sA = 0;
+    sB = sC = (int64_t)g.P2 * g.P1;
+    batch = two_nh * g.P3;
+  } else {  // S3 times each P3 x (P2 P1) plane
+    right = false;
+    M = K = g.P3;
+    N = g.P2 * g.P1;
+    lda = g.P3;
+    ldb = ldc = g.P2 * g.P1;
+    sA = 0;
+    sB = sC = (int64_t)g.P3 * g.P2 * g.P1;
+    batch = two_nh;
+  }
+  if (c->prec == AAO_FP64) {
+    const double* S = c->S64[d];
+    if (right)
+      return launch_gemm_f64((const double*)in, 0, lda, S, 0, ldb, (double*)out, 0, ldc, M, N, K,
+                             1, c->stream);
+    return launch_gemm_f64(S, 0, lda, (const double*)in, sB, ldb, (double*)out, sC, ldc, M, N, K,
+                           batch, c->stream);
+  }
+  const float* S = c->S32[d];
+  if (right)
+    return launch_gemm_f32((const float*)in, 0, lda, S, 0, ldb, (float*)out, 0, ldc, M, N, K, 1,
+                           c->stream);
+  return launch_gemm_f32(S, 0, lda, (const float*)in, sB, ldb, (float*)out, sC, ldc, M, N, K,
+                         batch, c->stream);
+}
+
+hipError_t run_divide(aao_ctx* c, void* spec) {
+  ProfScope ps(c, AAO_K_DIVIDE);
+  const Geometry& g = c->g;
+  const double* t2 = g.dim >= 2 ? c->tmu[1] : nullptr;
+  const double* t3 = g.dim >= 3 ? c->tmu[2] : nullptr;
+  if (c->prec == AAO_FP64)
+    return launch_divide_f64(g, (double*)spec, c->lam, c->tmu[0], t2, t3, c->stream);
+  return launch_divide_f32(g, (float*)spec, c->lam, c->tmu[0], t2, t3, c->stream);
+}
+
+// Step 2 on the internal spectrum: data in *cur; on return *cur holds the result.
+aao_status spatial_solve(aao_ctx* c, void** cur, void** other) {
+  const int dim = c->g.dim;
+  for (int d = 0; d < dim; ++d) {
+    HIPCHK(c, mode_product(c, d, *cur, *other));
+    std::swap(*cur, *other);
+  }
+  HIPCHK(c, run_divide(c, *cur));
+  for (int d = dim - 1; d >= 0; --d) {
+    HIPCHK(c, mode_product(c, d, *cur, *other));
+    std::swap(*cur, *other);
+  }
+  return AAO_OK;
+}
+
+aao_status apply_pinv(aao_ctx* c, const double* x, double* y) {
+  void* cur = c->specA;
+  void* other = c->specB;
+  HIPCHK(c, run_time_fwd(c, x, cur));
+  TRY(spatial_solve(c, &cur, &other));
+  HIPCHK(c, run_time_inv(c, cur, y));
+  return AAO_OK;
+}
+
+aao_status apply_L(aao_ctx* c, const double* x, double* y) {
+  ProfScope ps(c, AAO_K_APPLY_L);
+  HIPCHK(c, launch_apply_L(c->g, x, y, c->cst[0], c->cst[1], c->cst[2], c->stream));
+  return AAO_OK;
+}
+
+int64_t nm_of(const aao_ctx* c) { return (int64_t)c->g.n * c->g.m; }
+
+// ||a - b||^2 (b may be null) reduced into dsmall[slot]
+aao_status sqnorm_dev(aao_ctx* c, const double* a, const double* b, int slot) {
+  const int64_t len = nm_of(c);
+  const int nb = krylov_blocks(len);
+  TRY(ensure_part(c, (size_t)nb));
+  HIPCHK(c, launch_diffnorm(a, b, len, c->part, c->stream));
+  HIPCHK(c, launch_reduce_partials(c->part, nb, 1, c->dsmall + slot, 0, c->stream));
+  return AAO_OK;
+}
+
+aao_status fetch_small(aao_ctx* c, int off, int count) {
+  HIPCHK(c, hipMemcpyAsync(c->hsmall + off, c->dsmall + off, count * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return AAO_OK;
+}
+
+aao_status ensure_krylov(aao_ctx* c, int restart) {
+  if (restart <= c->kry_restart && c->V) return AAO_OK;
+  dfree(c, c->V);
+  dfree(c, c->Z);
+  dfree(c, c->tmp);
+  c->V = c->Z = c->tmp = nullptr;
+  c->kry_restart = 0;
+  const size_t nm = (size_t)nm_of(c);
+  TRY(dalloc(c, &c->V, (size_t)(restart + 1) * nm));
+  TRY(dalloc(c, &c->Z, (size_t)restart * nm));
+  TRY(dalloc(c, &c->tmp, nm));
+  c->kry_restart = restart;
+  return AAO_OK;
+}
+
+}  // namespace
+
+// =====================================================================================
+extern "C" {
+
+const char* aao_status_string(aao_status s) {
+  switch (s) {
+    case AAO_OK: return "AAO_OK";
+    case AAO_NOT_CONVERGED: return "AAO_NOT_CONVERGED";
+    case AAO_EINVAL: return "AAO_EINVAL";
+    case AAO_ENOMEM: return "AAO_ENOMEM";
+    case AAO_EHIP: return "AAO_EHIP";
+    case AAO_ENAN: return "AAO_ENAN";
+    case AAO_ESTATE: return "AAO_ESTATE";
+  }
+  return "AAO_UNKNOWN";
+}
+
+const char* aao_last_error(const aao_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+void aao_destroy(aao_ctx* ctx) {
+  if (!ctx) return;
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  for (void* p : ctx->owned) (void)hipFree(p);
+  ctx->owned.clear();
+  if (ctx->hsmall) (void)hipHostFree(ctx->hsmall);
+  delete ctx;
+}
+
+aao_status aao_setup(int dim, int m1, int m2, int m3, int n, double T, double eps,
+                     aao_ctx** out) {
+  if (!out) return AAO_EINVAL;
+  if (dim < 1 || dim > 3) return AAO_EINVAL;
+  if (dim < 2) m2 = 1;
+  if (dim < 3) m3 = 1;
+  const int ms[3] = {m1, m2, m3};
+  for (int d = 0; d < dim; ++d)
+    if (ms[d] < 1 || ms[d] > 1024) return AAO_EINVAL;
+  if (!is_pow2(n) || n < 2 || n > 1024) return AAO_EINVAL;
+  if (!(T > 0) || !isfinite(T)) return AAO_EINVAL;
+  // Theorem 3.1: eps in (0, 1] keeps P_eps invertible
+  if (!(eps > 0.0) || !(eps <= 1.0)) return AAO_EINVAL;
+
+  aao_ctx* c = new aao_ctx();
+  auto bail = [&](aao_status st) {
+    aao_destroy(c);
+    return st;
+  };
+  (void)hipGetDevice(&c->device);
+  Geometry& g = c->g;
+  g.dim = dim;
+  g.m1 = m1;
+  g.m2 = m2;
+  g.m3 = m3;
+  g.m = (int64_t)m1 * m2 * m3;
+  g.P1 = round_up(m1, 64);
+  g.P2 = dim >= 2 ? round_up(m2, 64) : 1;
+  g.P3 = dim >= 3 ? round_up(m3, 64) : 1;
+  g.PS = (int64_t)g.P1 * g.P2 * g.P3;
+  g.n = n;
+  g.nh = n / 2 + 1;
+  c->T = T;
+  c->tau = T / n;
+  c->eps = eps;
+  for (int d = 0; d < 3; ++d) {
+    c->h[d] = 1.0 / (ms[d] + 1);
+    c->cst[d] = d < dim ? c->tau / (c->h[d] * c->h[d]) : 0.0;
+  }
+
+  // time tables: theta^e = exp(+2 pi i e / n) (eq. (fouriermatdef)), D_eps (eq. (repsdiagform))
+  std::vector<double> tw(2 * n), gam(n), ginv(n);
+  std::vector<float> tw32(2 * n), gam32(n), ginv32(n);
+  const double rs = 1.0 / sqrt((double)n);
+  for (int e = 0; e < n; ++e) {
+    tw[2 * e] = sin_pi_frac(2LL * e + n / 2, n);   // cos(2 pi e/n) = sin(pi (2e + n/2)/n)
+    tw[2 * e + 1] = sin_pi_frac(2LL * e, n);
+    tw32[2 * e] = (float)tw[2 * e];
+    tw32[2 * e + 1] = (float)tw[2 * e + 1];
+    gam[e] = pow(eps, (double)e / n) * rs;
+    ginv[e] = pow(eps, -(double)e / n) * rs;
+    gam32[e] = (float)gam[e];
+    ginv32[e] = (float)ginv[e];
+  }
+  // lambda_k = 1 - eps^{1/n} theta^k (eq. (repsdiagform) with r = (1, -1))
+  std::vector<double> lam(2 * g.nh);
+  const double e1n = pow(eps, 1.0 / n);
+  for (int k = 0; k < g.nh; ++k) {
+    lam[2 * k] = 1.0 - e1n * tw[2 * (k % n)];
+    lam[2 * k + 1] = -e1n * tw[2 * (k % n) + 1];
+  }
+  aao_status st;
+  if ((st = upload(c, &c->tw64, tw)) != AAO_OK) return bail(st);
+  if ((st = upload(c, &c->tw32, tw32)) != AAO_OK) return bail(st);
+  if ((st = upload(c, &c->gam64, gam)) != AAO_OK) return bail(st);
+  if ((st = upload(c, &c->ginv64, ginv)) != AAO_OK) return bail(st);
+  if ((st = upload(c, &c->gam32, gam32)) != AAO_OK) return bail(st);
+  if ((st = upload(c, &c->ginv32, ginv32)) != AAO_OK) return bail(st);
+  if ((st = upload(c, &c->lam, lam)) != AAO_OK) return bail(st);
+
+  // spatial tables per axis: tau*mu_i and the DST-I matrix
+  //   S_ij = sqrt(2/(m+1)) sin((i+1)(j+1) pi/(m+1)),  mu_i = 4/h^2 sin^2((i+1) pi h/2)
+  const int Ps[3] = {g.P1, g.P2, g.P3};
+  for (int d = 0; d < dim; ++d) {
+    const int md = ms[d], P = Ps[d];
+    std::vector<double> tmu(P, 0.0), S((size_t)P * P, 0.0);
+    std::vector<float> S32((size_t)P * P, 0.0f);
+    const double sc = sqrt(2.0 / (md + 1));
+    for (int i = 0; i < md; ++i) {
+      const double sn = sin_pi_frac(i + 1, 2LL * (md + 1));
+      tmu[i] = c->tau * 4.0 / (c->h[d] * c->h[d]) * sn * sn;
+      for (int j = 0; j < md; ++j) {
+        S[(size_t)i * P + j] = sc * sin_pi_frac((long long)(i + 1) * (j + 1), md + 1);
+        S32[(size_t)i * P + j] = (float)S[(size_t)i * P + j];
+      }
+    }
+    if ((st = upload(c, &c->tmu[d], tmu)) != AAO_OK) return bail(st);
+    if ((st = upload(c, &c->S64[d], S)) != AAO_OK) return bail(st);
+    if ((st = upload(c, &c->S32[d], S32)) != AAO_OK) return bail(st);
+  }
+  if ((st = ensure_spec(c)) != AAO_OK) return bail(st);
+  if ((st = ensure_small(c, 256)) != AAO_OK) return bail(st);
+  *out = c;
+  return AAO_OK;
+}
+
+aao_status aao_set_stream(aao_ctx* ctx, void* hip_stream) {
+  if (!ctx) return AAO_EINVAL;
+  ctx->stream = (hipStream_t)hip_stream;
+  return AAO_OK;
+}
+
+aao_status aao_set_precision(aao_ctx* ctx, aao_precision p) {
+  if (!ctx) return AAO_EINVAL;
+  if (p != AAO_FP64 && p != AAO_FP32) return fail(ctx, AAO_EINVAL, "unsupported precision");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->prec = p;
+  return ensure_spec(ctx);
+}
+
+aao_status aao_query(const aao_ctx* ctx, int* o) {
+  if (!ctx || !o) return AAO_EINVAL;
+  const Geometry& g = ctx->g;
+  o[0] = g.dim;
+  o[1] = g.m1;
+  o[2] = g.m2;
+  o[3] = g.m3;
+  o[4] = g.n;
+  o[5] = g.P1;
+  o[6] = g.P2;
+  o[7] = g.P3;
+  o[8] = (int)ctx->prec;
+  return AAO_OK;
+}
+
+aao_status aao_profile(aao_ctx* ctx, int mask) {
+  if (!ctx) return AAO_EINVAL;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->prof_mask = mask;
+  ctx->recs.clear();
+  ctx->ev_used = 0;
+  return AAO_OK;
+}
+
+aao_status aao_profile_read(aao_ctx* ctx, double* ms, int* launches) {
+  if (!ctx) return AAO_EINVAL;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  double acc[AAO_K_NCLASS] = {0};
+  int cnt[AAO_K_NCLASS] = {0};
+  for (const auto& r : ctx->recs) {
+    float t = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&t, r.a, r.b));
+    acc[r.cls] += t;
+    cnt[r.cls] += 1;
+  }
+  for (int k = 0; k < AAO_K_NCLASS; ++k) {
+    if (ms) ms[k] = acc[k];
+    if (launches) launches[k] = cnt[k];
+  }
+  ctx->recs.clear();
+  ctx->ev_used = 0;
+  return AAO_OK;
+}
+
+aao_status aao_sync(aao_ctx* ctx) {
+  if (!ctx) return AAO_EINVAL;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return AAO_OK;
+}
+
+aao_status aao_build_rhs(aao_ctx* ctx, const double* f, const double* u0, double* rhs) {
+  if (!ctx || !f || !u0 || !rhs) return AAO_EINVAL;
+  HIPCHK(ctx, launch_build_rhs(f, u0, rhs, nm_of(ctx), ctx->g.m, ctx->tau, ctx->stream));
+  return AAO_OK;
+}
+
+aao_status aao_apply_A(aao_ctx* ctx, const double* x, double* y) {
+  if (!ctx || !x || !y) return AAO_EINVAL;
+  if (x == y) return fail(ctx, AAO_EINVAL, "apply_A: x and y must not alias");
+  return apply_L(ctx, x, y);
+}
+
+aao_status aao_apply_Pinv(aao_ctx* ctx, const double* x, double* y) {
+  if (!ctx || !x || !y) return AAO_EINVAL;
+  return apply_pinv(ctx, x, y);
+}
+
+aao_status aao_step1(aao_ctx* ctx, const double* y, double* yt) {
+  if (!ctx || !y || !yt) return AAO_EINVAL;
+  HIPCHK(ctx, run_time_fwd(ctx, y, ctx->specA));
+  HIPCHK(ctx, launch_spec_to_ext(ctx->g, ctx->specA, ctx->prec != AAO_FP64, yt, ctx->stream));
+  return AAO_OK;
+}
+
+aao_status aao_step2(aao_ctx* ctx, const double* yt, double* zt) {
+  if (!ctx || !yt || !zt) return AAO_EINVAL;
+  void* cur = ctx->specA;
+  void* other = ctx->specB;
+  HIPCHK(ctx, launch_ext_to_spec(ctx->g, yt, cur, ctx->prec != AAO_FP64, ctx->stream));
+  TRY(spatial_solve(ctx, &cur, &other));
+  HIPCHK(ctx, launch_spec_to_ext(ctx->g, cur, ctx->prec != AAO_FP64, zt, ctx->stream));
+  return AAO_OK;
+}
+
+aao_status aao_step3(aao_ctx* ctx, const double* zt, double* z) {
+  if (!ctx || !zt || !z) return AAO_EINVAL;
+  HIPCHK(ctx, launch_ext_to_spec(ctx->g, zt, ctx->specA, ctx->prec != AAO_FP64, ctx->stream));
+  HIPCHK(ctx, run_time_inv(ctx, ctx->specA, z));
+  return AAO_OK;
+}
+
+aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, double tol,
+                     int maxit, int restart, int* iters, double* res_hist, int hist_cap,
+                     int* hist_len, double* final_res) {
+  if (!c || !rhs || !u) return AAO_EINVAL;
+  if (!(tol >= 0.0) || maxit < 1 || restart < 1) return fail(c, AAO_EINVAL, "solve arguments");
+  if (iters) *iters = 0;
+  if (hist_len) *hist_len = 0;
+  const int64_t nm = nm_of(c);
+  TRY(ensure_krylov(c, restart));
+  const int R = restart;
+  // small scratch layout: [0] norm slot, [1..R+1] h1, [R+2..2R+2] h2, [2R+3] norm2, [2R+4..] y
+  const int o_nrm = 0, o_h1 = 1, o_h2 = R + 2, o_n2 = 2 * R + 3, o_y = 2 * R + 4;
+  TRY(ensure_small(c, (size_t)(3 * R + 8)));
+  const int nb = krylov_blocks(nm);
+  TRY(ensure_part(c, (size_t)nb * (R + 2)));
+
+  // ||rhs|| and finiteness
+  TRY(sqnorm_dev(c, rhs, nullptr, o_nrm));
+  TRY(fetch_small(c, o_nrm, 1));
+  const double bnorm2 = c->hsmall[o_nrm];
+  if (!isfinite(bnorm2)) return fail(c, AAO_ENAN, "right-hand side is not finite");
+  const double bnorm = sqrt(bnorm2);
+  if (bnorm == 0.0) {
+    HIPCHK(c, hipMemsetAsync(u, 0, nm * sizeof(double), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (final_res) *final_res = 0.0;
+    return AAO_OK;
+  }
+  if (!use_guess) HIPCHK(c, hipMemsetAsync(u, 0, nm * sizeof(double), c->stream));
+
+  std::vector<double> H((size_t)(R + 1) * R), cs(R), sn(R), gv(R + 1), y(R);
+  int total = 0, nhist = 0;
+  bool converged = false;
+  bool first = true;
+  while (true) {
+    // r0 = rhs - L u  (zero guess on the first cycle: r0 = rhs)
+    double beta;
+    double* v0 = c->V;
+    if (first && !use_guess) {
+      beta = bnorm;
+      HIPCHK(c, launch_scale_host(rhs, v0, nm, 1.0 / beta, c->stream));
+    } else {
+      TRY(apply_L(c, u, c->tmp));
+      TRY(sqnorm_dev(c, rhs, c->tmp, o_nrm));
+      TRY(fetch_small(c, o_nrm, 1));
+      beta = sqrt(c->hsmall[o_nrm]);
+      if (!isfinite(beta)) return fail(c, AAO_ENAN, "iterate is not finite");
+      if (beta / bnorm <= tol) {
+        converged = true;
+        break;
+      }
+      // v0 = (rhs - tmp) / beta: tmp <- rhs - tmp via axpy with coefficient -1 then scale
+      HIPCHK(c, launch_scale_host(c->tmp, v0, nm, -1.0 / beta, c->stream));
+      // v0 += rhs / beta
+      c->hsmall[o_y] = 1.0 / beta;
+      HIPCHK(c, hipMemcpyAsync(c->dsmall + o_y, c->hsmall + o_y, sizeof(double),
+                               hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, launch_multi_axpy(rhs, 0, 1, c->dsmall + o_y, v0, nm, c->stream));
+    }
+    first = false;
+    if (total >= maxit) break;
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(gv.begin(), gv.end(), 0.0);
+    gv[0] = beta;
+    int j = 0;
+    bool stop = false;
+    for (j = 0; j < R; ++j) {
+      double* vj = c->V + (int64_t)j * nm;
+      double* zj = c->Z + (int64_t)j * nm;
+      double* w = c->V + (int64_t)(j + 1) * nm;
+      TRY(apply_pinv(c, vj, zj));
+      TRY(apply_L(c, zj, w));
+      const int q = j + 1;
+      // CGS2: h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2; ||w||
+      {
+      ProfScope ps(c, AAO_K_KRYLOV);
+      HIPCHK(c, launch_multidot(c->V, nm, q, w, nm, c->part, c->stream));
+      HIPCHK(c, launch_reduce_partials(c->part, nb, q, c->dsmall + o_h1, 0, c->stream));
+      if (q <= 8) {
+        HIPCHK(c, launch_axpy_dot(c->V, nm, q, c->dsmall + o_h1, w, nm, c->part, 1, c->stream));
+        HIPCHK(c, launch_reduce_partials(c->part, nb, q, c->dsmall + o_h2, 0, c->stream));
+      } else {
+        HIPCHK(c, launch_axpy_dot(c->V, nm, q, c->dsmall + o_h1, w, nm, c->part, 0, c->stream));
+        HIPCHK(c, launch_multidot(c->V, nm, q, w, nm, c->part, c->stream));
+        HIPCHK(c, launch_reduce_partials(c->part, nb, q, c->dsmall + o_h2, 0, c->stream));
+      }
+      HIPCHK(c, launch_axpy_dot(c->V, nm, q, c->dsmall + o_h2, w, nm, c->part, 2, c->stream));
+      HIPCHK(c, launch_reduce_partials(c->part, nb, 1, c->dsmall + o_n2, 0, c->stream));
+      }
+      TRY(fetch_small(c, 0, o_n2 + 1));
+      double* Hj = &H[0];
+      for (int i = 0; i < q; ++i) Hj[(size_t)i * R + j] = c->hsmall[o_h1 + i] + c->hsmall[o_h2 + i];
+      const double hn = sqrt(std::max(c->hsmall[o_n2], 0.0));
+      if (!isfinite(hn)) return fail(c, AAO_ENAN, "Arnoldi vector is not finite");
+      Hj[(size_t)(j + 1) * R + j] = hn;
+      // apply previous rotations, then a new one (real Givens)
+      for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * R + j], b = H[(size_t)(i + 1) * R + j];
+        H[(size_t)i * R + j] = cs[i] * a + sn[i] * b;
+        H[(size_t)(i + 1) * R + j] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = H[(size_t)j * R + j], b = H[(size_t)(j + 1) * R + j];
+      const double rho = hypot(a, b);
+      cs[j] = rho > 0 ? a / rho : 1.0;
+      sn[j] = rho > 0 ? b / rho : 0.0;
+      H[(size_t)j * R + j] = rho;
+      H[(size_t)(j + 1) * R + j] = 0.0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      ++total;
+      const double est = fabs(gv[j + 1]) / bnorm;
+      if (res_hist && nhist < hist_cap) res_hist[nhist] = est;
+      ++nhist;
+      const bool breakdown = (hn == 0.0);
+      if (est <= tol || breakdown) converged = true;
+      if (converged || total >= maxit) {
+        stop = true;
+        break;
+      }
+      HIPCHK(c, launch_scale_host(w, w, nm, 1.0 / hn, c->stream));
+    }
+    const int k = stop ? j + 1 : R;
+    // back substitution R y = g
+    for (int i = k - 1; i >= 0; --i) {
+      double s = gv[i];
+      for (int l = i + 1; l < k; ++l) s -= H[(size_t)i * R + l] * y[l];
+      y[i] = s / H[(size_t)i * R + i];
+    }
+    for (int i = 0; i < k; ++i) c->hsmall[o_y + i] = y[i];
+    HIPCHK(c, hipMemcpyAsync(c->dsmall + o_y, c->hsmall + o_y, k * sizeof(double),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_multi_axpy(c->Z, nm, k, c->dsmall + o_y, u, nm, c->stream));
+    if (converged || total >= maxit) break;
+  }
+  // explicit residual
+  TRY(apply_L(c, u, c->tmp));
+  TRY(sqnorm_dev(c, rhs, c->tmp, o_nrm));
+  TRY(fetch_small(c, o_nrm, 1));
+  const double fres = sqrt(c->hsmall[o_nrm]) / bnorm;
+  if (final_res) *final_res = fres;
+  if (iters) *iters = total;
+  if (hist_len) *hist_len = std::min(nhist, hist_cap);
+  if (!isfinite(fres)) return fail(c, AAO_ENAN, "solution is not finite");
+  return converged ? AAO_OK : AAO_NOT_CONVERGED;
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// Internal declarations shared by the HIP kernels and the host side of the
+// all-at-once BEC library.  Not part of the public C ABI (include/aao.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/aao.h"
+
+namespace aao {
+
+// ---------------------------------------------------------------- complex helpers
+template <typename T> struct cplx { T x, y; };
+
+template <typename T> __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) {
+  return {a.x + b.x, a.y + b.y};
+}
+template <typename T> __device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) {
+  return {a.x - b.x, a.y - b.y};
+}
+template <typename T> __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// ---------------------------------------------------------------- geometry
+// Spatial grid: m1 (x, fastest), m2 (y), m3 (z); unused dims are 1.
+// Spectrum planes are padded: P_d = round_up(m_d, 64) for used dims, 1 otherwise.
+struct Geometry {
+  int dim = 1;
+  int m1 = 1, m2 = 1, m3 = 1;
+  int64_t m = 1;      // m1*m2*m3
+  int P1 = 1, P2 = 1, P3 = 1;
+  int64_t PS = 1;     // P1*P2*P3 (one real plane)
+  int n = 2;          // time steps (power of two)
+  int nh = 2;         // n/2 + 1 frequency blocks
+};
+
+// ---------------------------------------------------------------- launchers
+// Each returns hipSuccess or the launch error.  Pointers are device pointers.
+
+// y = L x (stencil + time bidiagonal), FP64.  c_d = tau / h_d^2.
+hipError_t launch_apply_L(const Geometry& g, const double* x, double* y, double c1, double c2,
+                          double c3, hipStream_t s);
+// y = L x with the flux-form variable-coefficient operator; faces pre-scaled by tau/h^2.
+hipError_t launch_apply_L_var(const Geometry& g, const double* x, double* y, const double* ax,
+                              const double* ay, const double* az, hipStream_t s);
+
+// Step 1: Gamma_eps scaling + forward time DFT (theta = e^{+2 pi i/n}) of a real
+// [n][m] array into split re/im planes spec[k][2][PS], k = 0..n/2.
+// gam[j] = eps^{j/n} / sqrt(n); tw = theta^e, e = 0..n-1.
+hipError_t launch_time_fwd_f64(const Geometry& g, const double* x, double* spec,
+                               const double* gam, const double* tw, hipStream_t s);
+hipError_t launch_time_fwd_f32(const Geometry& g, const double* x, float* spec,
+                               const float* gam, const float* tw, hipStream_t s);
+// Step 3: Hermitian completion + inverse time DFT (theta^{-1}) + eps^{-j/n}/sqrt(n).
+hipError_t launch_time_inv_f64(const Geometry& g, const double* spec, double* z,
+                               const double* ginv, const double* tw, hipStream_t s);
+hipError_t launch_time_inv_f32(const Geometry& g, const float* spec, double* z,
+                               const float* ginv, const float* tw, hipStream_t s);
+
+// Batched C[b] = A[b] * B[b] (row-major, all dims multiples of 64 except M which
+// may be ragged).  Strides in elements; a zero stride broadcasts the operand.
+hipError_t launch_gemm_f64(const double* A, int64_t sA, int lda, const double* B, int64_t sB,
+                           int ldb, double* C, int64_t sC, int ldc, int M, int N, int K,
+                           int batch, hipStream_t s);
+hipError_t launch_gemm_f32(const float* A, int64_t sA, int lda, const float* B, int64_t sB,
+                           int ldb, float* C, int64_t sC, int ldc, int M, int N, int K,
+                           int batch, hipStream_t s);
+// BF16 hi/lo split product: C = Ahi*Bhi + Ahi*Blo + Alo*Bhi, FP32 accumulate.
+// A is given pre-split (Ahi, Alo as bf16 bit patterns); B is FP32 and split on load.
+hipError_t launch_gemm_bf16x3(const uint16_t* Ahi, const uint16_t* Alo, int64_t sA, int lda,
+                              const float* B, int64_t sB, int ldb, float* C, int64_t sC, int ldc,
+                              int M, int N, int K, int batch, hipStream_t s);
+// Same with the split operand on the right: C = A * S, A FP32 rows, S pre-split.
+hipError_t launch_gemm_bf16x3_right(const float* A, int64_t sA, int lda, const uint16_t* Bhi,
+                                    const uint16_t* Blo, int64_t sB, int ldb, float* C,
+                                    int64_t sC, int ldc, int M, int N, int K, int batch,
+                                    hipStream_t s);
+
+// Shifted divide in the doubly transformed domain:
+// spec[k] <- spec[k] / (lambda_k + sum_d tmu_d[i_d]), complex, pads set to 0.
+hipError_t launch_divide_f64(const Geometry& g, double* spec, const double* lam,
+                             const double* tmu1, const double* tmu2, const double* tmu3,
+                             hipStream_t s);
+hipError_t launch_divide_f32(const Geometry& g, float* spec, const double* lam,
+                             const double* tmu1, const double* tmu2, const double* tmu3,
+                             hipStream_t s);
+
+// Layout conversions for the step-by-step entry points (external spectrum
+// layout: interleaved complex FP64 [nh][m][2]).
+hipError_t launch_spec_to_ext(const Geometry& g, const void* spec, int is_f32, double* ext,
+                              hipStream_t s);
+hipError_t launch_ext_to_spec(const Geometry& g, const double* ext, void* spec, int is_f32,
+                              hipStream_t s);
+
+// ---------------------------------------------------------------- Krylov kernels
+// Partial dot products: part[b*q + i] = sum over block b's elements of V_i . w,
+// V_i = V + i*ldv.  nblk blocks.  Then reduce_partials sums over blocks.
+int krylov_blocks(int64_t len);
+hipError_t launch_multidot(const double* V, int64_t ldv, int q, const double* w, int64_t len,
+                           double* part, hipStream_t s);
+// w -= sum_i h_i V_i, then (if q2 > 0) partial dots of V_i with the new w (q2 = q)
+// or (q2 < 0) partial squared norm of the new w.
+hipError_t launch_axpy_dot(const double* V, int64_t ldv, int q, const double* h, double* w,
+                           int64_t len, double* part, int mode, hipStream_t s);
+hipError_t launch_reduce_partials(const double* part, int nblk, int q, double* out,
+                                  int accumulate, hipStream_t s);
+// y = alpha * x  (alpha read from device memory as 1/alpha_ptr[0] if inv != 0)
+hipError_t launch_scale(const double* x, double* y, int64_t len, const double* alpha_dev,
+                        int inv, hipStream_t s);
+// y = alpha * x with alpha a host scalar
+hipError_t launch_scale_host(const double* x, double* y, int64_t len, double alpha, hipStream_t s);
+// x += sum_i c_i Z_i with c on device
+hipError_t launch_multi_axpy(const double* Z, int64_t ldz, int q, const double* c, double* x,
+                             int64_t len, hipStream_t s);
+// partial squared norm of (a - b) (b may be null -> ||a||^2)
+hipError_t launch_diffnorm(const double* a, const double* b, int64_t len, double* part,
+                           hipStream_t s);
+// nan/inf count partials
+hipError_t launch_nancheck(const double* a, int64_t len, double* part, hipStream_t s);
+// y = tau*f, y[0:m] += u0
+hipError_t launch_build_rhs(const double* f, const double* u0, double* y, int64_t nm, int64_t m,
+                            double tau, hipStream_t s);
+
+}  // namespace aao

@@ -1,0 +1,280 @@
+// FP64 vector kernels of the flexible GMRES loop: multi-vector dot products
+// for classical Gram-Schmidt, the fused update-then-dot/norm passes of its
+// second sweep, solution update, scaling and residual norms.
+//
+// Reductions are deterministic: every block writes its partial sums, a second
+// kernel adds the partials of each output in a fixed tree order.  Each thread
+// reads two consecutive doubles per step (16-byte loads) in a grid-stride loop.
+#include "common.h"
+
+namespace aao {
+namespace {
+
+constexpr int KT = 256;        // threads per block
+constexpr int QMAX = 8;        // vectors per fused pass
+constexpr int MAXBLK = 2048;   // partial-sum blocks
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Block-reduce Q accumulators; thread 0 writes part[blk*qtot + qoff + i].
+template <int Q>
+__device__ __forceinline__ void block_store(double (&acc)[Q], double* part, int qtot, int qoff) {
+  __shared__ double red[Q][KT / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double v = wave_sum(acc[i]);
+    if (lane == 0) red[i][wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < Q) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < KT / 64; ++w) s += red[threadIdx.x][w];
+    part[(int64_t)blockIdx.x * qtot + qoff + threadIdx.x] = s;
+  }
+}
+
+// part[b*qtot + qoff + i] = partial sum of V_{qoff+i} . w
+template <int Q>
+__global__ __launch_bounds__(KT) void k_multidot(const double* __restrict__ V, int64_t ldv,
+                                                 const double* __restrict__ w, int64_t len,
+                                                 double* __restrict__ part, int qtot, int qoff) {
+  double acc[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) acc[i] = 0.0;
+  const int64_t npair = len >> 1;
+  const double2* w2 = reinterpret_cast<const double2*>(w);
+  for (int64_t e = blockIdx.x * (int64_t)KT + threadIdx.x; e < npair;
+       e += (int64_t)gridDim.x * KT) {
+    const double2 wv = w2[e];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double2 v = reinterpret_cast<const double2*>(V + (qoff + i) * ldv)[e];
+      acc[i] += v.x * wv.x + v.y * wv.y;
+    }
+  }
+  if ((len & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) acc[i] += V[(qoff + i) * ldv + len - 1] * w[len - 1];
+  }
+  block_store<Q>(acc, part, qtot, qoff);
+}
+
+// w -= sum_{i<q} h_i V_i; then MODE 1: partial dots of V_0..V_{Q-1} with the
+// new w (requires q == Q);  MODE 2: partial ||w||^2;  MODE 0: nothing.
+template <int Q, int MODE>
+__global__ __launch_bounds__(KT) void k_axpy(const double* __restrict__ V, int64_t ldv, int q,
+                                             const double* __restrict__ h, double* __restrict__ w,
+                                             int64_t len, double* __restrict__ part) {
+  double acc[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) acc[i] = 0.0;
+  const int64_t npair = len >> 1;
+  double2* w2 = reinterpret_cast<double2*>(w);
+  auto body = [&](double& wx, int64_t idx) {
+    // scalar element update (used for the odd tail)
+    double s = wx;
+    for (int i = 0; i < q; ++i) s -= h[i] * V[i * ldv + idx];
+    wx = s;
+    if (MODE == 1) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) acc[i] += V[i * ldv + idx] * s;
+    } else if (MODE == 2) {
+      acc[0] += s * s;
+    }
+  };
+  for (int64_t e = blockIdx.x * (int64_t)KT + threadIdx.x; e < npair;
+       e += (int64_t)gridDim.x * KT) {
+    double2 wv = w2[e];
+    for (int i = 0; i < q; ++i) {
+      const double hi = h[i];
+      const double2 v = reinterpret_cast<const double2*>(V + i * ldv)[e];
+      wv.x -= hi * v.x;
+      wv.y -= hi * v.y;
+    }
+    w2[e] = wv;
+    if (MODE == 1) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const double2 v = reinterpret_cast<const double2*>(V + i * ldv)[e];
+        acc[i] += v.x * wv.x + v.y * wv.y;
+      }
+    } else if (MODE == 2) {
+      acc[0] += wv.x * wv.x + wv.y * wv.y;
+    }
+  }
+  if ((len & 1) && blockIdx.x == 0 && threadIdx.x == 0) body(w[len - 1], len - 1);
+  if (MODE != 0) block_store<Q>(acc, part, MODE == 1 ? Q : 1, 0);
+}
+
+// out[i] (+)= sum_b part[b*q + i], one block per output
+__global__ __launch_bounds__(KT) void k_reduce(const double* __restrict__ part, int nblk, int q,
+                                               double* __restrict__ out, int accumulate) {
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += KT) s += part[(int64_t)b * q + i];
+  __shared__ double red[KT / 64];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < KT / 64; ++w) t += red[w];
+    out[i] = accumulate ? out[i] + t : t;
+  }
+}
+
+__global__ void k_scale(const double* __restrict__ x, double* __restrict__ y, int64_t len,
+                        double alpha, const double* __restrict__ alpha_dev, int inv) {
+  double a = alpha;
+  if (alpha_dev) a = inv ? 1.0 / alpha_dev[0] : alpha_dev[0];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x)
+    y[e] = a * x[e];
+}
+
+__global__ void k_multi_axpy(const double* __restrict__ Z, int64_t ldz, int q,
+                             const double* __restrict__ c, double* __restrict__ x, int64_t len) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double s = x[e];
+    for (int i = 0; i < q; ++i) s += c[i] * Z[i * ldz + e];
+    x[e] = s;
+  }
+}
+
+// part[b] = partial ||a - b||^2 (b null -> ||a||^2); non-finite values propagate
+__global__ __launch_bounds__(KT) void k_diffnorm(const double* __restrict__ a,
+                                                 const double* __restrict__ b, int64_t len,
+                                                 double* __restrict__ part) {
+  double acc[1] = {0.0};
+  for (int64_t e = blockIdx.x * (int64_t)KT + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * KT) {
+    const double d = b ? a[e] - b[e] : a[e];
+    acc[0] += d * d;
+  }
+  block_store<1>(acc, part, 1, 0);
+}
+
+__global__ __launch_bounds__(KT) void k_nancheck(const double* __restrict__ a, int64_t len,
+                                                 double* __restrict__ part) {
+  double acc[1] = {0.0};
+  for (int64_t e = blockIdx.x * (int64_t)KT + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * KT)
+    if (!isfinite(a[e])) acc[0] += 1.0;
+  block_store<1>(acc, part, 1, 0);
+}
+
+__global__ void k_build_rhs(const double* __restrict__ f, const double* __restrict__ u0,
+                            double* __restrict__ y, int64_t nm, int64_t m, double tau) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nm;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double v = tau * f[e];
+    if (e < m) v += u0[e];
+    y[e] = v;
+  }
+}
+
+unsigned simple_grid(int64_t len) {
+  int64_t b = (len + 255) / 256;
+  if (b > 16384) b = 16384;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+int krylov_blocks(int64_t len) {
+  int64_t b = ((len >> 1) + KT * 4 - 1) / (KT * 4);
+  if (b > MAXBLK) b = MAXBLK;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+hipError_t launch_multidot(const double* V, int64_t ldv, int q, const double* w, int64_t len,
+                           double* part, hipStream_t s) {
+  const int nb = krylov_blocks(len);
+  for (int q0 = 0; q0 < q; q0 += QMAX) {
+    const int qq = (q - q0 < QMAX) ? q - q0 : QMAX;
+    switch (qq) {
+#define CASE(Q)                                                                                \
+  case Q:                                                                                      \
+    hipLaunchKernelGGL((k_multidot<Q>), dim3(nb), dim3(KT), 0, s, V, ldv, w, len, part, q, q0); \
+    break;
+      CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_dot(const double* V, int64_t ldv, int q, const double* h, double* w,
+                           int64_t len, double* part, int mode, hipStream_t s) {
+  const int nb = krylov_blocks(len);
+  if (mode == 1) {
+    if (q > QMAX || q < 1) return hipErrorInvalidValue;
+    switch (q) {
+#define CASE(Q)                                                                             \
+  case Q:                                                                                   \
+    hipLaunchKernelGGL((k_axpy<Q, 1>), dim3(nb), dim3(KT), 0, s, V, ldv, q, h, w, len, part); \
+    break;
+      CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    }
+  } else if (mode == 2) {
+    hipLaunchKernelGGL((k_axpy<1, 2>), dim3(nb), dim3(KT), 0, s, V, ldv, q, h, w, len, part);
+  } else {
+    hipLaunchKernelGGL((k_axpy<1, 0>), dim3(nb), dim3(KT), 0, s, V, ldv, q, h, w, len, part);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const double* part, int nblk, int q, double* out, int accumulate,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(q), dim3(KT), 0, s, part, nblk, q, out, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(const double* x, double* y, int64_t len, const double* alpha_dev, int inv,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(simple_grid(len)), dim3(256), 0, s, x, y, len, 0.0, alpha_dev,
+                     inv);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_host(const double* x, double* y, int64_t len, double alpha,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(simple_grid(len)), dim3(256), 0, s, x, y, len, alpha,
+                     (const double*)nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_axpy(const double* Z, int64_t ldz, int q, const double* c, double* x,
+                             int64_t len, hipStream_t s) {
+  hipLaunchKernelGGL(k_multi_axpy, dim3(simple_grid(len)), dim3(256), 0, s, Z, ldz, q, c, x, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_diffnorm(const double* a, const double* b, int64_t len, double* part,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_diffnorm, dim3(krylov_blocks(len)), dim3(KT), 0, s, a, b, len, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_nancheck(const double* a, int64_t len, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_nancheck, dim3(krylov_blocks(len)), dim3(KT), 0, s, a, len, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_rhs(const double* f, const double* u0, double* y, int64_t nm, int64_t m,
+                            double tau, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_rhs, dim3(simple_grid(nm)), dim3(256), 0, s, f, u0, y, nm, m, tau);
+  return hipGetLastError();
+}
+
+}  // namespace aao

@@ -1,0 +1,139 @@
+// All-at-once matrix-vector product y = L x (Section 2, eq. (allatoncesystem)):
+//   y^k = (I + tau K) x^k - x^{k-1},  x^0 := 0,
+// K the 3/5/7-point -Laplacian (constant coefficient) or the flux-form
+// discretisation of -div(a grad .) with coefficients on cell faces.
+//
+// One thread owns one spatial point and walks a chunk of time levels, keeping
+// x^{k-1} in a register, so x is read from HBM once per chunk (plus one
+// halo slab per chunk) and y written once: 16 B per unknown.  A block is a
+// 64 x 4 patch of the x-y plane; spatial neighbours come through L1/L2.
+// Workgroups are renumbered so that patches adjacent in y land on the same
+// XCD (consecutive hardware workgroup ids rotate over the 8 XCDs).
+#include "common.h"
+
+namespace aao {
+namespace {
+
+constexpr int TX = 64;       // points along x per block
+constexpr int TY = 4;        // rows along y per block
+constexpr int TCHUNK = 8;    // time levels per block
+constexpr int NXCD = 8;
+
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+  // Hardware places workgroup b on XCD b % 8.  Give each XCD a contiguous run
+  // of logical tiles.  Valid for any nblk: the first (nblk % 8) XCDs get one
+  // extra tile.
+  const int q = nblk / NXCD, r = nblk % NXCD;
+  const int xcd = bid % NXCD, slot = bid / NXCD;
+  const int start = xcd * q + (xcd < r ? xcd : r);
+  return start + slot;
+}
+
+template <int DIM, bool VAR>
+__global__ __launch_bounds__(TX * TY) void k_apply_L(
+    const double* __restrict__ x, double* __restrict__ y, int n, int m1, int m2, int m3,
+    int nbx, int nby, int nbt, double c1, double c2, double c3, const double* __restrict__ ax,
+    const double* __restrict__ ay, const double* __restrict__ az) {
+  const int nblk = nbx * nby * m3 * nbt;
+  const int b = xcd_remap(blockIdx.x, nblk);
+  // logical tile order: x tiles fastest, then y tiles, then z, then time chunk
+  int t = b;
+  const int bx = t % nbx; t /= nbx;
+  const int by = t % nby; t /= nby;
+  const int i3 = t % m3;  t /= m3;
+  const int bt = t;
+  const int i1 = bx * TX + threadIdx.x;
+  const int i2 = by * TY + threadIdx.y;
+  if (i1 >= m1 || i2 >= m2) return;
+  const int64_t m = (int64_t)m1 * m2 * m3;
+  const int64_t s = i1 + (int64_t)m1 * (i2 + (int64_t)m2 * i3);
+  const int64_t sx = 1, sy = m1, sz = (int64_t)m1 * m2;
+
+  // stencil weights (already multiplied by tau/h^2)
+  double wxm, wxp, wym = 0, wyp = 0, wzm = 0, wzp = 0, diag;
+  if (VAR) {
+    const int64_t fx = (int64_t)(i3 * m2 + i2) * (m1 + 1) + i1;
+    wxm = ax[fx];
+    wxp = ax[fx + 1];
+    diag = 1.0 + wxm + wxp;
+    if (DIM >= 2) {
+      const int64_t fy = (int64_t)(i3 * (m2 + 1) + i2) * m1 + i1;
+      wym = ay[fy];
+      wyp = ay[fy + m1];
+      diag += wym + wyp;
+    }
+    if (DIM >= 3) {
+      const int64_t fz = (int64_t)(i3 * m2 + i2) * m1 + i1;
+      wzm = az[fz];
+      wzp = az[fz + (int64_t)m2 * m1];
+      diag += wzm + wzp;
+    }
+  } else {
+    wxm = wxp = c1;
+    diag = 1.0 + 2.0 * c1;
+    if (DIM >= 2) { wym = wyp = c2; diag += 2.0 * c2; }
+    if (DIM >= 3) { wzm = wzp = c3; diag += 2.0 * c3; }
+  }
+  // Dirichlet zero: drop couplings that leave the grid
+  const bool hxm = i1 > 0, hxp = i1 < m1 - 1;
+  const bool hym = DIM >= 2 && i2 > 0, hyp = DIM >= 2 && i2 < m2 - 1;
+  const bool hzm = DIM >= 3 && i3 > 0, hzp = DIM >= 3 && i3 < m3 - 1;
+
+  const int k0 = bt * TCHUNK;
+  const int k1 = min(n, k0 + TCHUNK);
+  double prev = (k0 > 0) ? x[(int64_t)(k0 - 1) * m + s] : 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const double* xk = x + (int64_t)k * m + s;
+    const double xc = xk[0];
+    double nb = 0.0;
+    if (hxm) nb += wxm * xk[-sx];
+    if (hxp) nb += wxp * xk[sx];
+    if (DIM >= 2) {
+      if (hym) nb += wym * xk[-sy];
+      if (hyp) nb += wyp * xk[sy];
+    }
+    if (DIM >= 3) {
+      if (hzm) nb += wzm * xk[-sz];
+      if (hzp) nb += wzp * xk[sz];
+    }
+    y[(int64_t)k * m + s] = diag * xc - nb - prev;
+    prev = xc;
+  }
+}
+
+template <int DIM, bool VAR>
+hipError_t launch(const Geometry& g, const double* x, double* y, double c1, double c2, double c3,
+                  const double* ax, const double* ay, const double* az, hipStream_t s) {
+  const int nbx = (g.m1 + TX - 1) / TX;
+  const int nby = (g.m2 + TY - 1) / TY;
+  const int nbt = (g.n + TCHUNK - 1) / TCHUNK;
+  const int64_t nblk = (int64_t)nbx * nby * g.m3 * nbt;
+  if (nblk <= 0 || nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_apply_L<DIM, VAR>), dim3((unsigned)nblk), dim3(TX, TY), 0, s, x, y, g.n,
+                     g.m1, g.m2, g.m3, nbx, nby, nbt, c1, c2, c3, ax, ay, az);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_apply_L(const Geometry& g, const double* x, double* y, double c1, double c2,
+                          double c3, hipStream_t s) {
+  switch (g.dim) {
+    case 1: return launch<1, false>(g, x, y, c1, c2, c3, nullptr, nullptr, nullptr, s);
+    case 2: return launch<2, false>(g, x, y, c1, c2, c3, nullptr, nullptr, nullptr, s);
+    case 3: return launch<3, false>(g, x, y, c1, c2, c3, nullptr, nullptr, nullptr, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_apply_L_var(const Geometry& g, const double* x, double* y, const double* ax,
+                              const double* ay, const double* az, hipStream_t s) {
+  switch (g.dim) {
+    case 1: return launch<1, true>(g, x, y, 0, 0, 0, ax, ay, az, s);
+    case 2: return launch<2, true>(g, x, y, 0, 0, 0, ax, ay, az, s);
+    case 3: return launch<3, true>(g, x, y, 0, 0, 0, ax, ay, az, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace aao

@@ -1,0 +1,254 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances (relative 2-norm unless stated), derived in the design doc:
+  FP64 steps 1/3 and L v      1e-12   (u = 1.1e-16, log2 n passes, eps^{-1} <= 32)
+  FP64 step 2 / P^{-1}        1e-11   (dense orthogonal transforms, K <= 1024 terms)
+  FP64 solve                  1e-10   (iterate at equal k, and vs sequential BE)
+  FP32 steps                  3e-5    (u = 6e-8, same growth factors)
+  mixed / learned solves      1e-8    (after FGMRES, against the FP64 oracle)
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import heat
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def solver(dim, m1, n, eps, precision="fp64", T=1.0):
+    from paper_2002_01108_amd import Solver
+    return Solver(dim, m1, n, T=T, eps=eps, precision=precision)
+
+
+GRIDS = [  # (dim, m1, n, eps): ragged tiles, several tiles, every FFT length class
+    (1, 63, 64, 0.125),
+    (1, 5, 2, 0.5),
+    (1, 37, 4, 0.3),
+    (1, 64, 8, 0.2),
+    (1, 130, 16, 0.25),
+    (1, 19, 1024, 0.03),
+    (2, 37, 32, 0.1),
+    (2, 100, 128, 1.0 / 11),
+    (2, 65, 512, 0.05),
+    (2, 128, 256, 1.0),
+    (3, 13, 16, 0.25),
+    (3, 20, 64, 0.125),
+]
+
+
+def _rand(shape, seed):
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+@pytest.mark.parametrize("dim,m1,n,eps", GRIDS)
+def test_apply_A(dim, m1, n, eps):
+    p = heat.Problem(m1, dim, n, eps=eps)
+    x = _rand((n, p.m), 1)
+    s = solver(dim, m1, n, eps)
+    y = host(s.apply_A(dev(x)))
+    assert rel(y, p.L(x)) <= 1e-12
+
+
+@pytest.mark.parametrize("dim,m1,n,eps", GRIDS)
+def test_step1(dim, m1, n, eps):
+    p = heat.Problem(m1, dim, n, eps=eps)
+    y = _rand((n, p.m), 2)
+    s = solver(dim, m1, n, eps)
+    yt = host(s.step1(dev(y)))
+    got = yt[..., 0] + 1j * yt[..., 1]
+    want = heat.step1(y, eps)
+    assert rel(got, want) <= 1e-12
+
+
+@pytest.mark.parametrize("dim,m1,n,eps", GRIDS)
+def test_step3(dim, m1, n, eps):
+    p = heat.Problem(m1, dim, n, eps=eps)
+    rng = np.random.default_rng(3)
+    zt = rng.standard_normal((n // 2 + 1, p.m, 2))
+    s = solver(dim, m1, n, eps)
+    z = host(s.step3(dev(zt)))
+    want = heat.step3(zt[..., 0] + 1j * zt[..., 1], eps, n)
+    assert rel(z, want) <= 1e-12
+
+
+@pytest.mark.parametrize("dim,m1,n,eps", GRIDS)
+def test_step2(dim, m1, n, eps):
+    p = heat.Problem(m1, dim, n, eps=eps)
+    rng = np.random.default_rng(4)
+    yt = rng.standard_normal((n // 2 + 1, p.m, 2))
+    yt[0, :, 1] = 0.0
+    yt[-1, :, 1] = 0.0
+    s = solver(dim, m1, n, eps)
+    zt = host(s.step2(dev(yt)))
+    lam = heat.lambdas(n, eps)[: n // 2 + 1]
+    want = heat.step2(p.K, p.tau, lam, yt[..., 0] + 1j * yt[..., 1])
+    assert rel(zt[..., 0] + 1j * zt[..., 1], want) <= 1e-11
+
+
+@pytest.mark.parametrize("dim,m1,n,eps", GRIDS)
+def test_apply_Pinv(dim, m1, n, eps):
+    p = heat.Problem(m1, dim, n, eps=eps)
+    y = _rand((n, p.m), 5)
+    s = solver(dim, m1, n, eps)
+    z = host(s.apply_Pinv(dev(y)))
+    assert rel(z, p.Pinv(y)) <= 1e-11
+    assert rel(p.P(z), y) <= 1e-11
+
+
+def test_apply_Pinv_in_place():
+    dim, m1, n, eps = 2, 37, 32, 0.1
+    p = heat.Problem(m1, dim, n, eps=eps)
+    y = _rand((n, p.m), 6)
+    s = solver(dim, m1, n, eps)
+    t = dev(y)
+    s.apply_Pinv(t, out=t)
+    assert rel(host(t), p.Pinv(y)) <= 1e-11
+
+
+def test_build_rhs():
+    w = W.WORKLOADS["heat1d_63x64"]
+    f, u0, _ = W.make(w)
+    s = solver(1, w.m1, w.n, w.epsilon)
+    got = host(s.build_rhs(dev(f), dev(u0)))
+    assert np.array_equal(got, heat.build_rhs(f, u0, w.tau)) or rel(got, heat.build_rhs(f, u0, w.tau)) <= 1e-15
+
+
+def test_repeat_is_deterministic():
+    dim, m1, n, eps = 2, 100, 32, 0.1
+    y = dev(_rand((n, m1 * m1), 7))
+    s = solver(dim, m1, n, eps)
+    a = host(s.apply_Pinv(y))
+    b = host(s.apply_Pinv(y))
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ solve
+
+def _c1():
+    w = W.WORKLOADS["heat1d_63x64"]
+    p = heat.Problem(w.m1, w.dim, w.n, eps=w.epsilon)
+    f, u0, _ = W.make(w)
+    return w, p, p.rhs(f, u0)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_solve_iterate_matches_oracle_gmres(k):
+    """Same Krylov step count k on both sides (tol = 0, maxit = k)."""
+    w, p, rhs = _c1()
+    x_or, it, _ = p.gmres(rhs, tol=0.0, maxit=k)
+    assert it == k
+    s = solver(w.dim, w.m1, w.n, w.epsilon)
+    u, info = s.solve(dev(rhs), tol=0.0, maxit=k)
+    assert info["iters"] == k
+    assert rel(host(u), x_or) <= 1e-10
+
+
+def test_solve_matches_sequential_be():
+    w, p, rhs = _c1()
+    exact = p.exact(rhs)
+    s = solver(w.dim, w.m1, w.n, w.epsilon)
+    u, info = s.solve(dev(rhs), tol=1e-12)
+    assert info["status"] == 0
+    assert rel(host(u), exact) <= 1e-10
+
+
+def test_solve_metric_run_c1():
+    """tol 1e-8: same iteration count as the oracle, explicit RES within tol."""
+    w, p, rhs = _c1()
+    _, it_or, hist_or = p.gmres(rhs, tol=1e-8)
+    s = solver(w.dim, w.m1, w.n, w.epsilon)
+    u, info = s.solve(dev(rhs), tol=1e-8)
+    assert info["iters"] == it_or == 2
+    assert info["final_res"] <= 1e-8
+    np.testing.assert_allclose(info["hist"], hist_or, rtol=1e-6)
+
+
+@pytest.mark.parametrize("dim,m1,n", [(2, 100, 32), (3, 20, 16), (2, 65, 512)])
+def test_solve_grids(dim, m1, n):
+    p = heat.Problem(m1, dim, n)
+    f = _rand((n, p.m), 8)
+    u0 = W.initial_value(m1, dim, "modes", 9)
+    rhs = p.rhs(f, u0)
+    exact = p.exact(rhs)
+    s = solver(dim, m1, n, p.eps)
+    u, info = s.solve(dev(rhs), tol=1e-12)
+    assert info["status"] == 0 and info["iters"] <= 4
+    assert rel(host(u), exact) <= 1e-10
+
+
+def test_solve_restart_and_guess():
+    """Restart length 1 (many cycles) and a warm start reach the same solution."""
+    w, p, rhs = _c1()
+    exact = p.exact(rhs)
+    s = solver(w.dim, w.m1, w.n, w.epsilon)
+    u, info = s.solve(dev(rhs), tol=1e-12, restart=1, maxit=20)
+    assert info["status"] == 0
+    assert rel(host(u), exact) <= 1e-10
+    u2, info2 = s.solve(dev(rhs), tol=1e-12, u=u.clone(), use_guess=True)
+    assert info2["iters"] <= 1
+    assert rel(host(u2), exact) <= 1e-10
+
+
+def test_solve_not_converged_and_nan():
+    from paper_2002_01108_amd import AaoError
+    w, p, rhs = _c1()
+    s = solver(w.dim, w.m1, w.n, 1.0)          # block circulant: slow convergence
+    u, info = s.solve(dev(rhs), tol=1e-14, maxit=2)
+    assert info["status"] == 1 and info["iters"] == 2
+    bad = rhs.copy()
+    bad[3, 5] = np.nan
+    with pytest.raises(AaoError) as e:
+        s.solve(dev(bad))
+    assert e.value.status == -4
+
+
+def test_zero_rhs():
+    s = solver(1, 15, 8, 0.2)
+    u, info = s.solve(dev(np.zeros((8, 15))))
+    assert info["iters"] == 0 and np.all(host(u) == 0)
+
+
+# ------------------------------------------------------------------ FP32 preconditioner
+
+@pytest.mark.parametrize("dim,m1,n,eps", [(1, 63, 64, 0.125), (2, 100, 128, 1.0 / 11),
+                                          (3, 20, 64, 0.125), (2, 65, 512, 0.05)])
+def test_fp32_steps(dim, m1, n, eps):
+    p = heat.Problem(m1, dim, n, eps=eps)
+    s = solver(dim, m1, n, eps, precision="fp32")
+    y = _rand((n, p.m), 10)
+    yt = host(s.step1(dev(y)))
+    assert rel(yt[..., 0] + 1j * yt[..., 1], heat.step1(y, eps)) <= 3e-5
+    z = host(s.apply_Pinv(dev(y)))
+    assert rel(z, p.Pinv(y)) <= 3e-5
+
+
+@pytest.mark.parametrize("dim,m1,n", [(1, 63, 64), (2, 100, 32), (3, 20, 16)])
+def test_fp32_fgmres_recovers_fp64(dim, m1, n):
+    p = heat.Problem(m1, dim, n)
+    f = _rand((n, p.m), 11)
+    rhs = p.rhs(f, W.initial_value(m1, dim, "modes", 12))
+    exact = p.exact(rhs)
+    s = solver(dim, m1, n, p.eps, precision="fp32")
+    u, info = s.solve(dev(rhs), tol=1e-10)
+    assert info["status"] == 0
+    assert info["final_res"] <= 1e-10
+    assert rel(host(u), exact) <= 1e-8
