@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--variants", default="fp32", help="comma list of extra precisions to time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=32)
+    ap.add_argument("--cpu-sample-steps", type=int, default=64)
     return ap.parse_args()
 
 
