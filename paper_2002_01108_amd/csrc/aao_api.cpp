@@ -35,6 +35,8 @@ struct aao_ctx {
   double* tmu[3] = {nullptr, nullptr, nullptr};  // tau * mu_i per axis (padded, 0 in pads)
   double* S64[3] = {nullptr, nullptr, nullptr};  // DST-I matrices per axis, P_d x P_d
   float* S32[3] = {nullptr, nullptr, nullptr};
+  uint16_t* Shi[3] = {nullptr, nullptr, nullptr};  // BF16 hi/lo split of S32 (bit patterns)
+  uint16_t* Slo[3] = {nullptr, nullptr, nullptr};
 
   // spectrum workspace (ping-pong), sized for the current precision
   void* specA = nullptr;
@@ -149,6 +151,20 @@ double sin_pi_frac(long long p, long long q) {
   return sin(kPi * (double)r / (double)q);
 }
 
+// round-to-nearest-even FP32 -> BF16 (bit pattern) and back
+uint16_t bf16_rne_host(float x) {
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float bf16_value_host(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float x;
+  memcpy(&x, &u, 4);
+  return x;
+}
+
 size_t spec_elems(const Geometry& g) { return (size_t)g.nh * 2 * (size_t)g.PS; }
 
 aao_status ensure_spec(aao_ctx* c) {
@@ -251,6 +267,13 @@ hipError_t mode_product(aao_ctx* c, int d, const void* in, void* out) {
                              1, c->stream);
     return launch_gemm_f64(S, 0, lda, (const double*)in, sB, ldb, (double*)out, sC, ldc, M, N, K,
                            batch, c->stream);
+  }
+  if (c->prec == AAO_BF16X3) {
+    if (right)
+      return launch_gemm_bf16x3_right((const float*)in, 0, lda, c->Shi[d], c->Slo[d], 0, ldb,
+                                      (float*)out, 0, ldc, M, N, K, 1, c->stream);
+    return launch_gemm_bf16x3(c->Shi[d], c->Slo[d], 0, lda, (const float*)in, sB, ldb,
+                              (float*)out, sC, ldc, M, N, K, batch, c->stream);
   }
   const float* S = c->S32[d];
   if (right)
@@ -452,6 +475,14 @@ aao_status aao_setup(int dim, int m1, int m2, int m3, int n, double T, double ep
     if ((st = upload(c, &c->tmu[d], tmu)) != AAO_OK) return bail(st);
     if ((st = upload(c, &c->S64[d], S)) != AAO_OK) return bail(st);
     if ((st = upload(c, &c->S32[d], S32)) != AAO_OK) return bail(st);
+    // BF16 split of the FP32 matrix: hi = rne(s), lo = rne(s - hi)
+    std::vector<uint16_t> hi((size_t)P * P), lo((size_t)P * P);
+    for (size_t e = 0; e < S32.size(); ++e) {
+      hi[e] = bf16_rne_host(S32[e]);
+      lo[e] = bf16_rne_host(S32[e] - bf16_value_host(hi[e]));
+    }
+    if ((st = upload(c, &c->Shi[d], hi)) != AAO_OK) return bail(st);
+    if ((st = upload(c, &c->Slo[d], lo)) != AAO_OK) return bail(st);
   }
   if ((st = ensure_spec(c)) != AAO_OK) return bail(st);
   if ((st = ensure_small(c, 256)) != AAO_OK) return bail(st);
@@ -467,7 +498,8 @@ aao_status aao_set_stream(aao_ctx* ctx, void* hip_stream) {
 
 aao_status aao_set_precision(aao_ctx* ctx, aao_precision p) {
   if (!ctx) return AAO_EINVAL;
-  if (p != AAO_FP64 && p != AAO_FP32) return fail(ctx, AAO_EINVAL, "unsupported precision");
+  if (p != AAO_FP64 && p != AAO_FP32 && p != AAO_BF16X3)
+    return fail(ctx, AAO_EINVAL, "unsupported precision");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   ctx->prec = p;
   return ensure_spec(ctx);

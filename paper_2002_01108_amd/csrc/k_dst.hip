@@ -145,6 +145,151 @@ hipError_t gemm_launch(const T* A, int64_t sA, int lda, const T* B, int64_t sB, 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- BF16 hi/lo products
+// C = A * B with one FP32 operand (the spectrum) split on the fly into
+// hi = rne_bf16(x), lo = rne_bf16(x - hi) and the other (S) split once on the
+// host; C accumulates hi*hi + hi*lo + lo*hi in FP32 on v_mfma_f32_16x16x32_bf16.
+// Both LDS tiles keep k contiguous so that each lane reads its 8 k values of
+// a fragment with one 16-byte load.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s8v __attribute__((ext_vector_type(8)));
+typedef unsigned short u16;
+
+__device__ __forceinline__ u16 bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (u16)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(u16 h) { return __uint_as_float((uint32_t)h << 16); }
+
+constexpr int XBK = 32, XPAD = 8;
+
+template <bool A_DATA>
+__global__ __launch_bounds__(GTHREADS) void k_gemm_bf16x3(
+    const float* __restrict__ Dm, int64_t sD, int ldd,          // FP32 data operand
+    const u16* __restrict__ Shi, const u16* __restrict__ Slo,   // pre-split operand
+    int lds_, float* __restrict__ C, int64_t sC, int ldc, int M, int N, int K, int tiles_m,
+    int tiles_n) {
+  __shared__ __attribute__((aligned(16))) u16 Ah[2][BM][XBK + XPAD];
+  __shared__ __attribute__((aligned(16))) u16 Al[2][BM][XBK + XPAD];
+  __shared__ __attribute__((aligned(16))) u16 Bh[2][BN][XBK + XPAD];
+  __shared__ __attribute__((aligned(16))) u16 Bl[2][BN][XBK + XPAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  int bid = blockIdx.x;
+  const int tn = bid % tiles_n;
+  bid /= tiles_n;
+  const int tm = bid % tiles_m;
+  const int batch = bid / tiles_m;
+  const int m0 = tm * BM, n0 = tn * BN;
+  Dm += batch * sD;
+  C += batch * sC;
+
+  // A tile: row ar (0..63), k ak..ak+7;  B tile: k bk (0..31), cols bn..bn+7
+  const int ar = tid >> 2, ak = (tid & 3) * 8;
+  const int bk = tid >> 3, bn = (tid & 7) * 8;
+  const bool arow_ok = (m0 + ar) < M;
+
+  u16 rah[8], ral[8], rbh[8], rbl[8];
+  auto fetch = [&](int k0) {
+    if (A_DATA) {  // A = data rows (M x K, ldd), B = S (K x N, lds_)
+      const float* p = Dm + (int64_t)(arow_ok ? m0 + ar : 0) * ldd + k0 + ak;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float x = arow_ok ? p[e] : 0.f;
+        rah[e] = bf16_rne(x);
+        ral[e] = bf16_rne(x - bf16_val(rah[e]));
+      }
+      const int64_t o = (int64_t)(k0 + bk) * lds_ + n0 + bn;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) { rbh[e] = Shi[o + e]; rbl[e] = Slo[o + e]; }
+    } else {       // A = S (M x K, lds_), B = data (K x N, ldd)
+      const int64_t o = (int64_t)(m0 + ar) * lds_ + k0 + ak;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) { rah[e] = Shi[o + e]; ral[e] = Slo[o + e]; }
+      const float* p = Dm + (int64_t)(k0 + bk) * ldd + n0 + bn;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float x = p[e];
+        rbh[e] = bf16_rne(x);
+        rbl[e] = bf16_rne(x - bf16_val(rbh[e]));
+      }
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) { Ah[buf][ar][ak + e] = rah[e]; Al[buf][ar][ak + e] = ral[e]; }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) { Bh[buf][bn + e][bk] = rbh[e]; Bl[buf][bn + e][bk] = rbl[e]; }
+  };
+
+  f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0, 0, 0, 0};
+
+  const int lr = lane & 15, lk = lane >> 4;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  const int nk = K / XBK;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) fetch((kt + 1) * XBK);
+    bf16x8 ahi[2], alo[2], bhi[2], blo[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int r = wm * 32 + i * 16 + lr;
+      ahi[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const s8v*>(&Ah[buf][r][lk * 8]));
+      alo[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const s8v*>(&Al[buf][r][lk * 8]));
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = wn * 32 + j * 16 + lr;
+      bhi[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const s8v*>(&Bh[buf][c][lk * 8]));
+      blo[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const s8v*>(&Bl[buf][c][lk * 8]));
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i], bhi[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], blo[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], bhi[j], acc[i][j], 0, 0, 0);
+      }
+    if (kt + 1 < nk) stash(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn * 32 + j * 16 + lr;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm * 32 + i * 16 + 4 * lk + v;
+        if (row < M) C[(int64_t)row * ldc + col] = acc[i][j][v];
+      }
+    }
+}
+
+template <bool A_DATA>
+hipError_t bf16x3_launch(const float* D, int64_t sD, int ldd, const u16* Shi, const u16* Slo,
+                         int lds_, float* C, int64_t sC, int ldc, int M, int N, int K, int batch,
+                         hipStream_t s) {
+  if (N % BN || K % XBK || M <= 0 || batch <= 0) return hipErrorInvalidValue;
+  if (!A_DATA && M % BM) return hipErrorInvalidValue;
+  const int tiles_m = (M + BM - 1) / BM, tiles_n = N / BN;
+  const int64_t nblk = (int64_t)tiles_m * tiles_n * batch;
+  if (nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_gemm_bf16x3<A_DATA>), dim3((unsigned)nblk), dim3(GTHREADS), 0, s, D, sD,
+                     ldd, Shi, Slo, lds_, C, sC, ldc, M, N, K, tiles_m, tiles_n);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- shifted divide
 template <typename T>
 __global__ void k_divide(T* __restrict__ spec, const double* __restrict__ lam,
@@ -242,6 +387,21 @@ hipError_t launch_gemm_f32(const float* A, int64_t sA, int lda, const float* B, 
                            int ldb, float* C, int64_t sC, int ldc, int M, int N, int K, int batch,
                            hipStream_t s) {
   return gemm_launch<float>(A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, batch, s);
+}
+
+hipError_t launch_gemm_bf16x3(const uint16_t* Ahi, const uint16_t* Alo, int64_t sA, int lda,
+                              const float* B, int64_t sB, int ldb, float* C, int64_t sC, int ldc,
+                              int M, int N, int K, int batch, hipStream_t s) {
+  if (sA != 0) return hipErrorInvalidValue;  // the split operand is a shared matrix
+  return bf16x3_launch<false>(B, sB, ldb, Ahi, Alo, lda, C, sC, ldc, M, N, K, batch, s);
+}
+
+hipError_t launch_gemm_bf16x3_right(const float* A, int64_t sA, int lda, const uint16_t* Bhi,
+                                    const uint16_t* Blo, int64_t sB, int ldb, float* C,
+                                    int64_t sC, int ldc, int M, int N, int K, int batch,
+                                    hipStream_t s) {
+  if (sB != 0) return hipErrorInvalidValue;
+  return bf16x3_launch<true>(A, sA, lda, Bhi, Blo, ldb, C, sC, ldc, M, N, K, batch, s);
 }
 
 hipError_t launch_divide_f64(const Geometry& g, double* spec, const double* lam,

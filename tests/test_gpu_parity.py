@@ -252,3 +252,41 @@ def test_fp32_fgmres_recovers_fp64(dim, m1, n):
     assert info["status"] == 0
     assert info["final_res"] <= 1e-10
     assert rel(host(u), exact) <= 1e-8
+
+
+# ------------------------------------------------------------------ BF16 hi/lo preconditioner
+# Per product the split drops lo*lo (<= 2^-18 |ab|) and rounds both lo parts
+# (<= 2^-17 |ab| each): <= 1.9e-5 relative, about 1e-5 for a sum of K random-sign
+# terms; four mode products and the Gamma_eps^-1 growth (<= 33) give 3e-4.
+
+@pytest.mark.parametrize("dim,m1,n,eps", [(1, 63, 64, 0.125), (2, 100, 128, 1.0 / 11),
+                                          (3, 20, 64, 0.125), (2, 65, 512, 0.05)])
+def test_bf16x3_steps(dim, m1, n, eps):
+    p = heat.Problem(m1, dim, n, eps=eps)
+    s = solver(dim, m1, n, eps, precision="bf16x3")
+    y = _rand((n, p.m), 13)
+    z = host(s.apply_Pinv(dev(y)))
+    err = rel(z, p.Pinv(y))
+    assert err <= 3e-4
+    assert err >= 1e-9          # it really ran in reduced precision
+    rng = np.random.default_rng(14)
+    yt = rng.standard_normal((n // 2 + 1, p.m, 2))
+    yt[0, :, 1] = 0.0
+    yt[-1, :, 1] = 0.0
+    zt = host(s.step2(dev(yt)))
+    lam = heat.lambdas(n, eps)[: n // 2 + 1]
+    want = heat.step2(p.K, p.tau, lam, yt[..., 0] + 1j * yt[..., 1])
+    assert rel(zt[..., 0] + 1j * zt[..., 1], want) <= 3e-4
+
+
+@pytest.mark.parametrize("dim,m1,n", [(1, 63, 64), (2, 100, 32), (3, 20, 16)])
+def test_bf16x3_fgmres_recovers_fp64(dim, m1, n):
+    p = heat.Problem(m1, dim, n)
+    f = _rand((n, p.m), 15)
+    rhs = p.rhs(f, W.initial_value(m1, dim, "modes", 16))
+    exact = p.exact(rhs)
+    s = solver(dim, m1, n, p.eps, precision="bf16x3")
+    u, info = s.solve(dev(rhs), tol=1e-10)
+    assert info["status"] == 0
+    assert info["final_res"] <= 1e-10
+    assert rel(host(u), exact) <= 1e-8
