@@ -79,6 +79,41 @@ aao_status aao_set_stream(aao_ctx *ctx, void *hip_stream);
  * differently sized spectrum workspace. */
 aao_status aao_set_precision(aao_ctx *ctx, aao_precision p);
 
+/* Variable coefficient a(x) of -div(a grad u) (Section 2, eq. (heateq)), given
+ * on cell faces as HOST arrays (copied; the caller keeps ownership):
+ *   1D: ax[m1+1];  2D: ax[m2][m1+1], ay[m2+1][m1];
+ *   3D: ax[m3][m2][m1+1], ay[m3][m2+1][m1], az[m3+1][m2][m1];
+ * x-face i of a row lies between interior nodes i-1 and i (face 0 and face m1
+ * touch the walls).  K becomes the flux form (K u)_p = h^-2 sum_f a_f (u_p - u_nbr).
+ * ax = null restores a = 1.  Values must be positive and finite (AAO_EINVAL).
+ * With a variable coefficient the blocks of Step 2 are no longer diagonalised
+ * by sine transforms: select AAO_INNER_DST_MEAN or AAO_INNER_MG. */
+aao_status aao_set_coefficient(aao_ctx *ctx, const double *ax, const double *ay,
+                               const double *az);
+
+/* Inner solver of Step 2 (eq. (blockdiaginv)) for each block
+ * B_k = lambda_k I + tau K:
+ *   AAO_INNER_DST       exact sine-transform diagonalisation (constant a only;
+ *                       AAO_ESTATE at apply time otherwise)
+ *   AAO_INNER_DST_MEAN  sine-transform solve of lambda_k I + tau abar K_h, abar
+ *                       the arithmetic mean of all face coefficients
+ *   AAO_INNER_MG        `cycles` geometric multigrid V-cycles (Section 4 and
+ *                       Section 5, Example 2: one V-cycle, one pre- and one
+ *                       post-smoothing step; here red-black Gauss-Seidel, full
+ *                       weighting, bilinear prolongation, rediscretised coarse
+ *                       grids with harmonic face means).  Square 2D grids only
+ *                       (AAO_EINVAL otherwise); a full hierarchy needs
+ *                       m1 = 2^L - 1.
+ * Inexact inner solves make the preconditioner approximate: aao_solve is
+ * flexible GMRES, so any inner solver is admissible. */
+typedef enum {
+  AAO_INNER_DST = 0,
+  AAO_INNER_DST_MEAN = 1,
+  AAO_INNER_MG = 2,
+  AAO_INNER_CNN = 3
+} aao_inner;
+aao_status aao_set_inner(aao_ctx *ctx, aao_inner inner, int cycles);
+
 /* rhs = (tau f^1 + u0; tau f^2; ...; tau f^n) (Section 2, eq. (allatoncesystem)).
  * f: device [n][m], u0: device [m], rhs: device [n][m] (may alias f). */
 aao_status aao_build_rhs(aao_ctx *ctx, const double *f, const double *u0, double *rhs);

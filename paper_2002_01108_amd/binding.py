@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libaao.so")
 
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ENAN, ESTATE = 0, 1, -1, -2, -3, -4, -5
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+INNERS = {"dst": 0, "dst_mean": 1, "mg": 2, "cnn": 3}
 
 # exported symbols and their signatures: (restype, argtypes)
 _c_int, _c_double, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
@@ -39,6 +40,8 @@ SIGNATURES = {
     "aao_status_string": (ctypes.c_char_p, [_c_int]),
     "aao_last_error": (ctypes.c_char_p, [_vp]),
     "aao_query": (_c_int, [_vp, _pint]),
+    "aao_set_coefficient": (_c_int, [_vp, _pdbl, _pdbl, _pdbl]),
+    "aao_set_inner": (_c_int, [_vp, _c_int, _c_int]),
     "aao_profile": (_c_int, [_vp, _c_int]),
     "aao_profile_read": (_c_int, [_vp, _pdbl, _pint]),
 }
@@ -114,6 +117,19 @@ class Solver:
     def set_precision(self, precision: str):
         self.precision = precision
         self._check(self.lib.aao_set_precision(self._h, PRECISIONS[precision]))
+
+    def set_coefficient(self, faces=None):
+        """Face coefficients (host numpy arrays, see include/aao.h); None: a = 1."""
+        if faces is None:
+            self._check(self.lib.aao_set_coefficient(self._h, None, None, None))
+            return
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in faces]
+        self._faces = arrs   # keep alive during the call
+        ptrs = [a.ctypes.data_as(_pdbl) for a in arrs] + [None] * (3 - len(arrs))
+        self._check(self.lib.aao_set_coefficient(self._h, *ptrs))
+
+    def set_inner(self, inner: str = "dst", cycles: int = 1):
+        self._check(self.lib.aao_set_inner(self._h, INNERS[inner], cycles))
 
     def query(self):
         out = (ctypes.c_int * 9)()

@@ -54,6 +54,31 @@ struct aao_ctx {
   double* hsmall = nullptr;      // pinned host mirror
   size_t small_elems = 0;
 
+  // variable coefficient (aao_set_coefficient)
+  bool var = false;
+  std::vector<double> host_face[3];       // a on faces, caller layout
+  double* wface[3] = {nullptr, nullptr, nullptr};     // tau/h^2 * a per face (FP64)
+  double amean = 1.0;
+  double* tmu_mean[3] = {nullptr, nullptr, nullptr};  // amean * tau * mu_i
+
+  // inner solver of Step 2 (aao_set_inner)
+  aao_inner inner = AAO_INNER_DST;
+  int inner_cycles = 1;
+
+  // multigrid hierarchy (2D), built lazily for the current precision
+  struct MgLevel {
+    int m = 0;
+    void* wx = nullptr;   // [m][m+1] face weights, spectrum precision
+    void* wy = nullptr;   // [m+1][m]
+    void* E = nullptr;    // levels >= 1: correction, compact [nh][2][m][m]
+    void* R = nullptr;    // levels >= 1: right-hand side
+    void* Res = nullptr;  // residual on this level (compact)
+  };
+  std::vector<MgLevel> mg;
+  int mg_prec = -1;
+  void* specC = nullptr;  // outer residual / correction for several V-cycles
+  void* specD = nullptr;
+
   // per-class launch timing (aao_profile)
   int prof_mask = 0;
   std::vector<hipEvent_t> ev_pool;
@@ -173,7 +198,9 @@ aao_status ensure_spec(aao_ctx* c) {
   if (bytes == c->spec_bytes && c->specA) return AAO_OK;
   dfree(c, c->specA);
   dfree(c, c->specB);
-  c->specA = c->specB = nullptr;
+  dfree(c, c->specC);
+  dfree(c, c->specD);
+  c->specA = c->specB = c->specC = c->specD = nullptr;
   c->spec_bytes = 0;
   char* a = nullptr;
   char* b = nullptr;
@@ -283,29 +310,219 @@ hipError_t mode_product(aao_ctx* c, int d, const void* in, void* out) {
                          batch, c->stream);
 }
 
-hipError_t run_divide(aao_ctx* c, void* spec) {
+// Divide by lambda_k + sum_d tmu_d; `mean` selects the mean-coefficient tables.
+hipError_t run_divide(aao_ctx* c, void* spec, bool mean) {
   ProfScope ps(c, AAO_K_DIVIDE);
   const Geometry& g = c->g;
-  const double* t2 = g.dim >= 2 ? c->tmu[1] : nullptr;
-  const double* t3 = g.dim >= 3 ? c->tmu[2] : nullptr;
+  double* const* tm = mean ? c->tmu_mean : c->tmu;
+  const double* t2 = g.dim >= 2 ? tm[1] : nullptr;
+  const double* t3 = g.dim >= 3 ? tm[2] : nullptr;
   if (c->prec == AAO_FP64)
-    return launch_divide_f64(g, (double*)spec, c->lam, c->tmu[0], t2, t3, c->stream);
-  return launch_divide_f32(g, (float*)spec, c->lam, c->tmu[0], t2, t3, c->stream);
+    return launch_divide_f64(g, (double*)spec, c->lam, tm[0], t2, t3, c->stream);
+  return launch_divide_f32(g, (float*)spec, c->lam, tm[0], t2, t3, c->stream);
 }
 
-// Step 2 on the internal spectrum: data in *cur; on return *cur holds the result.
-aao_status spatial_solve(aao_ctx* c, void** cur, void** other) {
+// Sine-transform solve of lambda_k I + tau abar K_h (abar = 1: the exact blocks).
+aao_status dst_solve(aao_ctx* c, void** cur, void** other, bool mean) {
   const int dim = c->g.dim;
   for (int d = 0; d < dim; ++d) {
     HIPCHK(c, mode_product(c, d, *cur, *other));
     std::swap(*cur, *other);
   }
-  HIPCHK(c, run_divide(c, *cur));
+  HIPCHK(c, run_divide(c, *cur, mean));
   for (int d = dim - 1; d >= 0; --d) {
     HIPCHK(c, mode_product(c, d, *cur, *other));
     std::swap(*cur, *other);
   }
   return AAO_OK;
+}
+
+// ---------------------------------------------------------------- multigrid inner solve
+const int kCoarseSweeps = 16;  // red-black sweeps from zero on the coarsest grid
+
+double harmonic(double a, double b) { return 2.0 * a * b / (a + b); }
+
+MgGrid spec_view(const aao_ctx* c, void* p) {
+  MgGrid v;
+  v.p = p;
+  v.pitch = c->g.P1;
+  v.pstride = c->g.PS;
+  v.bstride = 2 * c->g.PS;
+  return v;
+}
+
+MgGrid compact_view(void* p, int m) {
+  MgGrid v;
+  v.p = p;
+  v.pitch = m;
+  v.pstride = (int64_t)m * m;
+  v.bstride = 2 * (int64_t)m * m;
+  return v;
+}
+
+void mg_release(aao_ctx* c);
+
+// Level hierarchy for the current coefficient and precision: m -> (m-1)/2 while m
+// is odd and >= 3; coarse faces are harmonic means of the two fine faces they span.
+aao_status mg_build(aao_ctx* c) {
+  const int want = (c->prec == AAO_FP64) ? 0 : 1;
+  if (!c->mg.empty() && c->mg_prec == want) return AAO_OK;
+  mg_release(c);
+  const Geometry& g = c->g;
+  const int nh = g.nh;
+  const size_t esz = want == 0 ? 8 : 4;
+  int m = g.m1;
+  std::vector<double> ax(g.m2 * (size_t)(g.m1 + 1), 1.0), ay((g.m2 + 1) * (size_t)g.m1, 1.0);
+  if (c->var) {
+    ax = c->host_face[0];
+    ay = c->host_face[1];
+  }
+  double h = c->h[0];
+  for (int lev = 0;; ++lev) {
+    aao_ctx::MgLevel L;
+    L.m = m;
+    const double sc = c->tau / (h * h);
+    std::vector<double> wx(ax.size()), wy(ay.size());
+    for (size_t e = 0; e < ax.size(); ++e) wx[e] = sc * ax[e];
+    for (size_t e = 0; e < ay.size(); ++e) wy[e] = sc * ay[e];
+    if (want == 0) {
+      double *px, *py;
+      TRY(upload(c, &px, wx));
+      TRY(upload(c, &py, wy));
+      L.wx = px;
+      L.wy = py;
+    } else {
+      std::vector<float> fx(wx.begin(), wx.end()), fy(wy.begin(), wy.end());
+      float *px, *py;
+      TRY(upload(c, &px, fx));
+      TRY(upload(c, &py, fy));
+      L.wx = px;
+      L.wy = py;
+    }
+    const size_t cells = (size_t)nh * 2 * (size_t)m * m;
+    char* p;
+    if (lev > 0) {
+      TRY(dalloc(c, &p, cells * esz));
+      L.E = p;
+      TRY(dalloc(c, &p, cells * esz));
+      L.R = p;
+    }
+    const bool last = (m < 3) || (m % 2 == 0);
+    if (!last) {
+      TRY(dalloc(c, &p, cells * esz));
+      L.Res = p;
+    }
+    c->mg.push_back(L);
+    if (last) break;
+    const int mc = (m - 1) / 2;
+    std::vector<double> axc((size_t)mc * (mc + 1)), ayc((size_t)(mc + 1) * mc);
+    for (int J = 0; J < mc; ++J)
+      for (int I = 0; I <= mc; ++I) {
+        const size_t row = (size_t)(2 * J + 1) * (m + 1);
+        axc[(size_t)J * (mc + 1) + I] = harmonic(ax[row + 2 * I], ax[row + 2 * I + 1]);
+      }
+    for (int J = 0; J <= mc; ++J)
+      for (int I = 0; I < mc; ++I)
+        ayc[(size_t)J * mc + I] = harmonic(ay[(size_t)(2 * J) * m + 2 * I + 1],
+                                           ay[(size_t)(2 * J + 1) * m + 2 * I + 1]);
+    ax.swap(axc);
+    ay.swap(ayc);
+    m = mc;
+    h *= 2.0;
+  }
+  c->mg_prec = want;
+  return AAO_OK;
+}
+
+void mg_release(aao_ctx* c) {
+  for (auto& L : c->mg) {
+    dfree(c, L.wx);
+    dfree(c, L.wy);
+    dfree(c, L.E);
+    dfree(c, L.R);
+    dfree(c, L.Res);
+  }
+  c->mg.clear();
+  c->mg_prec = -1;
+}
+
+template <typename T>
+aao_status vcycle(aao_ctx* c, size_t lev, const MgGrid& R, const MgGrid& E) {
+  const auto& L = c->mg[lev];
+  const int nh = c->g.nh, m = L.m;
+  hipStream_t s = c->stream;
+  auto sweep = [&](int zero_init) -> aao_status {
+    HIPCHK(c, mg_rbgs<T>(E, R, L.wx, L.wy, c->lam, m, nh, 0, zero_init, s));
+    HIPCHK(c, mg_rbgs<T>(E, R, L.wx, L.wy, c->lam, m, nh, 1, 0, s));
+    return AAO_OK;
+  };
+  if (lev + 1 == c->mg.size()) {
+    const int sweeps = (m == 1) ? 1 : kCoarseSweeps;  // one point: the first sweep is exact
+    for (int i = 0; i < sweeps; ++i) TRY(sweep(i == 0));
+    return AAO_OK;
+  }
+  TRY(sweep(1));
+  const MgGrid res = compact_view(L.Res, m);
+  HIPCHK(c, mg_residual<T>(E, R, res, L.wx, L.wy, c->lam, m, nh, s));
+  const auto& C = c->mg[lev + 1];
+  const MgGrid Rc = compact_view(C.R, C.m), Ec = compact_view(C.E, C.m);
+  HIPCHK(c, mg_restrict<T>(res, Rc, m, C.m, nh, s));
+  TRY(vcycle<T>(c, lev + 1, Rc, Ec));
+  HIPCHK(c, mg_prolong_add<T>(Ec, E, C.m, m, nh, s));
+  TRY(sweep(0));
+  return AAO_OK;
+}
+
+// e = MG(r) with c->inner_cycles V-cycles in correction form: e += V(r - B e).
+template <typename T>
+aao_status mg_solve_t(aao_ctx* c, void* r, void* e) {
+  const MgGrid R = spec_view(c, r), E = spec_view(c, e);
+  TRY(vcycle<T>(c, 0, R, E));
+  if (c->inner_cycles > 1) {
+    if (!c->specC) {
+      char* p;
+      TRY(dalloc(c, &p, c->spec_bytes));
+      HIPCHK(c, hipMemset(p, 0, c->spec_bytes));
+      c->specC = p;
+      TRY(dalloc(c, &p, c->spec_bytes));
+      HIPCHK(c, hipMemset(p, 0, c->spec_bytes));
+      c->specD = p;
+    }
+    const MgGrid Rs = spec_view(c, c->specC), D = spec_view(c, c->specD);
+    const auto& L0 = c->mg[0];
+    for (int cyc = 1; cyc < c->inner_cycles; ++cyc) {
+      HIPCHK(c, mg_residual<T>(E, R, Rs, L0.wx, L0.wy, c->lam, L0.m, c->g.nh, c->stream));
+      TRY(vcycle<T>(c, 0, Rs, D));
+      HIPCHK(c, mg_add<T>(E, D, L0.m, c->g.nh, c->stream));
+    }
+  }
+  return AAO_OK;
+}
+
+aao_status mg_solve(aao_ctx* c, void** cur, void** other) {
+  TRY(mg_build(c));
+  if (c->prec == AAO_FP64)
+    TRY(mg_solve_t<double>(c, *cur, *other));
+  else
+    TRY(mg_solve_t<float>(c, *cur, *other));
+  std::swap(*cur, *other);
+  return AAO_OK;
+}
+
+// Step 2 on the internal spectrum: data in *cur; on return *cur holds the result.
+aao_status spatial_solve(aao_ctx* c, void** cur, void** other) {
+  switch (c->inner) {
+    case AAO_INNER_DST:
+      if (c->var)
+        return fail(c, AAO_ESTATE, "the exact sine-transform solve needs a constant coefficient");
+      return dst_solve(c, cur, other, false);
+    case AAO_INNER_DST_MEAN:
+      return dst_solve(c, cur, other, true);
+    case AAO_INNER_MG:
+      return mg_solve(c, cur, other);
+    default:
+      return fail(c, AAO_ESTATE, "inner solver not available");
+  }
 }
 
 aao_status apply_pinv(aao_ctx* c, const double* x, double* y) {
@@ -319,7 +536,10 @@ aao_status apply_pinv(aao_ctx* c, const double* x, double* y) {
 
 aao_status apply_L(aao_ctx* c, const double* x, double* y) {
   ProfScope ps(c, AAO_K_APPLY_L);
-  HIPCHK(c, launch_apply_L(c->g, x, y, c->cst[0], c->cst[1], c->cst[2], c->stream));
+  if (c->var)
+    HIPCHK(c, launch_apply_L_var(c->g, x, y, c->wface[0], c->wface[1], c->wface[2], c->stream));
+  else
+    HIPCHK(c, launch_apply_L(c->g, x, y, c->cst[0], c->cst[1], c->cst[2], c->stream));
   return AAO_OK;
 }
 
@@ -473,6 +693,7 @@ aao_status aao_setup(int dim, int m1, int m2, int m3, int n, double T, double ep
       }
     }
     if ((st = upload(c, &c->tmu[d], tmu)) != AAO_OK) return bail(st);
+    if ((st = upload(c, &c->tmu_mean[d], tmu)) != AAO_OK) return bail(st);
     if ((st = upload(c, &c->S64[d], S)) != AAO_OK) return bail(st);
     if ((st = upload(c, &c->S32[d], S32)) != AAO_OK) return bail(st);
     // BF16 split of the FP32 matrix: hi = rne(s), lo = rne(s - hi)
@@ -503,6 +724,83 @@ aao_status aao_set_precision(aao_ctx* ctx, aao_precision p) {
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   ctx->prec = p;
   return ensure_spec(ctx);
+}
+
+aao_status aao_set_coefficient(aao_ctx* c, const double* ax, const double* ay,
+                               const double* az) {
+  if (!c) return AAO_EINVAL;
+  const Geometry& g = c->g;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (!ax) {  // back to a = 1
+    c->var = false;
+    for (int d = 0; d < 3; ++d) {
+      dfree(c, c->wface[d]);
+      c->wface[d] = nullptr;
+      c->host_face[d].clear();
+    }
+    c->amean = 1.0;
+  } else {
+    const double* src[3] = {ax, ay, az};
+    const int ms[3] = {g.m1, g.m2, g.m3};
+    size_t counts[3];
+    for (int d = 0; d < g.dim; ++d) {
+      if (!src[d]) return fail(c, AAO_EINVAL, "missing face array");
+      size_t cnt = 1;
+      for (int e = 0; e < g.dim; ++e) cnt *= (size_t)(ms[e] + (e == d ? 1 : 0));
+      counts[d] = cnt;
+      for (size_t i = 0; i < cnt; ++i)
+        if (!(src[d][i] > 0.0) || !isfinite(src[d][i]))
+          return fail(c, AAO_EINVAL, "coefficients must be positive and finite");
+    }
+    double sum = 0.0;
+    size_t tot = 0;
+    for (int d = 0; d < g.dim; ++d) {
+      c->host_face[d].assign(src[d], src[d] + counts[d]);
+      std::vector<double> w(counts[d]);
+      for (size_t i = 0; i < counts[d]; ++i) {
+        w[i] = c->cst[d] * src[d][i];
+        sum += src[d][i];
+      }
+      tot += counts[d];
+      dfree(c, c->wface[d]);
+      c->wface[d] = nullptr;
+      TRY(upload(c, &c->wface[d], w));
+    }
+    c->var = true;
+    c->amean = sum / (double)tot;
+  }
+  // mean-coefficient sine-transform tables: abar * tau * mu_i
+  const int Ps[3] = {g.P1, g.P2, g.P3};
+  const int ms[3] = {g.m1, g.m2, g.m3};
+  for (int d = 0; d < g.dim; ++d) {
+    std::vector<double> t(Ps[d], 0.0);
+    for (int i = 0; i < ms[d]; ++i) {
+      const double sn = sin_pi_frac(i + 1, 2LL * (ms[d] + 1));
+      t[i] = c->amean * c->tau * 4.0 / (c->h[d] * c->h[d]) * sn * sn;
+    }
+    HIPCHK(c, hipMemcpy(c->tmu_mean[d], t.data(), t.size() * sizeof(double),
+                        hipMemcpyHostToDevice));
+  }
+  mg_release(c);
+  return AAO_OK;
+}
+
+aao_status aao_set_inner(aao_ctx* c, aao_inner inner, int cycles) {
+  if (!c || cycles < 1 || cycles > 1000) return AAO_EINVAL;
+  switch (inner) {
+    case AAO_INNER_DST:
+    case AAO_INNER_DST_MEAN:
+      break;
+    case AAO_INNER_MG:
+      if (c->g.dim != 2 || c->g.m1 != c->g.m2)
+        return fail(c, AAO_EINVAL, "multigrid inner solve needs a square 2D grid");
+      break;
+    default:
+      return fail(c, AAO_EINVAL, "unknown inner solver");
+  }
+  c->inner = inner;
+  c->inner_cycles = cycles;
+  return AAO_OK;
 }
 
 aao_status aao_query(const aao_ctx* ctx, int* o) {

@@ -125,4 +125,26 @@ hipError_t launch_nancheck(const double* a, int64_t len, double* part, hipStream
 hipError_t launch_build_rhs(const double* f, const double* u0, double* y, int64_t nm, int64_t m,
                             double tau, hipStream_t s);
 
+// ---------------------------------------------------------------- multigrid (2D)
+// One level's complex grid for all blocks: element (k, plane, j, i) at
+// p + k*bstride + plane*pstride + j*pitch + i (elements of the level's type).
+struct MgGrid {
+  void* p = nullptr;
+  int pitch = 0;
+  int64_t pstride = 0, bstride = 0;
+};
+template <typename T>
+hipError_t mg_rbgs(const MgGrid& e, const MgGrid& r, const void* wx, const void* wy,
+                   const double* lam, int m, int nh, int color, int zero_init, hipStream_t s);
+template <typename T>
+hipError_t mg_residual(const MgGrid& e, const MgGrid& r, const MgGrid& res, const void* wx,
+                       const void* wy, const double* lam, int m, int nh, hipStream_t s);
+template <typename T>
+hipError_t mg_restrict(const MgGrid& f, const MgGrid& c, int mf, int mc, int nh, hipStream_t s);
+template <typename T>
+hipError_t mg_prolong_add(const MgGrid& c, const MgGrid& f, int mc, int mf, int nh,
+                          hipStream_t s);
+template <typename T>
+hipError_t mg_add(const MgGrid& x, const MgGrid& y, int m, int nh, hipStream_t s);
+
 }  // namespace aao

@@ -1,0 +1,239 @@
+// Geometric multigrid V-cycle on the shifted blocks B_k = lambda_k I + tau K_a
+// of Step 2 (Section 4, eq. (blockdiaginv)) when the coefficient varies and
+// the blocks no longer diagonalise by sine transforms; the paper applies one
+// V-cycle with one pre- and one post-smoothing step, linear interpolation and
+// its transpose (Section 4, closing paragraphs; Section 5, Example 2).
+//
+// All n/2+1 blocks are processed by every launch (one thread per grid point
+// and block).  Smoother: red-black Gauss-Seidel (red: i1 + i2 even).
+// Restriction: full weighting (transpose of bilinear interpolation / 4).
+// Prolongation: bilinear.  Coarse operators are rediscretised with harmonic
+// face averages, prepared on the host as face weights w = tau/h_l^2 * a.
+//
+// A grid view addresses element (k, plane, j, i) at
+//   p + k*bstride + plane*pstride + j*pitch + i
+// so the finest level works in place on the padded split-plane spectrum.
+#include "common.h"
+
+namespace aao {
+namespace {
+
+template <typename T> struct GView {
+  T* p;
+  int pitch;
+  int64_t pstride, bstride;
+  __device__ __forceinline__ T* at(int k, int j, int i) const {
+    return p + k * bstride + (int64_t)j * pitch + i;
+  }
+};
+
+// sum_f w_f e_nbr (complex) and the diagonal sum of w_f at (j, i)
+template <typename T>
+__device__ __forceinline__ void nbr_sum(const GView<T>& e, int k, int j, int i, int m,
+                                        const T* __restrict__ wx, const T* __restrict__ wy,
+                                        T& sr, T& si, T& d) {
+  const T wl = wx[(int64_t)j * (m + 1) + i], wr = wx[(int64_t)j * (m + 1) + i + 1];
+  const T wd = wy[(int64_t)j * m + i], wu = wy[(int64_t)(j + 1) * m + i];
+  d = wl + wr + wd + wu;
+  sr = T(0);
+  si = T(0);
+  const T* c = e.at(k, j, i);
+  const int64_t ps = e.pstride;
+  if (i > 0) { sr += wl * c[-1]; si += wl * c[ps - 1]; }
+  if (i < m - 1) { sr += wr * c[1]; si += wr * c[ps + 1]; }
+  if (j > 0) { sr += wd * c[-e.pitch]; si += wd * c[ps - e.pitch]; }
+  if (j < m - 1) { sr += wu * c[e.pitch]; si += wu * c[ps + e.pitch]; }
+}
+
+// One red or black half sweep.  zero_init: the iterate is zero on entry, so
+// the red sweep writes r / (lambda + d) on red points and 0 on black points.
+template <typename T>
+__global__ void k_rbgs(GView<T> e, GView<T> r, const T* __restrict__ wx,
+                       const T* __restrict__ wy, const double* __restrict__ lam, int m, int nh,
+                       int color, int zero_init) {
+  const int64_t total = (int64_t)nh * m * m;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(idx / ((int64_t)m * m));
+    const int rem = (int)(idx - (int64_t)k * m * m);
+    const int j = rem / m, i = rem - j * m;
+    T* ep = e.at(k, j, i);
+    if (((i + j) & 1) != color) {
+      if (zero_init) { ep[0] = T(0); ep[e.pstride] = T(0); }
+      continue;
+    }
+    T sr, si, d;
+    if (zero_init) {
+      const T wl = wx[(int64_t)j * (m + 1) + i], wr = wx[(int64_t)j * (m + 1) + i + 1];
+      const T wd = wy[(int64_t)j * m + i], wu = wy[(int64_t)(j + 1) * m + i];
+      d = wl + wr + wd + wu;
+      sr = si = T(0);
+    } else {
+      nbr_sum(e, k, j, i, m, wx, wy, sr, si, d);
+    }
+    const T* rp = r.at(k, j, i);
+    const T ar = rp[0] + sr, ai = rp[r.pstride] + si;
+    const T c = (T)lam[2 * k] + d, dd = (T)lam[2 * k + 1];
+    const T inv = T(1) / (c * c + dd * dd);
+    ep[0] = (ar * c + ai * dd) * inv;
+    ep[e.pstride] = (ai * c - ar * dd) * inv;
+  }
+}
+
+// res = r - (lambda + d) e + s
+template <typename T>
+__global__ void k_residual(GView<T> e, GView<T> r, GView<T> res, const T* __restrict__ wx,
+                           const T* __restrict__ wy, const double* __restrict__ lam, int m,
+                           int nh) {
+  const int64_t total = (int64_t)nh * m * m;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(idx / ((int64_t)m * m));
+    const int rem = (int)(idx - (int64_t)k * m * m);
+    const int j = rem / m, i = rem - j * m;
+    T sr, si, d;
+    nbr_sum(e, k, j, i, m, wx, wy, sr, si, d);
+    const T* ep = e.at(k, j, i);
+    const T* rp = r.at(k, j, i);
+    const T c = (T)lam[2 * k] + d, dd = (T)lam[2 * k + 1];
+    const T er = ep[0], ei = ep[e.pstride];
+    T* op = res.at(k, j, i);
+    op[0] = rp[0] - (c * er - dd * ei) + sr;
+    op[res.pstride] = rp[r.pstride] - (c * ei + dd * er) + si;
+  }
+}
+
+// coarse (J, I) = (1/16) [4 f(j,i) + 2 (edge neighbours) + corners], j = 2J+1, i = 2I+1
+template <typename T>
+__global__ void k_restrict(GView<T> f, GView<T> c, int mf, int mc, int nh) {
+  const int64_t total = (int64_t)nh * mc * mc;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(idx / ((int64_t)mc * mc));
+    const int rem = (int)(idx - (int64_t)k * mc * mc);
+    const int J = rem / mc, I = rem - J * mc;
+    const int j = 2 * J + 1, i = 2 * I + 1;   // interior of the fine grid: all 9 exist
+    for (int pl = 0; pl < 2; ++pl) {
+      const T* p = f.at(k, j, i) + pl * f.pstride;
+      const int P = f.pitch;
+      const T v = T(4) * p[0] + T(2) * (p[-1] + p[1] + p[-P] + p[P]) +
+                  (p[-P - 1] + p[-P + 1] + p[P - 1] + p[P + 1]);
+      c.at(k, J, I)[pl * c.pstride] = v * T(0.0625);
+    }
+  }
+}
+
+// fine += bilinear interpolation of coarse (zero beyond the coarse grid)
+template <typename T>
+__global__ void k_prolong_add(GView<T> c, GView<T> f, int mc, int mf, int nh) {
+  const int64_t total = (int64_t)nh * mf * mf;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(idx / ((int64_t)mf * mf));
+    const int rem = (int)(idx - (int64_t)k * mf * mf);
+    const int j = rem / mf, i = rem - j * mf;
+    int Ix[2], Jy[2];
+    T wxv[2], wyv[2];
+    int nx, ny;
+    if (i & 1) { Ix[0] = (i - 1) >> 1; wxv[0] = T(1); nx = 1; }
+    else { Ix[0] = (i >> 1) - 1; Ix[1] = i >> 1; wxv[0] = wxv[1] = T(0.5); nx = 2; }
+    if (j & 1) { Jy[0] = (j - 1) >> 1; wyv[0] = T(1); ny = 1; }
+    else { Jy[0] = (j >> 1) - 1; Jy[1] = j >> 1; wyv[0] = wyv[1] = T(0.5); ny = 2; }
+    T ar = T(0), ai = T(0);
+    for (int b = 0; b < ny; ++b) {
+      if (Jy[b] < 0 || Jy[b] >= mc) continue;
+      for (int a = 0; a < nx; ++a) {
+        if (Ix[a] < 0 || Ix[a] >= mc) continue;
+        const T w = wxv[a] * wyv[b];
+        const T* cp = c.at(k, Jy[b], Ix[a]);
+        ar += w * cp[0];
+        ai += w * cp[c.pstride];
+      }
+    }
+    T* fp = f.at(k, j, i);
+    fp[0] += ar;
+    fp[f.pstride] += ai;
+  }
+}
+
+// x += y on the valid region
+template <typename T>
+__global__ void k_add(GView<T> x, GView<T> y, int m, int nh) {
+  const int64_t total = (int64_t)nh * m * m;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(idx / ((int64_t)m * m));
+    const int rem = (int)(idx - (int64_t)k * m * m);
+    const int j = rem / m, i = rem - j * m;
+    T* xp = x.at(k, j, i);
+    const T* yp = y.at(k, j, i);
+    xp[0] += yp[0];
+    xp[x.pstride] += yp[y.pstride];
+  }
+}
+
+unsigned mg_grid(int64_t total) {
+  int64_t b = (total + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+template <typename T> GView<T> view(const MgGrid& g) {
+  return GView<T>{(T*)g.p, g.pitch, g.pstride, g.bstride};
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t mg_rbgs(const MgGrid& e, const MgGrid& r, const void* wx, const void* wy,
+                   const double* lam, int m, int nh, int color, int zero_init, hipStream_t s) {
+  hipLaunchKernelGGL((k_rbgs<T>), dim3(mg_grid((int64_t)nh * m * m)), dim3(256), 0, s, view<T>(e),
+                     view<T>(r), (const T*)wx, (const T*)wy, lam, m, nh, color, zero_init);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mg_residual(const MgGrid& e, const MgGrid& r, const MgGrid& res, const void* wx,
+                       const void* wy, const double* lam, int m, int nh, hipStream_t s) {
+  hipLaunchKernelGGL((k_residual<T>), dim3(mg_grid((int64_t)nh * m * m)), dim3(256), 0, s,
+                     view<T>(e), view<T>(r), view<T>(res), (const T*)wx, (const T*)wy, lam, m, nh);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mg_restrict(const MgGrid& f, const MgGrid& c, int mf, int mc, int nh, hipStream_t s) {
+  hipLaunchKernelGGL((k_restrict<T>), dim3(mg_grid((int64_t)nh * mc * mc)), dim3(256), 0, s,
+                     view<T>(f), view<T>(c), mf, mc, nh);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mg_prolong_add(const MgGrid& c, const MgGrid& f, int mc, int mf, int nh,
+                          hipStream_t s) {
+  hipLaunchKernelGGL((k_prolong_add<T>), dim3(mg_grid((int64_t)nh * mf * mf)), dim3(256), 0, s,
+                     view<T>(c), view<T>(f), mc, mf, nh);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mg_add(const MgGrid& x, const MgGrid& y, int m, int nh, hipStream_t s) {
+  hipLaunchKernelGGL((k_add<T>), dim3(mg_grid((int64_t)nh * m * m)), dim3(256), 0, s, view<T>(x),
+                     view<T>(y), m, nh);
+  return hipGetLastError();
+}
+
+#define INST(T)                                                                                 \
+  template hipError_t mg_rbgs<T>(const MgGrid&, const MgGrid&, const void*, const void*,       \
+                                 const double*, int, int, int, int, hipStream_t);              \
+  template hipError_t mg_residual<T>(const MgGrid&, const MgGrid&, const MgGrid&, const void*, \
+                                     const void*, const double*, int, int, hipStream_t);       \
+  template hipError_t mg_restrict<T>(const MgGrid&, const MgGrid&, int, int, int, hipStream_t); \
+  template hipError_t mg_prolong_add<T>(const MgGrid&, const MgGrid&, int, int, int,           \
+                                        hipStream_t);                                          \
+  template hipError_t mg_add<T>(const MgGrid&, const MgGrid&, int, int, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace aao
