@@ -104,6 +104,9 @@ aao_status aao_set_coefficient(aao_ctx *ctx, const double *ax, const double *ay,
  *                       grids with harmonic face means).  Square 2D grids only
  *                       (AAO_EINVAL otherwise); a full hierarchy needs
  *                       m1 = 2^L - 1.
+ *   AAO_INNER_CNN       one V-cycle followed by the learned correction below
+ *                       (square 2D grids; parameters must be set first,
+ *                       AAO_ESTATE otherwise; `cycles` is ignored).
  * Inexact inner solves make the preconditioner approximate: aao_solve is
  * flexible GMRES, so any inner solver is admissible. */
 typedef enum {
@@ -113,6 +116,56 @@ typedef enum {
   AAO_INNER_CNN = 3
 } aao_inner;
 aao_status aao_set_inner(aao_ctx *ctx, aao_inner inner, int cycles);
+
+/* ---- learned inner solve (AAO_INNER_CNN) ----------------------------------
+ * Extends the paper's inner solve of Step 2 (one multigrid V-cycle per block,
+ * Section 4 and Section 5, Example 2) with a small network N that corrects the
+ * V-cycle's result per frequency block k:
+ *     e1 = V(r),  rho = r - B_k e1,  s = rms(rho),  e = e1 + s N(rho/s, log a; lambda_k)
+ * N: three 3x3 convolutions 3 -> 8 -> 8 -> 2 channels with ReLU, the two hidden
+ * layers modulated by gamma = 1 + G phi, beta = H phi of the features
+ * phi = (Re lambda_k, Im lambda_k, log|lambda_k|, 1); input channels
+ * (Re rho/s, Im rho/s, log a - mean log a) with log a the log of the mean of the
+ * four faces around a node; FP32.  Parameter vector (float, host order):
+ *     W1[8][3][3][3] G1[8][4] H1[8][4] W2[8][8][3][3] G2[8][4] H2[8][4]
+ *     W3[2][8][3][3] b3[2]          (aao_cnn_param_count() floats)
+ * Square 2D grids only (the V-cycle's domain). */
+int aao_cnn_param_count(void);
+
+/* Load parameters from host memory (count must equal aao_cnn_param_count());
+ * resets the optimiser state.  AAO_EINVAL for a wrong count or non-finite values. */
+aao_status aao_cnn_set_params(aao_ctx *ctx, const float *params, int count);
+
+/* Copy the current parameters to host memory. AAO_ESTATE if none are set. */
+aao_status aao_cnn_get_params(aao_ctx *ctx, float *params, int count);
+
+/* N on B images: x device [B][3][H][W], lam host [B][2] (Re, Im of lambda per
+ * image, non-zero), y device [B][2][H][W].  For verification. */
+aao_status aao_cnn_forward(aao_ctx *ctx, const float *x, const double *lam, int B, int H, int W,
+                           float *y);
+
+/* Gradients of sum(dy * N(x)): parameter gradient to host grad[count] (may be
+ * null), input gradient to device dx [B][3][H][W] (may be null). */
+aao_status aao_cnn_backward(aao_ctx *ctx, const float *x, const double *lam, int B, int H, int W,
+                            const float *dy, float *dx, float *grad);
+
+/* Build training pairs from S space-time fields y (device [S][n][m]): for each
+ * field and kept block k, r = Step 1 of y, rho = r - B_k V(r), target
+ * delta = B_k^{-1} rho approximated by `target_cycles` V-cycles (the method's
+ * own multigrid inner solves), stored as (rho/s, delta/s) with s = rms(rho).
+ * Replaces earlier pairs; uses the context's coefficient and precision. */
+aao_status aao_cnn_make_pairs(aao_ctx *ctx, const double *y, int S, int target_cycles);
+
+/* Number of stored pairs (S * (n/2+1)). */
+aao_status aao_cnn_num_pairs(const aao_ctx *ctx, int *count);
+
+/* `steps` Adam steps (lr; beta1 0.9, beta2 0.999, 1e-8) on minibatches of
+ * `batch` pairs chosen by the caller: idx host [steps][batch] in [0, num_pairs).
+ * Loss per step (mean over the batch of ||N(x) - t||^2 / ||t||^2) to host
+ * loss[steps] (may be null).  Parameters must be set first (initial values are
+ * the caller's; drawing them is the caller's business). */
+aao_status aao_cnn_train(aao_ctx *ctx, int steps, int batch, float lr, const int *idx,
+                         float *loss);
 
 /* rhs = (tau f^1 + u0; tau f^2; ...; tau f^n) (Section 2, eq. (allatoncesystem)).
  * f: device [n][m], u0: device [m], rhs: device [n][m] (may alias f). */

@@ -11,4 +11,4 @@ differential equations", arXiv 2002.01108); each one cites the passage it
 follows.  Library primitives (matrix products, sparse LU, dense LU, QR,
 eigenvalues) serve as steps; no blocking or reordering beyond the definitions.
 """
-from . import heat  # noqa: F401
+from . import heat, mg, cnn  # noqa: F401

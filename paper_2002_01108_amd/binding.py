@@ -22,6 +22,7 @@ INNERS = {"dst": 0, "dst_mean": 1, "mg": 2, "cnn": 3}
 # exported symbols and their signatures: (restype, argtypes)
 _c_int, _c_double, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
 _pint, _pdbl = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+_pflt = ctypes.POINTER(ctypes.c_float)
 SIGNATURES = {
     "aao_setup": (_c_int, [_c_int, _c_int, _c_int, _c_int, _c_int, _c_double, _c_double,
                            ctypes.POINTER(_vp)]),
@@ -42,6 +43,14 @@ SIGNATURES = {
     "aao_query": (_c_int, [_vp, _pint]),
     "aao_set_coefficient": (_c_int, [_vp, _pdbl, _pdbl, _pdbl]),
     "aao_set_inner": (_c_int, [_vp, _c_int, _c_int]),
+    "aao_cnn_param_count": (_c_int, []),
+    "aao_cnn_set_params": (_c_int, [_vp, _pflt, _c_int]),
+    "aao_cnn_get_params": (_c_int, [_vp, _pflt, _c_int]),
+    "aao_cnn_forward": (_c_int, [_vp, _vp, _pdbl, _c_int, _c_int, _c_int, _vp]),
+    "aao_cnn_backward": (_c_int, [_vp, _vp, _pdbl, _c_int, _c_int, _c_int, _vp, _vp, _pflt]),
+    "aao_cnn_make_pairs": (_c_int, [_vp, _vp, _c_int, _c_int]),
+    "aao_cnn_num_pairs": (_c_int, [_vp, _pint]),
+    "aao_cnn_train": (_c_int, [_vp, _c_int, _c_int, ctypes.c_float, _pint, _pflt]),
     "aao_profile": (_c_int, [_vp, _c_int]),
     "aao_profile_read": (_c_int, [_vp, _pdbl, _pint]),
 }
@@ -82,6 +91,15 @@ def _ptr(t):
         raise TypeError("expected a GPU torch tensor")
     if t.dtype != torch.float64 or not t.is_contiguous():
         raise TypeError("expected a contiguous float64 tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _fptr(t):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a GPU torch tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float32 tensor")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -130,6 +148,62 @@ class Solver:
 
     def set_inner(self, inner: str = "dst", cycles: int = 1):
         self._check(self.lib.aao_set_inner(self._h, INNERS[inner], cycles))
+
+    # ------------------------------------------------------------ learned correction
+    def cnn_param_count(self) -> int:
+        return int(self.lib.aao_cnn_param_count())
+
+    def cnn_set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self.lib.aao_cnn_set_params(self._h, p.ctypes.data_as(_pflt), p.size))
+
+    def cnn_get_params(self):
+        p = np.zeros(self.cnn_param_count(), dtype=np.float32)
+        self._check(self.lib.aao_cnn_get_params(self._h, p.ctypes.data_as(_pflt), p.size))
+        return p
+
+    @staticmethod
+    def _lam(lam):
+        lam = np.asarray(lam, dtype=np.complex128).reshape(-1)
+        return np.ascontiguousarray(np.stack([lam.real, lam.imag], -1))
+
+    def cnn_forward(self, x, lam):
+        """x: GPU float32 [B][3][H][W]; lam: B complex values. Returns y [B][2][H][W]."""
+        import torch
+        B, _, H, W = x.shape
+        y = torch.empty((B, 2, H, W), dtype=torch.float32, device=x.device)
+        la = self._lam(lam)
+        self._check(self.lib.aao_cnn_forward(self._h, _fptr(x), la.ctypes.data_as(_pdbl),
+                                             B, H, W, _fptr(y)))
+        return y
+
+    def cnn_backward(self, x, lam, dy):
+        """(parameter gradient numpy float32, input gradient GPU tensor)."""
+        import torch
+        B, _, H, W = x.shape
+        dx = torch.empty_like(x)
+        g = np.zeros(self.cnn_param_count(), dtype=np.float32)
+        la = self._lam(lam)
+        self._check(self.lib.aao_cnn_backward(self._h, _fptr(x), la.ctypes.data_as(_pdbl), B, H,
+                                              W, _fptr(dy), _fptr(dx), g.ctypes.data_as(_pflt)))
+        return g, dx
+
+    def cnn_make_pairs(self, y, target_cycles: int = 12):
+        """y: GPU float64 [S][n][m] space-time fields."""
+        S = y.shape[0]
+        self._check(self.lib.aao_cnn_make_pairs(self._h, _ptr(y), S, target_cycles))
+        cnt = ctypes.c_int(0)
+        self._check(self.lib.aao_cnn_num_pairs(self._h, ctypes.byref(cnt)))
+        return cnt.value
+
+    def cnn_train(self, idx, lr: float = 3e-3):
+        """idx: int array [steps][batch] of pair indices. Returns the loss per step."""
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        steps, batch = idx.shape
+        loss = np.zeros(steps, dtype=np.float32)
+        self._check(self.lib.aao_cnn_train(self._h, steps, batch, lr, idx.ctypes.data_as(_pint),
+                                           loss.ctypes.data_as(_pflt)))
+        return loss
 
     def query(self):
         out = (ctypes.c_int * 9)()

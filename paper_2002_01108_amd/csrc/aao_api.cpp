@@ -79,6 +79,32 @@ struct aao_ctx {
   void* specC = nullptr;  // outer residual / correction for several V-cycles
   void* specD = nullptr;
 
+  // learned correction (aao_cnn_*)
+  struct Cnn {
+    bool has_params = false;
+    float* prm = nullptr;   // parameters, gradient, Adam moments
+    float* grad = nullptr;
+    float* am = nullptr;
+    float* av = nullptr;
+    int step = 0;
+    float* loga = nullptr;  // centred log-coefficient image [m1*m1]
+    float* phik = nullptr;  // features of lambda_k [nh][4]
+    // training pairs
+    int npairs = 0;
+    float *px = nullptr, *pt = nullptr, *pphi = nullptr, *ptn = nullptr;
+    // workspace for B images of HW pixels
+    size_t cap = 0;         // B*HW capacity
+    int capB = 0;
+    float *X = nullptr, *Z1 = nullptr, *H1 = nullptr, *Z2 = nullptr, *H2 = nullptr, *Y = nullptr;
+    float *T = nullptr, *DY = nullptr, *DH = nullptr, *DZ = nullptr, *E = nullptr, *Q = nullptr;
+    float *wxf = nullptr, *wyf = nullptr;  // level-0 face weights tau/h^2 a (FP32)
+    float *phi = nullptr, *gb = nullptr, *tn = nullptr, *dfilm = nullptr, *lb = nullptr;
+    float* part = nullptr;
+    size_t part_cap = 0;
+    float* ss = nullptr;    // per-block sums of squares [nh]
+    float* ss2 = nullptr;
+  } cnn;
+
   // per-class launch timing (aao_profile)
   int prof_mask = 0;
   std::vector<hipEvent_t> ev_pool;
@@ -509,6 +535,188 @@ aao_status mg_solve(aao_ctx* c, void** cur, void** other) {
   return AAO_OK;
 }
 
+// ---------------------------------------------------------------- learned correction
+// Workspace for B images of HW pixels (grown on demand).
+aao_status cnn_ws(aao_ctx* c, int B, int H, int W) {
+  auto& n = c->cnn;
+  const size_t HW = (size_t)H * W, need = (size_t)B * HW;
+  const size_t tiles = (size_t)cnn_tiles(H, W), chunks = (size_t)cnn_chunks((int)HW);
+  const size_t part_need = std::max({(size_t)kCnnC * kCnnC * 9 * B * tiles,
+                                     (size_t)2 * kCnnC * B * chunks, (size_t)2 * B * chunks,
+                                     (size_t)c->g.nh * chunks});
+  if (need > n.cap || B > n.capB) {
+    float** bufs[] = {&n.X, &n.Z1, &n.H1, &n.Z2, &n.H2, &n.Y, &n.T, &n.DY, &n.DH, &n.DZ,
+                      &n.E, &n.Q};
+    const int ch[] = {3, kCnnC, kCnnC, kCnnC, kCnnC, 2, 2, 2, kCnnC, kCnnC, 2, 2};
+    for (int i = 0; i < 12; ++i) {
+      dfree(c, *bufs[i]);
+      *bufs[i] = nullptr;
+      TRY(dalloc(c, bufs[i], ch[i] * need));
+    }
+    float** small[] = {&n.phi, &n.gb, &n.tn, &n.dfilm, &n.lb};
+    const int sz[] = {4 * B, 4 * B * kCnnC, B, 2 * kCnnC * B, B};
+    for (int i = 0; i < 5; ++i) {
+      dfree(c, *small[i]);
+      *small[i] = nullptr;
+      TRY(dalloc(c, small[i], (size_t)sz[i]));
+    }
+    n.cap = need;
+    n.capB = B;
+  }
+  if (part_need > n.part_cap) {
+    dfree(c, n.part);
+    n.part = nullptr;
+    TRY(dalloc(c, &n.part, part_need));
+    n.part_cap = part_need;
+  }
+  return AAO_OK;
+}
+
+aao_status cnn_alloc_params(aao_ctx* c) {
+  auto& n = c->cnn;
+  if (n.prm) return AAO_OK;
+  TRY(dalloc(c, &n.prm, kCnnParams));
+  TRY(dalloc(c, &n.grad, kCnnParams));
+  TRY(dalloc(c, &n.am, kCnnParams));
+  TRY(dalloc(c, &n.av, kCnnParams));
+  return AAO_OK;
+}
+
+// Forward pass of B images in n.X (features in n.phi).  train: keep z1, z2.
+aao_status cnn_forward_run(aao_ctx* c, int B, int H, int W, bool train) {
+  auto& n = c->cnn;
+  hipStream_t s = c->stream;
+  const float* gam1 = n.gb;
+  const float* bet1 = n.gb + B * kCnnC;
+  const float* gam2 = n.gb + 2 * B * kCnnC;
+  const float* bet2 = n.gb + 3 * B * kCnnC;
+  HIPCHK(c, cnn_film_params(n.prm, n.phi, n.gb, B, s));
+  HIPCHK(c, cnn_conv_fwd(1, n.X, n.prm + kCnnOffW1, gam1, bet1, nullptr, train ? n.Z1 : nullptr,
+                         n.H1, B, H, W, s));
+  HIPCHK(c, cnn_conv_fwd(2, n.H1, n.prm + kCnnOffW2, gam2, bet2, nullptr,
+                         train ? n.Z2 : nullptr, n.H2, B, H, W, s));
+  HIPCHK(c, cnn_conv_fwd(3, n.H2, n.prm + kCnnOffW3, nullptr, nullptr, n.prm + kCnnOffB3, nullptr,
+                         n.Y, B, H, W, s));
+  return AAO_OK;
+}
+
+// Backward pass from n.DY after cnn_forward_run(train = true); gradient in n.grad,
+// input gradient into dx when non-null.
+aao_status cnn_backward_run(aao_ctx* c, int B, int H, int W, float* dx) {
+  auto& n = c->cnn;
+  hipStream_t s = c->stream;
+  const float* gam1 = n.gb;
+  const float* gam2 = n.gb + 2 * B * kCnnC;
+  HIPCHK(c, cnn_bias_grad(n.DY, n.part, n.grad + kCnnOffB3, B, H, W, s));
+  HIPCHK(c, cnn_conv_wgrad(3, n.DY, n.H2, n.part, n.grad + kCnnOffW3, B, H, W, s));
+  HIPCHK(c, cnn_conv_bwd_data(3, n.DY, n.prm + kCnnOffW3, n.DH, B, H, W, s));
+  HIPCHK(c, cnn_film_bwd(n.DH, n.Z2, n.H2, gam2, n.DZ, n.part, n.dfilm, B, H, W, s));
+  HIPCHK(c, cnn_film_grad(n.dfilm, n.phi, n.grad, B, 2, s));
+  HIPCHK(c, cnn_conv_wgrad(2, n.DZ, n.H1, n.part, n.grad + kCnnOffW2, B, H, W, s));
+  HIPCHK(c, cnn_conv_bwd_data(2, n.DZ, n.prm + kCnnOffW2, n.DH, B, H, W, s));
+  HIPCHK(c, cnn_film_bwd(n.DH, n.Z1, n.H1, gam1, n.DZ, n.part, n.dfilm, B, H, W, s));
+  HIPCHK(c, cnn_film_grad(n.dfilm, n.phi, n.grad, B, 1, s));
+  HIPCHK(c, cnn_conv_wgrad(1, n.DZ, n.X, n.part, n.grad + kCnnOffW1, B, H, W, s));
+  if (dx) HIPCHK(c, cnn_conv_bwd_data(1, n.DZ, n.prm + kCnnOffW1, dx, B, H, W, s));
+  return AAO_OK;
+}
+
+// features (Re lambda, Im lambda, log|lambda|, 1) of the kept blocks, and the
+// centred node log-coefficient image
+aao_status cnn_tables(aao_ctx* c) {
+  auto& n = c->cnn;
+  const Geometry& g = c->g;
+  if (!n.phik) {
+    std::vector<float> phi(4 * (size_t)g.nh);
+    const double e1n = pow(c->eps, 1.0 / g.n);
+    for (int k = 0; k < g.nh; ++k) {
+      const double re = 1.0 - e1n * sin_pi_frac(2LL * k + g.n / 2, g.n);
+      const double im = -e1n * sin_pi_frac(2LL * k, g.n);
+      phi[4 * k] = (float)re;
+      phi[4 * k + 1] = (float)im;
+      phi[4 * k + 2] = (float)log(hypot(re, im));
+      phi[4 * k + 3] = 1.f;
+    }
+    TRY(upload(c, &n.phik, phi));
+  }
+  if (!n.loga) {
+    const int m = g.m1;
+    std::vector<double> la((size_t)m * m, 0.0);
+    double mean = 0.0;
+    if (c->var) {
+      const auto& ax = c->host_face[0];
+      const auto& ay = c->host_face[1];
+      for (int j = 0; j < m; ++j)
+        for (int i = 0; i < m; ++i) {
+          const double a = 0.25 * (ax[(size_t)j * (m + 1) + i] + ax[(size_t)j * (m + 1) + i + 1] +
+                                   ay[(size_t)j * m + i] + ay[(size_t)(j + 1) * m + i]);
+          la[(size_t)j * m + i] = log(a);
+          mean += log(a);
+        }
+      mean /= (double)m * m;
+    }
+    std::vector<float> lf(la.size());
+    for (size_t e = 0; e < la.size(); ++e) lf[e] = (float)(la[e] - mean);
+    TRY(upload(c, &n.loga, lf));
+    // level-0 face weights tau/h^2 a in FP32 for the training loss
+    const double sc = c->cst[0];
+    std::vector<float> fx((size_t)m * (m + 1)), fy((size_t)(m + 1) * m);
+    for (size_t e = 0; e < fx.size(); ++e) fx[e] = (float)(sc * (c->var ? c->host_face[0][e] : 1.0));
+    for (size_t e = 0; e < fy.size(); ++e) fy[e] = (float)(sc * (c->var ? c->host_face[1][e] : 1.0));
+    dfree(c, n.wxf);
+    dfree(c, n.wyf);
+    n.wxf = n.wyf = nullptr;
+    TRY(upload(c, &n.wxf, fx));
+    TRY(upload(c, &n.wyf, fy));
+  }
+  if (!n.ss) {
+    TRY(dalloc(c, &n.ss, (size_t)g.nh));
+    TRY(dalloc(c, &n.ss2, (size_t)g.nh));
+  }
+  return AAO_OK;
+}
+
+// Learned inner solve: e1 = V(r); rho = r - B e1; e = S_r(e1 + s N(rho/s)) with S_r
+// one red-black Gauss-Seidel sweep for B e = r.
+template <typename T>
+aao_status cnn_inner_t(aao_ctx* c, void* r, void* e) {
+  auto& n = c->cnn;
+  const Geometry& g = c->g;
+  const int m = g.m1, nh = g.nh;
+  if (!c->specC) {
+    char* p;
+    TRY(dalloc(c, &p, c->spec_bytes));
+    HIPCHK(c, hipMemset(p, 0, c->spec_bytes));
+    c->specC = p;
+  }
+  const MgGrid R = spec_view(c, r), E = spec_view(c, e), Rho = spec_view(c, c->specC);
+  TRY(vcycle<T>(c, 0, R, E));
+  const auto& L0 = c->mg[0];
+  HIPCHK(c, mg_residual<T>(E, R, Rho, L0.wx, L0.wy, c->lam, m, nh, c->stream));
+  TRY(cnn_ws(c, nh, m, m));
+  HIPCHK(c, cnn_block_sumsq<T>(Rho, m, nh, n.part, n.ss, c->stream));
+  HIPCHK(c, cnn_pack_input<T>(Rho, n.ss, n.loga, n.X, m, nh, 3, c->stream));
+  HIPCHK(c, hipMemcpyAsync(n.phi, n.phik, 4 * nh * sizeof(float), hipMemcpyDeviceToDevice,
+                           c->stream));
+  TRY(cnn_forward_run(c, nh, m, m, false));
+  HIPCHK(c, cnn_unpack_add<T>(n.Y, n.ss, E, m, nh, c->stream));
+  HIPCHK(c, mg_rbgs<T>(E, R, L0.wx, L0.wy, c->lam, m, nh, 0, 0, c->stream));
+  HIPCHK(c, mg_rbgs<T>(E, R, L0.wx, L0.wy, c->lam, m, nh, 1, 0, c->stream));
+  return AAO_OK;
+}
+
+aao_status cnn_inner(aao_ctx* c, void** cur, void** other) {
+  if (!c->cnn.has_params) return fail(c, AAO_ESTATE, "no network parameters");
+  TRY(mg_build(c));
+  TRY(cnn_tables(c));
+  if (c->prec == AAO_FP64)
+    TRY(cnn_inner_t<double>(c, *cur, *other));
+  else
+    TRY(cnn_inner_t<float>(c, *cur, *other));
+  std::swap(*cur, *other);
+  return AAO_OK;
+}
+
 // Step 2 on the internal spectrum: data in *cur; on return *cur holds the result.
 aao_status spatial_solve(aao_ctx* c, void** cur, void** other) {
   switch (c->inner) {
@@ -520,6 +728,8 @@ aao_status spatial_solve(aao_ctx* c, void** cur, void** other) {
       return dst_solve(c, cur, other, true);
     case AAO_INNER_MG:
       return mg_solve(c, cur, other);
+    case AAO_INNER_CNN:
+      return cnn_inner(c, cur, other);
     default:
       return fail(c, AAO_ESTATE, "inner solver not available");
   }
@@ -782,6 +992,8 @@ aao_status aao_set_coefficient(aao_ctx* c, const double* ax, const double* ay,
                         hipMemcpyHostToDevice));
   }
   mg_release(c);
+  dfree(c, c->cnn.loga);  // rebuilt from the new coefficient on next use
+  c->cnn.loga = nullptr;
   return AAO_OK;
 }
 
@@ -792,8 +1004,11 @@ aao_status aao_set_inner(aao_ctx* c, aao_inner inner, int cycles) {
     case AAO_INNER_DST_MEAN:
       break;
     case AAO_INNER_MG:
+    case AAO_INNER_CNN:
       if (c->g.dim != 2 || c->g.m1 != c->g.m2)
         return fail(c, AAO_EINVAL, "multigrid inner solve needs a square 2D grid");
+      if (inner == AAO_INNER_CNN && !c->cnn.has_params)
+        return fail(c, AAO_ESTATE, "set or train the network parameters first");
       break;
     default:
       return fail(c, AAO_EINVAL, "unknown inner solver");
@@ -801,6 +1016,200 @@ aao_status aao_set_inner(aao_ctx* c, aao_inner inner, int cycles) {
   c->inner = inner;
   c->inner_cycles = cycles;
   return AAO_OK;
+}
+
+int aao_cnn_param_count(void) { return kCnnParams; }
+
+aao_status aao_cnn_set_params(aao_ctx* c, const float* params, int count) {
+  if (!c || !params || count != kCnnParams) return AAO_EINVAL;
+  for (int i = 0; i < count; ++i)
+    if (!isfinite(params[i])) return fail(c, AAO_EINVAL, "parameters must be finite");
+  TRY(cnn_alloc_params(c));
+  HIPCHK(c, hipMemcpy(c->cnn.prm, params, count * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemset(c->cnn.am, 0, count * sizeof(float)));
+  HIPCHK(c, hipMemset(c->cnn.av, 0, count * sizeof(float)));
+  c->cnn.step = 0;
+  c->cnn.has_params = true;
+  return AAO_OK;
+}
+
+aao_status aao_cnn_get_params(aao_ctx* c, float* params, int count) {
+  if (!c || !params || count != kCnnParams) return AAO_EINVAL;
+  if (!c->cnn.has_params) return fail(c, AAO_ESTATE, "no network parameters");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(params, c->cnn.prm, count * sizeof(float), hipMemcpyDeviceToHost));
+  return AAO_OK;
+}
+
+static aao_status cnn_set_features(aao_ctx* c, const double* lam, int B) {
+  std::vector<float> phi(4 * (size_t)B);
+  for (int b = 0; b < B; ++b) {
+    const double re = lam[2 * b], im = lam[2 * b + 1];
+    if (!isfinite(re) || !isfinite(im) || (re == 0.0 && im == 0.0))
+      return fail(c, AAO_EINVAL, "lambda must be finite and non-zero");
+    phi[4 * b] = (float)re;
+    phi[4 * b + 1] = (float)im;
+    phi[4 * b + 2] = (float)log(hypot(re, im));
+    phi[4 * b + 3] = 1.f;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->cnn.phi, phi.data(), phi.size() * sizeof(float),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return AAO_OK;
+}
+
+aao_status aao_cnn_forward(aao_ctx* c, const float* x, const double* lam, int B, int H, int W,
+                           float* y) {
+  if (!c || !x || !lam || !y || B < 1 || H < 1 || W < 1) return AAO_EINVAL;
+  if (!c->cnn.has_params) return fail(c, AAO_ESTATE, "no network parameters");
+  TRY(cnn_ws(c, B, H, W));
+  TRY(cnn_set_features(c, lam, B));
+  auto& n = c->cnn;
+  const size_t HW = (size_t)H * W;
+  HIPCHK(c, hipMemcpyAsync(n.X, x, 3 * B * HW * sizeof(float), hipMemcpyDeviceToDevice,
+                           c->stream));
+  TRY(cnn_forward_run(c, B, H, W, false));
+  HIPCHK(c, hipMemcpyAsync(y, n.Y, 2 * B * HW * sizeof(float), hipMemcpyDeviceToDevice,
+                           c->stream));
+  return AAO_OK;
+}
+
+aao_status aao_cnn_backward(aao_ctx* c, const float* x, const double* lam, int B, int H, int W,
+                            const float* dy, float* dx, float* grad) {
+  if (!c || !x || !lam || !dy || B < 1 || H < 1 || W < 1) return AAO_EINVAL;
+  if (!c->cnn.has_params) return fail(c, AAO_ESTATE, "no network parameters");
+  TRY(cnn_ws(c, B, H, W));
+  TRY(cnn_set_features(c, lam, B));
+  auto& n = c->cnn;
+  const size_t HW = (size_t)H * W;
+  HIPCHK(c, hipMemcpyAsync(n.X, x, 3 * B * HW * sizeof(float), hipMemcpyDeviceToDevice,
+                           c->stream));
+  TRY(cnn_forward_run(c, B, H, W, true));
+  HIPCHK(c, hipMemcpyAsync(n.DY, dy, 2 * B * HW * sizeof(float), hipMemcpyDeviceToDevice,
+                           c->stream));
+  TRY(cnn_backward_run(c, B, H, W, dx));
+  if (grad) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(grad, n.grad, kCnnParams * sizeof(float), hipMemcpyDeviceToHost));
+  }
+  return AAO_OK;
+}
+
+}  // extern "C"
+
+template <typename T>
+static aao_status make_pairs_t(aao_ctx* c, const double* y, int S, int target_cycles) {
+  auto& n = c->cnn;
+  const Geometry& g = c->g;
+  const int m = g.m1, nh = g.nh;
+  const size_t HW = (size_t)m * m;
+  const int64_t nm = nm_of(c);
+  std::vector<float> phik(4 * (size_t)nh), hss(nh), tn((size_t)S * nh);
+  HIPCHK(c, hipMemcpy(phik.data(), n.phik, phik.size() * sizeof(float), hipMemcpyDeviceToHost));
+  const int saved = c->inner_cycles;
+  for (int s = 0; s < S; ++s) {
+    void* r = c->specA;
+    void* e = c->specB;
+    HIPCHK(c, run_time_fwd(c, y + (int64_t)s * nm, r));
+    const MgGrid R = spec_view(c, r), E = spec_view(c, e);
+    TRY(vcycle<T>(c, 0, R, E));
+    const auto& L0 = c->mg[0];
+    HIPCHK(c, mg_residual<T>(E, R, R, L0.wx, L0.wy, c->lam, m, nh, c->stream));
+    HIPCHK(c, cnn_block_sumsq<T>(R, m, nh, n.part, n.ss, c->stream));
+    HIPCHK(c, cnn_pack_input<T>(R, n.ss, nullptr, n.px + (size_t)s * nh * 2 * HW, m, nh, 2,
+                                c->stream));
+    c->inner_cycles = target_cycles;
+    const aao_status st = mg_solve_t<T>(c, r, e);
+    c->inner_cycles = saved;
+    TRY(st);
+    HIPCHK(c, cnn_pack_input<T>(E, n.ss, nullptr, n.pt + (size_t)s * nh * 2 * HW, m, nh, 2,
+                                c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(hss.data(), n.ss, nh * sizeof(float), hipMemcpyDeviceToHost));
+    // loss normaliser ||rho/s||^2: 2 HW by the choice of s (1 for an all-zero block)
+    for (int k = 0; k < nh; ++k) tn[(size_t)s * nh + k] = hss[k] > 0.f ? (float)(2 * HW) : 1.f;
+  }
+  std::vector<float> pphi(4 * (size_t)S * nh);
+  for (int s = 0; s < S; ++s)
+    std::copy(phik.begin(), phik.end(), pphi.begin() + (size_t)s * 4 * nh);
+  HIPCHK(c, hipMemcpy(n.pphi, pphi.data(), pphi.size() * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(n.ptn, tn.data(), tn.size() * sizeof(float), hipMemcpyHostToDevice));
+  n.npairs = S * nh;
+  return AAO_OK;
+}
+
+extern "C" {
+
+aao_status aao_cnn_make_pairs(aao_ctx* c, const double* y, int S, int target_cycles) {
+  if (!c || !y || S < 1 || target_cycles < 1 || target_cycles > 1000) return AAO_EINVAL;
+  if (c->g.dim != 2 || c->g.m1 != c->g.m2)
+    return fail(c, AAO_EINVAL, "training pairs need a square 2D grid");
+  auto& n = c->cnn;
+  TRY(mg_build(c));
+  TRY(cnn_tables(c));
+  const int m = c->g.m1, nh = c->g.nh;
+  TRY(cnn_ws(c, 1, m, m));
+  const size_t P = (size_t)S * nh, HW = (size_t)m * m;
+  dfree(c, n.px);
+  dfree(c, n.pt);
+  dfree(c, n.pphi);
+  dfree(c, n.ptn);
+  n.px = n.pt = n.pphi = n.ptn = nullptr;
+  n.npairs = 0;
+  TRY(dalloc(c, &n.px, P * 2 * HW));
+  TRY(dalloc(c, &n.pt, P * 2 * HW));
+  TRY(dalloc(c, &n.pphi, P * 4));
+  TRY(dalloc(c, &n.ptn, P));
+  if (c->prec == AAO_FP64) return make_pairs_t<double>(c, y, S, target_cycles);
+  return make_pairs_t<float>(c, y, S, target_cycles);
+}
+
+aao_status aao_cnn_num_pairs(const aao_ctx* c, int* count) {
+  if (!c || !count) return AAO_EINVAL;
+  *count = c->cnn.npairs;
+  return AAO_OK;
+}
+
+aao_status aao_cnn_train(aao_ctx* c, int steps, int batch, float lr, const int* idx,
+                         float* loss) {
+  if (!c || !idx || steps < 1 || batch < 1 || !(lr > 0.f)) return AAO_EINVAL;
+  auto& n = c->cnn;
+  if (!n.has_params) return fail(c, AAO_ESTATE, "no network parameters");
+  if (n.npairs < 1) return fail(c, AAO_ESTATE, "no training pairs");
+  for (size_t i = 0; i < (size_t)steps * batch; ++i)
+    if (idx[i] < 0 || idx[i] >= n.npairs) return fail(c, AAO_EINVAL, "pair index out of range");
+  const int m = c->g.m1;
+  TRY(cnn_ws(c, batch, m, m));
+  TRY(cnn_tables(c));
+  int* didx = nullptr;
+  float* dloss = nullptr;
+  TRY(dalloc(c, &didx, (size_t)steps * batch));
+  TRY(dalloc(c, &dloss, (size_t)steps));
+  aao_status st = AAO_OK;
+  hipError_t he = hipMemcpy(didx, idx, (size_t)steps * batch * sizeof(int), hipMemcpyHostToDevice);
+  if (he != hipSuccess) st = hip_fail(c, he, "hipMemcpy");
+  for (int it = 0; it < steps && st == AAO_OK; ++it) {
+    he = cnn_gather(n.px, n.pphi, n.ptn, n.loga, didx + (size_t)it * batch, n.X, n.T, n.phi,
+                    n.tn, batch, m * m, c->stream);
+    if (he != hipSuccess) { st = hip_fail(c, he, "gather"); break; }
+    if ((st = cnn_forward_run(c, batch, m, m, true)) != AAO_OK) break;
+    he = cnn_resid_loss(n.Y, n.T, n.tn, n.phi, n.wxf, n.wyf, n.E, n.Q, n.DH, n.DZ, n.DY, n.part,
+                        n.lb, dloss + it, batch, m, m, c->stream);
+    if (he != hipSuccess) { st = hip_fail(c, he, "loss"); break; }
+    if ((st = cnn_backward_run(c, batch, m, m, nullptr)) != AAO_OK) break;
+    n.step += 1;
+    he = cnn_adam(n.prm, n.grad, n.am, n.av, kCnnParams, lr, n.step, c->stream);
+    if (he != hipSuccess) { st = hip_fail(c, he, "adam"); break; }
+  }
+  if (st == AAO_OK && loss) {
+    he = hipMemcpyAsync(loss, dloss, steps * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) st = hip_fail(c, he, "loss copy");
+  }
+  (void)hipStreamSynchronize(c->stream);
+  dfree(c, didx);
+  dfree(c, dloss);
+  return st;
 }
 
 aao_status aao_query(const aao_ctx* ctx, int* o) {

@@ -147,4 +147,53 @@ hipError_t mg_prolong_add(const MgGrid& c, const MgGrid& f, int mc, int mf, int 
 template <typename T>
 hipError_t mg_add(const MgGrid& x, const MgGrid& y, int m, int nh, hipStream_t s);
 
+// ---------------------------------------------------------------- learned correction
+// Parameter vector: W1[C][3][3][3] G1[C][4] H1[C][4] W2[C][C][3][3] G2[C][4] H2[C][4]
+// W3[2][C][3][3] b3[2] (float).
+constexpr int kCnnC = 8;
+constexpr int kCnnOffW1 = 0;
+constexpr int kCnnOffG1 = kCnnOffW1 + kCnnC * 3 * 9;
+constexpr int kCnnOffH1 = kCnnOffG1 + kCnnC * 4;
+constexpr int kCnnOffW2 = kCnnOffH1 + kCnnC * 4;
+constexpr int kCnnOffG2 = kCnnOffW2 + kCnnC * kCnnC * 9;
+constexpr int kCnnOffH2 = kCnnOffG2 + kCnnC * 4;
+constexpr int kCnnOffW3 = kCnnOffH2 + kCnnC * 4;
+constexpr int kCnnOffB3 = kCnnOffW3 + 2 * kCnnC * 9;
+constexpr int kCnnParams = kCnnOffB3 + 2;
+
+int cnn_chunks(int HW);
+int cnn_tiles(int H, int W);
+hipError_t cnn_conv_fwd(int layer, const float* x, const float* w, const float* gam,
+                        const float* bet, const float* bias, float* z, float* out, int B, int H,
+                        int W, hipStream_t s);
+hipError_t cnn_conv_bwd_data(int layer, const float* dz, const float* w, float* dx, int B, int H,
+                             int W, hipStream_t s);
+hipError_t cnn_conv_wgrad(int layer, const float* dz, const float* x, float* part, float* grad,
+                          int B, int H, int W, hipStream_t s);
+hipError_t cnn_film_bwd(const float* dh, const float* z, const float* h, const float* gam,
+                        float* dz, float* part, float* dfilm, int B, int H, int W,
+                        hipStream_t s);
+hipError_t cnn_bias_grad(const float* dy, float* part, float* grad, int B, int H, int W,
+                         hipStream_t s);
+hipError_t cnn_film_params(const float* prm, const float* phi, float* gb, int B, hipStream_t s);
+hipError_t cnn_film_grad(const float* dfilm, const float* phi, float* grad, int B, int layer,
+                         hipStream_t s);
+hipError_t cnn_resid_loss(const float* y, const float* rho, const float* rn, const float* phi,
+                          const float* wx, const float* wy, float* E, float* Q, float* G,
+                          float* Hb, float* dy, float* part, float* lb, float* out, int B, int H,
+                          int W, hipStream_t s);
+hipError_t cnn_adam(float* prm, const float* g, float* m, float* v, int np, float lr, int step,
+                    hipStream_t s);
+hipError_t cnn_gather(const float* px, const float* pphi, const float* ptn, const float* loga,
+                      const int* idx, float* X, float* R, float* phi, float* tn, int B, int HW,
+                      hipStream_t s);
+template <typename T>
+hipError_t cnn_block_sumsq(const MgGrid& v, int m, int nh, float* part, float* out, hipStream_t s);
+template <typename T>
+hipError_t cnn_pack_input(const MgGrid& v, const float* ss, const float* loga, float* X, int m,
+                          int nh, int nch, hipStream_t s);
+template <typename T>
+hipError_t cnn_unpack_add(const float* Y, const float* ss, const MgGrid& v, int m, int nh,
+                          hipStream_t s);
+
 }  // namespace aao
