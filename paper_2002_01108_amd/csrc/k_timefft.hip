@@ -5,8 +5,9 @@
 // conj(ztilde^k) (conjugate symmetry at the end of Section 4).
 //
 // The transform runs along time, the slowest axis of the [n][m] array.  A
-// block owns CW pairs of adjacent spatial points of one x-row and all n time
-// levels: consecutive lanes read consecutive addresses of each time row.  Two
+// block owns 2 CW consecutive spatial points of one x-row (paired as c and
+// c + CW) and all n time levels: consecutive lanes read consecutive addresses
+// of each time row, every load and store instruction is contiguous.  Two
 // real sequences a, b travel as one complex sequence a + i b ("two for one"),
 // untangled after the forward transform and re-tangled before the inverse.
 // The FFT is a Stockham autosort sequence of radix-16 (last: smaller) passes;
@@ -183,10 +184,12 @@ __global__ __launch_bounds__(THREADS) void k_time_fwd(
   b /= nseg;
   const int i2 = b % P2;
   const int i3 = b / P2;
-  const int i1a = sg * 2 * CW + 2 * c;
+  // the two real columns of complex column c are i1a and i1a + CW, so every
+  // load and store instruction of a wave covers contiguous addresses
+  const int i1a = sg * 2 * CW + c, i1b = i1a + CW;
   const bool rowvalid = (i2 < m2) && (i3 < m3);
   const bool va = rowvalid && i1a < m1;
-  const bool vb = rowvalid && i1a + 1 < m1;
+  const bool vb = rowvalid && i1b < m1;
   const int64_t m = (int64_t)m1 * m2 * m3;
   const int64_t xoff = rowvalid ? ((int64_t)i3 * m2 + i2) * m1 + i1a : 0;
   const int64_t poff = ((int64_t)i3 * P2 + i2) * P1;
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(THREADS) void k_time_fwd(
     const int j = t + r * TPC;
     const double* xp = x + (int64_t)j * m + xoff;
     const T a = va ? (T)xp[0] : T(0);
-    const T bb = vb ? (T)xp[1] : T(0);
+    const T bb = vb ? (T)xp[CW] : T(0);
     const T gj = gam[j];
     v[r] = {a * gj, bb * gj};
   }
@@ -217,9 +220,9 @@ __global__ __launch_bounds__(THREADS) void k_time_fwd(
       pr[i1a] = va ? (ck.x + cn.x) * half : T(0);
       pi[i1a] = va ? (ck.y - cn.y) * half : T(0);
     }
-    if (i1a + 1 < P1) {
-      pr[i1a + 1] = vb ? (ck.y + cn.y) * half : T(0);
-      pi[i1a + 1] = vb ? (cn.x - ck.x) * half : T(0);
+    if (i1b < P1) {
+      pr[i1b] = vb ? (ck.y + cn.y) * half : T(0);
+      pi[i1b] = vb ? (cn.x - ck.x) * half : T(0);
     }
   }
 }
@@ -240,9 +243,9 @@ __global__ __launch_bounds__(THREADS) void k_time_inv(
   b /= nseg;
   const int i2 = b % m2;
   const int i3 = b / m2;
-  const int i1a = sg * 2 * CW + 2 * c;
+  const int i1a = sg * 2 * CW + c, i1b = i1a + CW;   // as in the forward kernel
   const bool va = i1a < m1;
-  const bool vb = i1a + 1 < m1;
+  const bool vb = i1b < m1;
   const int64_t m = (int64_t)m1 * m2 * m3;
   const int64_t zoff = ((int64_t)i3 * m2 + i2) * m1 + i1a;
   const int64_t poff = ((int64_t)i3 * P2 + i2) * P1;
@@ -257,10 +260,10 @@ __global__ __launch_bounds__(THREADS) void k_time_inv(
     const T* pr = spec + (int64_t)kk * 2 * PS + poff;
     const T* pi = pr + PS;
     const T ar = va ? pr[i1a] : T(0);
-    const T br = vb ? pr[i1a + 1] : T(0);
+    const T br = vb ? pr[i1b] : T(0);
     const bool realblk = (kk == 0) || (kk == N / 2);
     const T ai = (va && !realblk) ? pi[i1a] : T(0);
-    const T bi = (vb && !realblk) ? pi[i1a + 1] : T(0);
+    const T bi = (vb && !realblk) ? pi[i1b] : T(0);
     v[r] = upper ? C{ar + bi, br - ai} : C{ar - bi, ai + br};
   }
   dft<T, R1, -1>(v);
@@ -268,7 +271,7 @@ __global__ __launch_bounds__(THREADS) void k_time_inv(
     const T g = ginv[j];
     double* zp = z + (int64_t)j * m + zoff;
     if (va) zp[0] = (double)(val.x * g);
-    if (vb) zp[1] = (double)(val.y * g);
+    if (vb) zp[CW] = (double)(val.y * g);
   };
   if constexpr (R1 == N) {
 #pragma unroll
