@@ -51,11 +51,17 @@ def parse():
     return ap.parse_args()
 
 
-def dst_flops_per_launch(w):
-    """Algorithmic flops of one DST-I mode product: every real plane of the
-    n/2+1 kept frequency blocks (2 planes each) gets an m_d x m_d product along
-    one axis: 2 * (n/2+1) * (m / m_d) * m_d^2 * 2 = 4 (n/2+1) m m_d."""
-    return 4.0 * (w.n // 2 + 1) * w.m * w.m1
+def dst_flops_per_launch(w, prec):
+    """Algorithmic flops of one DST-I mode product over the n/2+1 kept
+    frequency blocks (2 real planes each), m/m_d vectors of length m_d per plane.
+    2D/3D with an FP64/FP32 preconditioner use the even/odd fold: two
+    h x ceil(m_d/2) and h x floor(m_d/2) products per vector (h = ceil(m_d/2)),
+    2 h m_d flops, so 4 (n/2+1) m h per launch.  Otherwise the dense product,
+    2 m_d^2 flops per vector: 4 (n/2+1) m m_d."""
+    nh = w.n // 2 + 1
+    if w.dim >= 2 and prec in ("fp64", "fp32"):
+        return 4.0 * nh * w.m * ((w.m1 + 1) // 2)
+    return 4.0 * nh * w.m * w.m1
 
 
 def time_solver(s, fd, u0d, tol, restart, steps, warmup, prof_classes):
@@ -172,12 +178,13 @@ def main():
     value = dof / t_step
 
     dst_ms, dst_n = prof["dst"]
-    flops = dst_flops_per_launch(w)
+    flops = dst_flops_per_launch(w, prec)
     avg_s = dst_ms / 1e3 / max(dst_n, 1)
     peak = {"fp64": PEAKS["fp64_TFs"], "fp32": PEAKS["fp32_TFs"],
             "bf16x3": PEAKS["bf16_TFs"]}[prec]
     achieved = flops / avg_s / 1e12 if dst_n else None
-    roofline = {"kernel": f"dst_gemm_{prec} (one DST-I mode product)", "bound": "mfma",
+    kname = "dst_fold" if w.dim >= 2 and prec in ("fp64", "fp32") else "dst_gemm"
+    roofline = {"kernel": f"{kname}_{prec} (one DST-I mode product)", "bound": "mfma",
                 "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak if achieved else None, "traffic": None,
                 "avg_launch_us": avg_s * 1e6, "launches": dst_n,

@@ -37,6 +37,11 @@ struct aao_ctx {
   float* S32[3] = {nullptr, nullptr, nullptr};
   uint16_t* Shi[3] = {nullptr, nullptr, nullptr};  // BF16 hi/lo split of S32 (bit patterns)
   uint16_t* Slo[3] = {nullptr, nullptr, nullptr};
+  // folded DST-I tables S[0:h, 0::2] and S[0:h, 1::2], (P_d/2) x (P_d/2)
+  double* Foe64[3] = {nullptr, nullptr, nullptr};
+  double* Foo64[3] = {nullptr, nullptr, nullptr};
+  float* Foe32[3] = {nullptr, nullptr, nullptr};
+  float* Foo32[3] = {nullptr, nullptr, nullptr};
 
   // spectrum workspace (ping-pong), sized for the current precision
   void* specA = nullptr;
@@ -199,7 +204,14 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 double sin_pi_frac(long long p, long long q) {
   long long r = p % (2 * q);
   if (r < 0) r += 2 * q;
-  return sin(kPi * (double)r / (double)q);
+  double sg = 1.0;
+  if (r >= q) {  // sin(x + pi) = -sin(x)
+    r -= q;
+    sg = -1.0;
+  }
+  if (r == 0) return 0.0;
+  if (2 * r > q) r = q - r;  // sin(pi - x) = sin(x): first-quadrant argument
+  return sg * sin(kPi * (double)r / (double)q);
 }
 
 // round-to-nearest-even FP32 -> BF16 (bit pattern) and back
@@ -279,7 +291,56 @@ hipError_t run_time_inv(aao_ctx* c, const void* spec, double* z) {
   return launch_time_inv_f32(c->g, (const float*)spec, z, c->ginv32, c->tw32, c->stream);
 }
 
-// One mode product along axis d (0 = x, 1 = y, 2 = z) from `in` to `out`.
+// Folded product (2D/3D, FP64 or FP32 preconditioner) along axis d; with
+// `divtm` the shifted divide by lambda_k + sum_d divtm_d runs in its epilogue.
+bool use_fold(const aao_ctx* c) { return c->g.dim >= 2 && c->prec != AAO_BF16X3; }
+
+hipError_t fold_product(aao_ctx* c, int d, const void* in, void* out,
+                        double* const* divtm) {
+  ProfScope ps(c, AAO_K_DST);
+  const Geometry& g = c->g;
+  FoldArgs f;
+  f.PS = g.PS;
+  f.nk = g.nh;
+  f.axis = d;
+  f.m1 = g.m1;
+  f.m2 = g.m2;
+  f.m3 = g.m3;
+  f.P1 = g.P1;
+  f.P2 = g.P2;
+  f.OS = 0;
+  f.nout = 1;
+  if (d == 0) {  // rows (z, y) of length P1
+    f.m = g.m1;
+    f.Hp = g.P1 / 2;
+    f.R = g.P1;
+    f.ndt = g.P2 * g.P3 / 64;
+  } else if (d == 1) {  // each z slab: P2 rows of P1
+    f.m = g.m2;
+    f.Hp = g.P2 / 2;
+    f.R = g.P1;
+    f.OS = (int64_t)g.P2 * g.P1;
+    f.nout = g.P3;
+    f.ndt = g.P1 / 64;
+  } else {  // P3 rows of P2*P1
+    f.m = g.m3;
+    f.Hp = g.P3 / 2;
+    f.R = (int64_t)g.P2 * g.P1;
+    f.ndt = g.P2 * g.P1 / 64;
+  }
+  const double* lam = divtm ? c->lam : nullptr;
+  const double* t1 = divtm ? divtm[0] : nullptr;
+  const double* t2 = divtm && g.dim >= 2 ? divtm[1] : nullptr;
+  const double* t3 = divtm && g.dim >= 3 ? divtm[2] : nullptr;
+  if (c->prec == AAO_FP64)
+    return launch_dst_fold<double>((const double*)in, (double*)out, c->Foe64[d], c->Foo64[d], f,
+                                   d != 0, lam, t1, t2, t3, c->stream);
+  return launch_dst_fold<float>((const float*)in, (float*)out, c->Foe32[d], c->Foo32[d], f,
+                                d != 0, lam, t1, t2, t3, c->stream);
+}
+
+// One mode product along axis d (0 = x, 1 = y, 2 = z) from `in` to `out`
+// as a dense batched GEMM (1D, and the BF16x3 preconditioner).
 hipError_t mode_product(aao_ctx* c, int d, const void* in, void* out) {
   ProfScope ps(c, AAO_K_DST);
   const Geometry& g = c->g;
@@ -349,8 +410,21 @@ hipError_t run_divide(aao_ctx* c, void* spec, bool mean) {
 }
 
 // Sine-transform solve of lambda_k I + tau abar K_h (abar = 1: the exact blocks).
+// S_d is symmetric and orthogonal, so the backward sweep reuses the same tables.
 aao_status dst_solve(aao_ctx* c, void** cur, void** other, bool mean) {
   const int dim = c->g.dim;
+  if (use_fold(c)) {
+    double* const* tm = mean ? c->tmu_mean : c->tmu;
+    for (int d = 0; d < dim; ++d) {
+      HIPCHK(c, fold_product(c, d, *cur, *other, d == dim - 1 ? tm : nullptr));
+      std::swap(*cur, *other);
+    }
+    for (int d = dim - 1; d >= 0; --d) {
+      HIPCHK(c, fold_product(c, d, *cur, *other, nullptr));
+      std::swap(*cur, *other);
+    }
+    return AAO_OK;
+  }
   for (int d = 0; d < dim; ++d) {
     HIPCHK(c, mode_product(c, d, *cur, *other));
     std::swap(*cur, *other);
@@ -914,6 +988,22 @@ aao_status aao_setup(int dim, int m1, int m2, int m3, int n, double T, double ep
     }
     if ((st = upload(c, &c->Shi[d], hi)) != AAO_OK) return bail(st);
     if ((st = upload(c, &c->Slo[d], lo)) != AAO_OK) return bail(st);
+    // folded tables: rows r < ceil(m/2) of the even and odd columns
+    const int Hp = P / 2, hh = (md + 1) / 2;
+    std::vector<double> fe((size_t)Hp * Hp, 0.0), fo((size_t)Hp * Hp, 0.0);
+    std::vector<float> fe32((size_t)Hp * Hp, 0.0f), fo32((size_t)Hp * Hp, 0.0f);
+    for (int r = 0; r < hh; ++r)
+      for (int t = 0; t < Hp; ++t) {
+        const size_t e = (size_t)r * Hp + t;
+        if (2 * t < md) fe[e] = S[(size_t)r * P + 2 * t];
+        if (2 * t + 1 < md) fo[e] = S[(size_t)r * P + 2 * t + 1];
+        fe32[e] = (float)fe[e];
+        fo32[e] = (float)fo[e];
+      }
+    if ((st = upload(c, &c->Foe64[d], fe)) != AAO_OK) return bail(st);
+    if ((st = upload(c, &c->Foo64[d], fo)) != AAO_OK) return bail(st);
+    if ((st = upload(c, &c->Foe32[d], fe32)) != AAO_OK) return bail(st);
+    if ((st = upload(c, &c->Foo32[d], fo32)) != AAO_OK) return bail(st);
   }
   if ((st = ensure_spec(c)) != AAO_OK) return bail(st);
   if ((st = ensure_small(c, 256)) != AAO_OK) return bail(st);

@@ -80,6 +80,29 @@ hipError_t launch_gemm_bf16x3_right(const float* A, int64_t sA, int lda, const u
                                     int64_t sC, int ldc, int M, int N, int K, int batch,
                                     hipStream_t s);
 
+// Folded DST-I mode product over both planes of every frequency block (2D/3D).
+// LEFT (axis y or z): each (k, plane, o) slab is a P x R-strided matrix whose
+// rows run along the axis; RIGHT (axis x): each plane is P2*P3 rows of R = P1.
+struct FoldArgs {
+  int m;          // axis length m_d
+  int Hp;         // P_d / 2 (multiple of 32): size of the folded tables
+  int64_t R;      // stride between consecutive axis rows (LEFT) / data rows (RIGHT)
+  int64_t PS;     // plane size
+  int64_t OS;     // stride between outer slabs (LEFT axis y); 0 otherwise
+  int nout;       // outer slabs per plane (P3 for LEFT axis y, else 1)
+  int ndt;        // 64-wide data tiles per slab
+  int nk;         // frequency blocks
+  int axis;       // 0 = x, 1 = y, 2 = z
+  int m1, m2, m3, P1, P2;
+};
+// out = S_d applied along `axis`; Soe = S[0:h, 0::2], Soo = S[0:h, 1::2] (Hp x Hp,
+// zero padded).  With lam != nullptr the result is divided by
+// lambda_k + tmu1[i1] + tmu2[i2] + tmu3[i3] (tmu2/tmu3 may be null).
+template <typename T>
+hipError_t launch_dst_fold(const T* in, T* out, const T* Soe, const T* Soo, const FoldArgs& f,
+                           bool left, const double* lam, const double* tmu1, const double* tmu2,
+                           const double* tmu3, hipStream_t s);
+
 // Shifted divide in the doubly transformed domain:
 // spec[k] <- spec[k] / (lambda_k + sum_d tmu_d[i_d]), complex, pads set to 0.
 hipError_t launch_divide_f64(const Geometry& g, double* spec, const double* lam,

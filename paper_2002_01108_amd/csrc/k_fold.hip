@@ -1,0 +1,295 @@
+// Folded DST-I mode product on the matrix cores (constant-coefficient Step 2,
+// Section 4, eq. (blockdiaginv)).  S_{ij} = sqrt(2/(m+1)) sin((i+1)(j+1) pi/(m+1))
+// obeys S_{m-1-r, c} = (-1)^c S_{r, c} (0-based), so with
+//   O_r = sum_{c even} S_{r c} x_c,   E_r = sum_{c odd} S_{r c} x_c   (r < h = ceil(m/2))
+// the product is y_r = O_r + E_r and y_{m-1-r} = O_r - E_r: two half-size dense
+// products (S_oe = S[0:h, 0::2], S_oo = S[0:h, 1::2], zero-padded to Hp x Hp,
+// Hp = P/2) instead of one, half the matrix-core work.
+//
+// Both planes (Re, Im) of a frequency block go through the same block, so the
+// S fragments are reused twice and the shifted divide of the last forward
+// product (by lambda_k + sum_d tau mu_{i_d}) runs in the epilogue.
+//   LEFT  (axis y or z): out[k][pl][o][a][c] = sum_b S[a][b] in[k][pl][o][b][c]
+//   RIGHT (axis x):      out[k][pl][rho][a]  = sum_b in[k][pl][rho][b] S[b][a]
+// Block tile: FR half-indices r x 64 columns (LEFT) or 64 rows x FR r (RIGHT),
+// FR = 64 when P_d/2 allows it (else 32), K slice 8, LDS double buffer, 4 waves
+// of 16 columns (rows) each.  Padding positions are written as zero.
+#include "common.h"
+
+namespace aao {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mf;
+template <> struct Mf<double> {
+  typedef d4 V;
+  static __device__ __forceinline__ V mfma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+template <> struct Mf<float> {
+  typedef f4 V;
+  static __device__ __forceinline__ V mfma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
+
+constexpr int FBK = 8;     // K slice (half indices t)
+constexpr int FC = 64;     // column (LEFT) / row (RIGHT) tile
+constexpr int PD = 1;      // LDS padding
+
+template <typename T, int FR, bool LEFT, bool DIVIDE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_dst_fold(const T* __restrict__ in, T* __restrict__ out,
+                                                  const T* __restrict__ Soe,
+                                                  const T* __restrict__ Soo, FoldArgs f,
+                                                  const double* __restrict__ lam,
+                                                  const double* __restrict__ tmu1,
+                                                  const double* __restrict__ tmu2,
+                                                  const double* __restrict__ tmu3) {
+  using V = typename Mf<T>::V;
+  constexpr int NS = FR / 16;            // 16-wide sub-tiles per wave
+  constexpr int SPT = 2 * FR * FBK / 256;  // S elements per thread per K slice
+  constexpr int STR = FBK / SPT;         // threads per S row
+  // LEFT: As = S tiles [mat][t][r], Bs = data [pl][par][t][c]
+  // RIGHT: As = data [pl][par][t][row], Bs = S^T tiles [mat][t][r]
+  __shared__ T Sd[2][2][2][FBK][FC + PD];   // [buf][pl][par][t][c or row]
+  __shared__ T Ss[2][2][FBK][FR + PD];      // [buf][mat][t][r]
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  // XCD-aware logical block index (workgroup b runs on XCD b % 8)
+  int bid;
+  {
+    const int nblk = gridDim.x, q = nblk / 8, rr = nblk % 8;
+    const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+    bid = xcd * q + (xcd < rr ? xcd : rr) + slot;
+  }
+  // tiles: half-index tile fastest (the data tile is reused across it), then data tile, then batch
+  const int nrt = f.Hp / FR;
+  const int rt = bid % nrt;
+  bid /= nrt;
+  const int dt = bid % f.ndt;   // LEFT: column tile; RIGHT: row tile
+  bid /= f.ndt;
+  const int o = bid % f.nout;   // LEFT: outer index; RIGHT: unused (nout = 1)
+  const int k = bid / f.nout;
+  const int r0 = rt * FR, d0 = dt * FC;
+  const int64_t kbase = (int64_t)k * 2 * f.PS + (int64_t)o * f.OS;
+
+  // global -> register staging
+  T rs[SPT], rd[8];
+  // S loads: 2 mats x FR r x FBK t, SPT consecutive t per thread
+  const int s_mat = tid >> 7, s_r = (tid & 127) / STR, s_t = ((tid & 127) % STR) * SPT;
+  const T* Sm = s_mat ? Soo : Soe;
+  // data loads: 2 planes x 2*FBK input indices x FC = 2048, 8 per thread
+  const int d_pl = tid >> 7;
+  int d_a, d_c;   // LEFT: input row (0..15) and 8 columns; RIGHT: data row (0..63) and 8 inputs
+  if (LEFT) { d_a = (tid & 127) >> 3; d_c = (tid & 7) * 8; }
+  else { d_a = (tid & 127) >> 1; d_c = (tid & 1) * 8; }
+
+  auto fetch = [&](int t0) {
+#pragma unroll
+    for (int e = 0; e < SPT; ++e) rs[e] = Sm[(int64_t)(r0 + s_r) * f.Hp + t0 + s_t + e];
+    const T* src = in + kbase + (int64_t)d_pl * f.PS;
+    if (LEFT) {
+      const T* p = src + (int64_t)(2 * t0 + d_a) * f.R + d0 + d_c;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rd[e] = p[e];
+    } else {
+      const T* p = src + (int64_t)(d0 + d_a) * f.R + 2 * t0 + d_c;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rd[e] = p[e];
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < SPT; ++e) Ss[buf][s_mat][s_t + e][s_r] = rs[e];
+    if (LEFT) {
+      // input row 2t+par -> (par, t)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) Sd[buf][d_pl][d_a & 1][d_a >> 1][d_c + e] = rd[e];
+    } else {
+      // input column 2t+par of data row d_a
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int cidx = d_c + e;
+        Sd[buf][d_pl][cidx & 1][cidx >> 1][d_a] = rd[e];
+      }
+    }
+  };
+
+  V acc[2][2][NS];   // [plane][O/E][sub-tile]
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc[a][b][s] = V{0, 0, 0, 0};
+
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  const int nk = f.Hp / FBK;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) fetch((kt + 1) * FBK);
+#pragma unroll
+    for (int ks = 0; ks < FBK / 4; ++ks) {
+      const int kk = ks * 4 + lk;
+      if (LEFT) {
+        T a[2][NS], b[2][2];   // a[mat][i], b[pl][par]
+#pragma unroll
+        for (int mat = 0; mat < 2; ++mat)
+#pragma unroll
+          for (int i = 0; i < NS; ++i) a[mat][i] = Ss[buf][mat][kk][i * 16 + lr];
+#pragma unroll
+        for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+          for (int par = 0; par < 2; ++par) b[pl][par] = Sd[buf][pl][par][kk][w * 16 + lr];
+#pragma unroll
+        for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+          for (int oe = 0; oe < 2; ++oe)
+#pragma unroll
+            for (int i = 0; i < NS; ++i)
+              acc[pl][oe][i] = Mf<T>::mfma(a[oe][i], b[pl][oe], acc[pl][oe][i]);
+      } else {
+        T a[2][2], b[2][NS];   // a[pl][par], b[mat][j]
+#pragma unroll
+        for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+          for (int par = 0; par < 2; ++par) a[pl][par] = Sd[buf][pl][par][kk][w * 16 + lr];
+#pragma unroll
+        for (int mat = 0; mat < 2; ++mat)
+#pragma unroll
+          for (int j = 0; j < NS; ++j) b[mat][j] = Ss[buf][mat][kk][j * 16 + lr];
+#pragma unroll
+        for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+          for (int oe = 0; oe < 2; ++oe)
+#pragma unroll
+            for (int j = 0; j < NS; ++j)
+              acc[pl][oe][j] = Mf<T>::mfma(a[pl][oe], b[oe][j], acc[pl][oe][j]);
+      }
+    }
+    if (kt + 1 < nk) stash(buf ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: y_r = O + E, y_{m-1-r} = O - E, optional complex divide, zero padding
+  const int m = f.m, h = (m + 1) / 2;
+  T* ob = out + kbase;
+  const double lre = DIVIDE ? lam[2 * k] : 0.0, lim = DIVIDE ? lam[2 * k + 1] : 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int r, dpos;   // half index and data position (column for LEFT, row for RIGHT)
+      if (LEFT) { r = r0 + s * 16 + Mf<T>::row(lk, v); dpos = d0 + w * 16 + lr; }
+      else { r = r0 + s * 16 + lr; dpos = d0 + w * 16 + Mf<T>::row(lk, v); }
+      if (r >= h) continue;
+      // position of the data index in the full grid (for validity and the divide)
+      int i1, i2, i3;
+      if (LEFT) {
+        if (f.axis == 1) { i1 = dpos; i2 = 0; i3 = o; }          // y-mode: column = x, outer = z
+        else { i1 = dpos % f.P1; i2 = dpos / f.P1; i3 = 0; }    // z-mode: column = (y, x)
+      } else {
+        i1 = 0; i2 = dpos % f.P2; i3 = dpos / f.P2;              // x-mode: row = (z, y)
+      }
+      const bool dvalid = i1 < f.m1 && i2 < f.m2 && i3 < f.m3;
+      const T ore = acc[0][0][s][v], ere = acc[0][1][s][v];
+      const T oim = acc[1][0][s][v], eim = acc[1][1][s][v];
+      const int a_top = r, a_bot = m - 1 - r;
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const int a = half ? a_bot : a_top;
+        if (half && a_bot <= a_top) break;
+        T vr = half ? ore - ere : ore + ere;
+        T vi = half ? oim - eim : oim + eim;
+        if (!dvalid) {
+          vr = T(0);
+          vi = T(0);
+        } else if (DIVIDE) {
+          int j1 = i1, j2 = i2, j3 = i3;
+          if (LEFT) { if (f.axis == 1) j2 = a; else j3 = a; }
+          else j1 = a;
+          const double c = lre + tmu1[j1] + (tmu2 ? tmu2[j2] : 0.0) + (tmu3 ? tmu3[j3] : 0.0);
+          const T cc = (T)c, dd = (T)lim;
+          const T inv = T(1) / (cc * cc + dd * dd);
+          const T nr = (vr * cc + vi * dd) * inv;
+          const T ni = (vi * cc - vr * dd) * inv;
+          vr = nr;
+          vi = ni;
+        }
+        int64_t off;
+        if (LEFT) off = (int64_t)a * f.R + dpos;
+        else off = (int64_t)dpos * f.R + a;
+        ob[off] = vr;
+        ob[off + f.PS] = vi;
+      }
+    }
+  }
+  // output indices m .. 2 Hp - 1 along the axis are padding: zero them for this data tile
+  if (rt == 0) {
+    const int np = 2 * f.Hp - m, cnt = 2 * np * FC;
+    for (int e = tid; e < cnt; e += 256) {
+      const int pl = e / (np * FC), rem = e % (np * FC);
+      int64_t off;
+      if (LEFT) off = (int64_t)(m + rem / FC) * f.R + d0 + rem % FC;
+      else off = (int64_t)(d0 + rem / np) * f.R + m + rem % np;
+      ob[off + pl * f.PS] = T(0);
+    }
+  }
+}
+
+template <typename T, int FR>
+hipError_t launch_fold_fr(const T* in, T* out, const T* Soe, const T* Soo, const FoldArgs& f,
+                          bool left, const double* lam, const double* tmu1, const double* tmu2,
+                          const double* tmu3, hipStream_t s) {
+  const int64_t nblk = (int64_t)(f.Hp / FR) * f.ndt * f.nout * f.nk;
+  if (nblk > 0x7fffffff || nblk < 1) return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)nblk), blk(256);
+  const bool div = lam != nullptr;
+  if (left) {
+    if (div)
+      hipLaunchKernelGGL((k_dst_fold<T, FR, true, true>), grid, blk, 0, s, in, out, Soe, Soo, f,
+                         lam, tmu1, tmu2, tmu3);
+    else
+      hipLaunchKernelGGL((k_dst_fold<T, FR, true, false>), grid, blk, 0, s, in, out, Soe, Soo, f,
+                         lam, tmu1, tmu2, tmu3);
+  } else {
+    if (div)
+      hipLaunchKernelGGL((k_dst_fold<T, FR, false, true>), grid, blk, 0, s, in, out, Soe, Soo, f,
+                         lam, tmu1, tmu2, tmu3);
+    else
+      hipLaunchKernelGGL((k_dst_fold<T, FR, false, false>), grid, blk, 0, s, in, out, Soe, Soo,
+                         f, lam, tmu1, tmu2, tmu3);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_dst_fold(const T* in, T* out, const T* Soe, const T* Soo, const FoldArgs& f,
+                           bool left, const double* lam, const double* tmu1, const double* tmu2,
+                           const double* tmu3, hipStream_t s) {
+  if (f.Hp % 32 || f.Hp < 32 || f.ndt < 1 || f.nout < 1 || f.nk < 1) return hipErrorInvalidValue;
+  if (f.m < 1 || f.m > 2 * f.Hp) return hipErrorInvalidValue;
+  if (f.Hp % 64 == 0)
+    return launch_fold_fr<T, 64>(in, out, Soe, Soo, f, left, lam, tmu1, tmu2, tmu3, s);
+  return launch_fold_fr<T, 32>(in, out, Soe, Soo, f, left, lam, tmu1, tmu2, tmu3, s);
+}
+
+template hipError_t launch_dst_fold<double>(const double*, double*, const double*, const double*,
+                                            const FoldArgs&, bool, const double*, const double*,
+                                            const double*, const double*, hipStream_t);
+template hipError_t launch_dst_fold<float>(const float*, float*, const float*, const float*,
+                                           const FoldArgs&, bool, const double*, const double*,
+                                           const double*, const double*, hipStream_t);
+
+}  // namespace aao
