@@ -295,13 +295,16 @@ hipError_t run_time_inv(aao_ctx* c, const void* spec, double* z) {
 // `divtm` the shifted divide by lambda_k + sum_d divtm_d runs in its epilogue.
 bool use_fold(const aao_ctx* c) { return c->g.dim >= 2 && c->prec != AAO_BF16X3; }
 
-hipError_t fold_product(aao_ctx* c, int d, const void* in, void* out,
-                        double* const* divtm) {
+hipError_t fold_product(aao_ctx* c, int d, const void* in, void* out, double* const* divtm,
+                        bool real_ends) {
   ProfScope ps(c, AAO_K_DST);
   const Geometry& g = c->g;
   FoldArgs f;
   f.PS = g.PS;
-  f.nk = g.nh;
+  // real_ends: the k = 0 and k = n/2 blocks are real (spectrum of real data),
+  // so their two real planes share one block and the grid covers n/2 blocks
+  f.packed = real_ends ? 1 : 0;
+  f.nk = real_ends ? g.nh - 1 : g.nh;
   f.axis = d;
   f.m1 = g.m1;
   f.m2 = g.m2;
@@ -411,16 +414,18 @@ hipError_t run_divide(aao_ctx* c, void* spec, bool mean) {
 
 // Sine-transform solve of lambda_k I + tau abar K_h (abar = 1: the exact blocks).
 // S_d is symmetric and orthogonal, so the backward sweep reuses the same tables.
-aao_status dst_solve(aao_ctx* c, void** cur, void** other, bool mean) {
+// real_ends: the spectrum comes from real time data (imaginary parts of the
+// k = 0 and k = n/2 blocks are zero and are neither read nor written).
+aao_status dst_solve(aao_ctx* c, void** cur, void** other, bool mean, bool real_ends) {
   const int dim = c->g.dim;
   if (use_fold(c)) {
     double* const* tm = mean ? c->tmu_mean : c->tmu;
     for (int d = 0; d < dim; ++d) {
-      HIPCHK(c, fold_product(c, d, *cur, *other, d == dim - 1 ? tm : nullptr));
+      HIPCHK(c, fold_product(c, d, *cur, *other, d == dim - 1 ? tm : nullptr, real_ends));
       std::swap(*cur, *other);
     }
     for (int d = dim - 1; d >= 0; --d) {
-      HIPCHK(c, fold_product(c, d, *cur, *other, nullptr));
+      HIPCHK(c, fold_product(c, d, *cur, *other, nullptr, real_ends));
       std::swap(*cur, *other);
     }
     return AAO_OK;
@@ -792,14 +797,15 @@ aao_status cnn_inner(aao_ctx* c, void** cur, void** other) {
 }
 
 // Step 2 on the internal spectrum: data in *cur; on return *cur holds the result.
-aao_status spatial_solve(aao_ctx* c, void** cur, void** other) {
+// real_ends as for dst_solve.
+aao_status spatial_solve(aao_ctx* c, void** cur, void** other, bool real_ends) {
   switch (c->inner) {
     case AAO_INNER_DST:
       if (c->var)
         return fail(c, AAO_ESTATE, "the exact sine-transform solve needs a constant coefficient");
-      return dst_solve(c, cur, other, false);
+      return dst_solve(c, cur, other, false, real_ends);
     case AAO_INNER_DST_MEAN:
-      return dst_solve(c, cur, other, true);
+      return dst_solve(c, cur, other, true, real_ends);
     case AAO_INNER_MG:
       return mg_solve(c, cur, other);
     case AAO_INNER_CNN:
@@ -813,7 +819,7 @@ aao_status apply_pinv(aao_ctx* c, const double* x, double* y) {
   void* cur = c->specA;
   void* other = c->specB;
   HIPCHK(c, run_time_fwd(c, x, cur));
-  TRY(spatial_solve(c, &cur, &other));
+  TRY(spatial_solve(c, &cur, &other, true));
   HIPCHK(c, run_time_inv(c, cur, y));
   return AAO_OK;
 }
@@ -1381,7 +1387,7 @@ aao_status aao_step2(aao_ctx* ctx, const double* yt, double* zt) {
   void* cur = ctx->specA;
   void* other = ctx->specB;
   HIPCHK(ctx, launch_ext_to_spec(ctx->g, yt, cur, ctx->prec != AAO_FP64, ctx->stream));
-  TRY(spatial_solve(ctx, &cur, &other));
+  TRY(spatial_solve(ctx, &cur, &other, false));
   HIPCHK(ctx, launch_spec_to_ext(ctx->g, cur, ctx->prec != AAO_FP64, zt, ctx->stream));
   return AAO_OK;
 }

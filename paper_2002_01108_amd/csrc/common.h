@@ -25,6 +25,17 @@ template <typename T> __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T>
   return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 
+// Hardware places workgroup b on XCD b % 8, and each XCD has its own L2.  This
+// maps the hardware index to a logical tile index so that every XCD gets one
+// contiguous run of logical tiles (neighbouring tiles share cache lines and
+// operands in one L2).  A bijection for any nblk: the first nblk % 8 XCDs get
+// one extra tile.
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+  const int q = nblk / 8, r = nblk % 8;
+  const int xcd = bid % 8, slot = bid / 8;
+  return xcd * q + (xcd < r ? xcd : r) + slot;
+}
+
 // ---------------------------------------------------------------- geometry
 // Spatial grid: m1 (x, fastest), m2 (y), m3 (z); unused dims are 1.
 // Spectrum planes are padded: P_d = round_up(m_d, 64) for used dims, 1 otherwise.
@@ -91,7 +102,8 @@ struct FoldArgs {
   int64_t OS;     // stride between outer slabs (LEFT axis y); 0 otherwise
   int nout;       // outer slabs per plane (P3 for LEFT axis y, else 1)
   int ndt;        // 64-wide data tiles per slab
-  int nk;         // frequency blocks
+  int nk;         // frequency blocks processed (n/2 + 1, or n/2 when packed)
+  int packed;     // 1: block 0 pairs the real planes of frequencies 0 and n/2
   int axis;       // 0 = x, 1 = y, 2 = z
   int m1, m2, m3, P1, P2;
 };

@@ -58,15 +58,8 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm(const T* __restrict__ A, int6
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  // XCD-aware order: hardware workgroup b runs on XCD b % 8; give each XCD a
-  // contiguous run of logical tiles so that tiles sharing an A row-block (tn
-  // fastest) hit the same L2
-  int bid;
-  {
-    const int nblk = gridDim.x, q = nblk / 8, r = nblk % 8;
-    const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
-    bid = xcd * q + (xcd < r ? xcd : r) + slot;
-  }
+  // tiles sharing an A row-block (tn fastest) stay in one XCD's L2
+  int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int tn = bid % tiles_n;
   bid /= tiles_n;
   const int tm = bid % tiles_m;

@@ -62,13 +62,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
 
-  // XCD-aware logical block index (workgroup b runs on XCD b % 8)
-  int bid;
-  {
-    const int nblk = gridDim.x, q = nblk / 8, rr = nblk % 8;
-    const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
-    bid = xcd * q + (xcd < rr ? xcd : rr) + slot;
-  }
+  int bid = xcd_remap(blockIdx.x, gridDim.x);
   // tiles: half-index tile fastest (the data tile is reused across it), then data tile, then batch
   const int nrt = f.Hp / FR;
   const int rt = bid % nrt;
@@ -78,7 +72,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int o = bid % f.nout;   // LEFT: outer index; RIGHT: unused (nout = 1)
   const int k = bid / f.nout;
   const int r0 = rt * FR, d0 = dt * FC;
-  const int64_t kbase = (int64_t)k * 2 * f.PS + (int64_t)o * f.OS;
+  // plane bases: block k holds (Re, Im) of frequency k; with f.packed, block 0
+  // holds the real planes of frequencies 0 and n/2 (both blocks are real when
+  // the time data is real) and block k >= 1 frequency k
+  const bool real_pair = f.packed && k == 0;
+  const int64_t base0 = (int64_t)k * 2 * f.PS + (int64_t)o * f.OS;
+  const int64_t base1 = real_pair ? (int64_t)f.nk * 2 * f.PS + (int64_t)o * f.OS : base0 + f.PS;
 
   // global -> register staging
   T rs[SPT], rd[8];
@@ -94,7 +93,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   auto fetch = [&](int t0) {
 #pragma unroll
     for (int e = 0; e < SPT; ++e) rs[e] = Sm[(int64_t)(r0 + s_r) * f.Hp + t0 + s_t + e];
-    const T* src = in + kbase + (int64_t)d_pl * f.PS;
+    const T* src = in + (d_pl ? base1 : base0);
     if (LEFT) {
       const T* p = src + (int64_t)(2 * t0 + d_a) * f.R + d0 + d_c;
 #pragma unroll
@@ -182,8 +181,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 
   // epilogue: y_r = O + E, y_{m-1-r} = O - E, optional complex divide, zero padding
   const int m = f.m, h = (m + 1) / 2;
-  T* ob = out + kbase;
+  T* ob0 = out + base0;
+  T* ob1 = out + base1;
   const double lre = DIVIDE ? lam[2 * k] : 0.0, lim = DIVIDE ? lam[2 * k + 1] : 0.0;
+  // real pair: lambda_0 and lambda_{n/2} are real
+  const double lre1 = (DIVIDE && real_pair) ? lam[2 * f.nk] : 0.0;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
 #pragma unroll
@@ -217,19 +219,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
           int j1 = i1, j2 = i2, j3 = i3;
           if (LEFT) { if (f.axis == 1) j2 = a; else j3 = a; }
           else j1 = a;
-          const double c = lre + tmu1[j1] + (tmu2 ? tmu2[j2] : 0.0) + (tmu3 ? tmu3[j3] : 0.0);
-          const T cc = (T)c, dd = (T)lim;
-          const T inv = T(1) / (cc * cc + dd * dd);
-          const T nr = (vr * cc + vi * dd) * inv;
-          const T ni = (vi * cc - vr * dd) * inv;
-          vr = nr;
-          vi = ni;
+          const double mu = tmu1[j1] + (tmu2 ? tmu2[j2] : 0.0) + (tmu3 ? tmu3[j3] : 0.0);
+          if (real_pair) {
+            vr = vr / (T)(lre + mu);
+            vi = vi / (T)(lre1 + mu);
+          } else {
+            const T cc = (T)(lre + mu), dd = (T)lim;
+            const T inv = T(1) / (cc * cc + dd * dd);
+            const T nr = (vr * cc + vi * dd) * inv;
+            const T ni = (vi * cc - vr * dd) * inv;
+            vr = nr;
+            vi = ni;
+          }
         }
         int64_t off;
         if (LEFT) off = (int64_t)a * f.R + dpos;
         else off = (int64_t)dpos * f.R + a;
-        ob[off] = vr;
-        ob[off + f.PS] = vi;
+        ob0[off] = vr;
+        ob1[off] = vi;
       }
     }
   }
@@ -241,7 +248,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       int64_t off;
       if (LEFT) off = (int64_t)(m + rem / FC) * f.R + d0 + rem % FC;
       else off = (int64_t)(d0 + rem / np) * f.R + m + rem % np;
-      ob[off + pl * f.PS] = T(0);
+      (pl ? ob1 : ob0)[off] = T(0);
     }
   }
 }

@@ -17,17 +17,6 @@ namespace {
 constexpr int TX = 64;       // points along x per block
 constexpr int TY = 4;        // rows along y per block
 constexpr int TCHUNK = 8;    // time levels per block
-constexpr int NXCD = 8;
-
-__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
-  // Hardware places workgroup b on XCD b % 8.  Give each XCD a contiguous run
-  // of logical tiles.  Valid for any nblk: the first (nblk % 8) XCDs get one
-  // extra tile.
-  const int q = nblk / NXCD, r = nblk % NXCD;
-  const int xcd = bid % NXCD, slot = bid / NXCD;
-  const int start = xcd * q + (xcd < r ? xcd : r);
-  return start + slot;
-}
 
 template <int DIM, bool VAR>
 __global__ __launch_bounds__(TX * TY) void k_apply_L(

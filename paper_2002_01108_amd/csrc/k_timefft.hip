@@ -23,12 +23,12 @@
 namespace aao {
 namespace {
 
-constexpr int THREADS = 256;
-
-template <int N> struct Cfg {
+// TH threads per block: 256, or 512 for long transforms of HBM-resident data
+// (wider column strips per block keep more of each DRAM page per request).
+template <int N, int TH> struct Cfg {
   static constexpr int R1 = N < 16 ? N : 16;
-  static constexpr int TPC = N / R1;         // threads per column
-  static constexpr int CW = THREADS / TPC;   // complex columns per block
+  static constexpr int TPC = N / R1;     // threads per column
+  static constexpr int CW = TH / TPC;    // complex columns per block
 };
 
 // multiply by exp(SIGN * 2 pi i * e / 16) for a compile-time-known e in [0,16)
@@ -102,11 +102,11 @@ __device__ __forceinline__ cplx<T> twiddle(const cplx<T>* __restrict__ tw, int e
 
 // One Stockham pass (accumulated length NS -> NS*R) from the LDS tile.
 // Results go back to LDS unless FINAL, in which case sink(index, value) gets them.
-template <typename T, int N, int SIGN, int NS, bool FINAL, typename Sink>
+template <typename T, int N, int TH, int SIGN, int NS, bool FINAL, typename Sink>
 __device__ __forceinline__ void lds_pass(cplx<T>* lds, const cplx<T>* __restrict__ tw, int t,
                                          int c, Sink&& sink) {
   using C = cplx<T>;
-  constexpr int TPC = Cfg<N>::TPC, CW = Cfg<N>::CW;
+  constexpr int TPC = Cfg<N, TH>::TPC, CW = Cfg<N, TH>::CW;
   constexpr int R = (N / NS) < 16 ? (N / NS) : 16;
   constexpr int NB = N / R;
   constexpr int PER = NB / TPC;
@@ -139,26 +139,26 @@ __device__ __forceinline__ void lds_pass(cplx<T>* lds, const cplx<T>* __restrict
 }
 
 // All passes after the first, writing back to LDS, ending with a barrier.
-template <typename T, int N, int SIGN, int NS>
+template <typename T, int N, int TH, int SIGN, int NS>
 __device__ __forceinline__ void lds_passes_all(cplx<T>* lds, const cplx<T>* __restrict__ tw, int t,
                                                int c) {
   if constexpr (NS < N) {
-    lds_pass<T, N, SIGN, NS, false>(lds, tw, t, c, [](int, cplx<T>) {});
+    lds_pass<T, N, TH, SIGN, NS, false>(lds, tw, t, c, [](int, cplx<T>) {});
     constexpr int R = (N / NS) < 16 ? (N / NS) : 16;
-    lds_passes_all<T, N, SIGN, NS * R>(lds, tw, t, c);
+    lds_passes_all<T, N, TH, SIGN, NS * R>(lds, tw, t, c);
   } else {
     __syncthreads();
   }
 }
 
 // Passes after the first except the last (which the caller runs as FINAL).
-template <typename T, int N, int SIGN, int NS>
+template <typename T, int N, int TH, int SIGN, int NS>
 __device__ __forceinline__ void lds_passes_but_last(cplx<T>* lds, const cplx<T>* __restrict__ tw,
                                                     int t, int c) {
   constexpr int R = (N / NS) < 16 ? (N / NS) : 16;
   if constexpr (NS * R < N) {
-    lds_pass<T, N, SIGN, NS, false>(lds, tw, t, c, [](int, cplx<T>) {});
-    lds_passes_but_last<T, N, SIGN, NS * R>(lds, tw, t, c);
+    lds_pass<T, N, TH, SIGN, NS, false>(lds, tw, t, c, [](int, cplx<T>) {});
+    lds_passes_but_last<T, N, TH, SIGN, NS * R>(lds, tw, t, c);
   }
 }
 
@@ -169,17 +169,18 @@ template <int N, int NS> struct LastNS {
 template <int N> struct LastNS<N, N> { static constexpr int value = N; };
 
 // ---------------------------------------------------------------- forward (Step 1)
-template <typename T, int N>
-__global__ __launch_bounds__(THREADS) void k_time_fwd(
+template <typename T, int N, int TH>
+__global__ __launch_bounds__(TH) void k_time_fwd(
     const double* __restrict__ x, T* __restrict__ spec, const T* __restrict__ gam,
     const cplx<T>* __restrict__ tw, int m1, int m2, int m3, int P1, int P2, int64_t PS,
     int nseg) {
   using C = cplx<T>;
-  constexpr int R1 = Cfg<N>::R1, TPC = Cfg<N>::TPC, CW = Cfg<N>::CW;
+  constexpr int R1 = Cfg<N, TH>::R1, TPC = Cfg<N, TH>::TPC, CW = Cfg<N, TH>::CW;
   __shared__ C lds[N * CW];
   const int tid = threadIdx.x;
   const int c = tid % CW, t = tid / CW;
-  int b = blockIdx.x;
+  // neighbouring column segments share cache lines: keep them in one XCD
+  int b = xcd_remap(blockIdx.x, gridDim.x);
   const int sg = b % nseg;
   b /= nseg;
   const int i2 = b % P2;
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(THREADS) void k_time_fwd(
   dft<T, R1, +1>(v);
 #pragma unroll
   for (int r = 0; r < R1; ++r) lds[(t * R1 + r) * CW + c] = v[r];
-  lds_passes_all<T, N, +1, R1>(lds, tw, t, c);
+  lds_passes_all<T, N, TH, +1, R1>(lds, tw, t, c);
 
   // untangle: A(k) = (C(k) + conj C(n-k))/2, B(k) = (C(k) - conj C(n-k))/(2i)
   for (int k = t; k <= N / 2; k += TPC) {
@@ -228,17 +229,18 @@ __global__ __launch_bounds__(THREADS) void k_time_fwd(
 }
 
 // ---------------------------------------------------------------- inverse (Step 3)
-template <typename T, int N>
-__global__ __launch_bounds__(THREADS) void k_time_inv(
+template <typename T, int N, int TH>
+__global__ __launch_bounds__(TH) void k_time_inv(
     const T* __restrict__ spec, double* __restrict__ z, const T* __restrict__ ginv,
     const cplx<T>* __restrict__ tw, int m1, int m2, int m3, int P1, int P2, int64_t PS,
     int nseg) {
   using C = cplx<T>;
-  constexpr int R1 = Cfg<N>::R1, TPC = Cfg<N>::TPC, CW = Cfg<N>::CW;
+  constexpr int R1 = Cfg<N, TH>::R1, TPC = Cfg<N, TH>::TPC, CW = Cfg<N, TH>::CW;
   __shared__ C lds[(R1 == N) ? 1 : N * CW];
   const int tid = threadIdx.x;
   const int c = tid % CW, t = tid / CW;
-  int b = blockIdx.x;
+  // neighbouring column segments share cache lines: keep them in one XCD
+  int b = xcd_remap(blockIdx.x, gridDim.x);
   const int sg = b % nseg;
   b /= nseg;
   const int i2 = b % m2;
@@ -279,32 +281,39 @@ __global__ __launch_bounds__(THREADS) void k_time_inv(
   } else {
 #pragma unroll
     for (int r = 0; r < R1; ++r) lds[(t * R1 + r) * CW + c] = v[r];
-    lds_passes_but_last<T, N, -1, R1>(lds, tw, t, c);
+    lds_passes_but_last<T, N, TH, -1, R1>(lds, tw, t, c);
     constexpr int NSL = LastNS<N, R1>::value;
-    lds_pass<T, N, -1, NSL, true>(lds, tw, t, c, store);
+    lds_pass<T, N, TH, -1, NSL, true>(lds, tw, t, c, store);
   }
 }
 
-template <typename T, int N>
+template <typename T, int N, int TH>
 hipError_t launch_fwd_n(const Geometry& g, const double* x, T* spec, const T* gam,
                         const cplx<T>* tw, hipStream_t s) {
-  constexpr int CW = Cfg<N>::CW;
+  constexpr int CW = Cfg<N, TH>::CW;
   const int nseg = (g.P1 + 2 * CW - 1) / (2 * CW);
   const int64_t nblk = (int64_t)nseg * g.P2 * g.P3;
-  hipLaunchKernelGGL((k_time_fwd<T, N>), dim3((unsigned)nblk), dim3(THREADS), 0, s, x, spec, gam,
+  hipLaunchKernelGGL((k_time_fwd<T, N, TH>), dim3((unsigned)nblk), dim3(TH), 0, s, x, spec, gam,
                      tw, g.m1, g.m2, g.m3, g.P1, g.P2, g.PS, nseg);
   return hipGetLastError();
 }
 
-template <typename T, int N>
+template <typename T, int N, int TH>
 hipError_t launch_inv_n(const Geometry& g, const T* spec, double* z, const T* ginv,
                         const cplx<T>* tw, hipStream_t s) {
-  constexpr int CW = Cfg<N>::CW;
+  constexpr int CW = Cfg<N, TH>::CW;
   const int nseg = (g.m1 + 2 * CW - 1) / (2 * CW);
   const int64_t nblk = (int64_t)nseg * g.m2 * g.m3;
-  hipLaunchKernelGGL((k_time_inv<T, N>), dim3((unsigned)nblk), dim3(THREADS), 0, s, spec, z,
+  hipLaunchKernelGGL((k_time_inv<T, N, TH>), dim3((unsigned)nblk), dim3(TH), 0, s, spec, z,
                      ginv, tw, g.m1, g.m2, g.m3, g.P1, g.P2, g.PS, nseg);
   return hipGetLastError();
+}
+
+// 512-thread blocks for n >= 128 once the [n][m] array (FP64) exceeds the
+// 256 MiB last-level cache; below that the 256-thread shape is as fast or faster.
+template <int N> struct WideTH { static constexpr int value = N >= 128 ? 512 : 256; };
+template <int N> bool wide_strips(const Geometry& g) {
+  return N >= 128 && (int64_t)N * g.m * 8 > (int64_t(256) << 20);
 }
 
 #define AAO_FOR_EACH_N(X) \
@@ -316,7 +325,9 @@ hipError_t dispatch_fwd(const Geometry& g, const double* x, T* spec, const T* ga
   const cplx<T>* twc = reinterpret_cast<const cplx<T>*>(tw);
   switch (g.n) {
 #define CASE(NN) \
-  case NN: return launch_fwd_n<T, NN>(g, x, spec, gam, twc, s);
+  case NN:                                                                          \
+    return wide_strips<NN>(g) ? launch_fwd_n<T, NN, WideTH<NN>::value>(g, x, spec, gam, twc, s) \
+                              : launch_fwd_n<T, NN, 256>(g, x, spec, gam, twc, s);
     AAO_FOR_EACH_N(CASE)
 #undef CASE
   }
@@ -329,7 +340,9 @@ hipError_t dispatch_inv(const Geometry& g, const T* spec, double* z, const T* gi
   const cplx<T>* twc = reinterpret_cast<const cplx<T>*>(tw);
   switch (g.n) {
 #define CASE(NN) \
-  case NN: return launch_inv_n<T, NN>(g, spec, z, ginv, twc, s);
+  case NN:                                                                         \
+    return wide_strips<NN>(g) ? launch_inv_n<T, NN, WideTH<NN>::value>(g, spec, z, ginv, twc, s) \
+                              : launch_inv_n<T, NN, 256>(g, spec, z, ginv, twc, s);
     AAO_FOR_EACH_N(CASE)
 #undef CASE
   }
