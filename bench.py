@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=64)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the plain-copy kernel used to calibrate PMC byte counters")
     return ap.parse_args()
 
 
@@ -65,6 +67,9 @@ def dst_flops_per_launch(w, prec):
 
 
 def time_solver(s, fd, u0d, tol, restart, steps, warmup, prof_classes):
+    """Warm-up, then `steps` timed solves with no event profiling attached;
+    then (if prof_classes) the same number of solves with HIP-event timing of
+    those kernel classes on the solver's stream, for per-launch averages."""
     import torch
     rhs = s.new()
     u = s.new()
@@ -77,15 +82,92 @@ def time_solver(s, fd, u0d, tol, restart, steps, warmup, prof_classes):
     for _ in range(warmup):
         info = step()
     torch.cuda.synchronize()
-    s.profile(prof_classes)
     t0 = time.perf_counter()
     for _ in range(steps):
         info = step()
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = s.profile_read()
-    s.profile(None)
-    return dt / steps, info, prof, u, rhs
+    dt = (time.perf_counter() - t0) / steps
+    prof = None
+    if prof_classes:
+        s.profile(prof_classes)
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        prof = s.profile_read()
+        s.profile(None)
+    return dt, info, prof, u, rhs
+
+
+def class_bytes(w, prec):
+    """Algorithmic HBM bytes of one launch of each bandwidth-bound kernel class
+    (valid points only; padding and cache re-reads are not counted).
+    apply_L reads v and writes L v; time_fwd reads the real [n][m] FP64 array
+    and writes n/2+1 complex blocks; time_inv reads n/2-1 complex and 2 real
+    blocks and writes [n][m] FP64; one DST product reads and writes the
+    spectrum (n/2-1 complex and 2 real blocks when packed)."""
+    sT = 8 if prec == "fp64" else 4
+    nm = w.n * w.m
+    spec = (w.n // 2 + 1) * 2 * w.m * sT
+    spec_real_ends = w.n * w.m * sT     # (n/2 - 1) complex + 2 real blocks
+    # the folded product (2D/3D, FP64/FP32) skips the zero imaginary planes of
+    # the two real blocks; the dense product moves every plane
+    folded = w.dim >= 2 and prec in ("fp64", "fp32")
+    return {"apply_L": 2 * nm * 8,
+            "time_fwd": nm * 8 + spec,
+            "time_inv": spec_real_ends + nm * 8,
+            "dst": 2 * (spec_real_ends if folded else spec)}
+
+
+def kernel_table(w, prec, prof):
+    out = {}
+    byt = class_bytes(w, prec)
+    for k, (ms, cnt) in prof.items():
+        if not cnt:
+            continue
+        avg = ms / 1e3 / cnt
+        rec = {"launches": cnt, "avg_us": avg * 1e6}
+        if k in byt:
+            gbs = byt[k] / avg / 1e9
+            rec.update({"bytes_per_launch": byt[k], "GBps": gbs,
+                        "frac_hbm": gbs / PEAKS["hbm_GBs"]})
+        out[k] = rec
+    return out
+
+
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def measured_traffic(kernel_file, workload, prec):
+    """HBM bytes per launch of the DST kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, if it was taken on the current source of
+    that kernel (sha256 recorded in the summary); else None."""
+    import hashlib
+    import re
+    path = os.path.join(PROFILES, f"pmc_dst_fold_{prec}_{workload}.md")
+    src = os.path.join(ROOT, "paper_2002_01108_amd", "csrc", kernel_file)
+    if not (os.path.exists(path) and os.path.exists(src)):
+        return None
+    text = open(path).read()
+    sha = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    tb = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (sha and tb):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != sha.group(1):
+        return None
+    return float(tb.group(1))
+
+
+def copy_calibration():
+    """A plain device copy of known size (1 GiB in, 1 GiB out, 5 times), run
+    under rocprofv3 --pmc to scale FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8,
+                      "copies": 5}), flush=True)
 
 
 def cpu_baseline(w, f, u0, sample_steps):
@@ -158,6 +240,9 @@ def main():
         print(f"bench.py measures one GPU only (the method runs on one MI355X here); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
     import workloads as W
     from paper_2002_01108_amd import Solver
@@ -173,22 +258,25 @@ def main():
 
     s = Solver(w.dim, w.m1, w.n, T=w.T, eps=w.epsilon, precision=prec)
     t_step, info, prof, u, rhs = time_solver(s, fd, u0d, args.tol, restart, args.steps,
-                                             args.warmup, ["dst"])
+                                             args.warmup, ["dst", "time_fwd", "time_inv",
+                                                           "apply_L", "divide", "krylov"])
     dof = w.dof
     value = dof / t_step
 
     dst_ms, dst_n = prof["dst"]
+    folded = w.dim >= 2 and prec in ("fp64", "fp32")
     flops = dst_flops_per_launch(w, prec)
     avg_s = dst_ms / 1e3 / max(dst_n, 1)
     peak = {"fp64": PEAKS["fp64_TFs"], "fp32": PEAKS["fp32_TFs"],
             "bf16x3": PEAKS["bf16_TFs"]}[prec]
     achieved = flops / avg_s / 1e12 if dst_n else None
-    kname = "dst_fold" if w.dim >= 2 and prec in ("fp64", "fp32") else "dst_gemm"
-    roofline = {"kernel": f"{kname}_{prec} (one DST-I mode product)", "bound": "mfma",
-                "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak if achieved else None, "traffic": None,
+    traffic = measured_traffic("k_fold.hip", w.name, prec) if folded else None
+    roofline = {"kernel": f"{'dst_fold' if folded else 'dst_gemm'}_{prec} (one DST-I mode product)",
+                "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak if achieved else None, "traffic": traffic,
                 "avg_launch_us": avg_s * 1e6, "launches": dst_n,
-                "flops_per_launch": flops}
+                "flops_per_launch": flops,
+                "algorithmic_bytes_per_launch": class_bytes(w, prec)["dst"]}
 
     out = {
         "metric": METRIC, "value": value, "unit": "unknowns/s", "n_gpus": 1,
@@ -201,6 +289,7 @@ def main():
                    "restart": restart, "dof": dof},
         "gmres_iters": info["iters"], "rel_res": info["final_res"],
         "roofline": roofline,
+        "kernels": kernel_table(w, prec, prof),
     }
 
     if not args.no_oracle_check:
