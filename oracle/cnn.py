@@ -8,7 +8,9 @@ inner solve keeps that V-cycle and adds a small convolutional network N that
 maps the V-cycle's residual to a correction:
 
     e1 = V(r),  rho = r - B_k e1,  s = rms(rho),
-    e  = e1 + s * N(rho / s, log a; lambda_k).
+    e  = S_r(e1 + s * N(rho / s, log a; lambda_k)),
+where S_r is one red-black Gauss-Seidel sweep for B_k e = r started from its
+argument (it damps the high-frequency error the network leaves).
 
 N (parity unpinned as a model: its architecture is this build's choice, not the
 paper's; its arithmetic is pinned below):
@@ -17,8 +19,11 @@ paper's; its arithmetic is pinned below):
     z2 = conv3x3(h1, W2); h2 = relu((1 + G2 phi) * z2 + H2 phi)     C channels
     y  = conv3x3(h2, W3) + b3                                       2 channels
 with phi = (Re lambda_k, Im lambda_k, log|lambda_k|, 1) (feature-wise linear
-modulation), zero padding, cross-correlation convention.  Loss per block:
-||y - t||^2 / ||t||^2, averaged over the batch; Adam (Kingma & Ba) updates.
+modulation), zero padding, cross-correlation convention.  Training loss per
+block (residual_loss): ||rho_hat - B_k S(y)||^2 / ||rho_hat||^2, with rho_hat
+the normalised V-cycle residual and S the same sweep applied to the network
+output, averaged over the batch; Adam (Kingma & Ba) updates.  The plain
+error loss ||y - t||^2 / ||t||^2 (loss) is kept for the gradient pins.
 
 Parameter vector layout (float): W1[C][3][3][3], G1[C][4], H1[C][4],
 W2[C][C][3][3], G2[C][4], H2[C][4], W3[2][C][3][3], b3[2].
