@@ -170,7 +170,7 @@ aao_status aao_cnn_num_pairs(const aao_ctx *ctx, int *count);
  * B_k e = rho_hat started from N(x); its gradient runs back through the
  * sweep.  Per-step loss to host loss[steps] (may be null).  Parameters must be
  * set first (initial values are the caller's; drawing them is the caller's
- * business). 
+ * business). */
 aao_status aao_cnn_train(aao_ctx *ctx, int steps, int batch, float lr, const int *idx,
                          float *loss);
 
