@@ -841,7 +841,7 @@ aao_status sqnorm_dev(aao_ctx* c, const double* a, const double* b, int slot) {
   const int nb = krylov_blocks(len);
   TRY(ensure_part(c, (size_t)nb));
   HIPCHK(c, launch_diffnorm(a, b, len, c->part, c->stream));
-  HIPCHK(c, launch_reduce_partials(c->part, nb, 1, c->dsmall + slot, 0, c->stream));
+  HIPCHK(c, launch_reduce_partials(c->part, nb, 1, c->dsmall + slot, 0, nullptr, c->stream));
   return AAO_OK;
 }
 
@@ -1409,9 +1409,11 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
   const int64_t nm = nm_of(c);
   TRY(ensure_krylov(c, restart));
   const int R = restart;
-  // small scratch layout: [0] norm slot, [1..R+1] h1, [R+2..2R+2] h2, [2R+3] norm2, [2R+4..] y
+  // small scratch (doubles): [0] norm, [1..R+1] c1, [R+2..2R+2] c2, [2R+3] norm2,
+  // [2R+4..3R+4] y or the unit coefficient, [3R+5..4R+5] 1/s_i^2
   const int o_nrm = 0, o_h1 = 1, o_h2 = R + 2, o_n2 = 2 * R + 3, o_y = 2 * R + 4;
-  TRY(ensure_small(c, (size_t)(3 * R + 8)));
+  const int o_is2 = 3 * R + 5;
+  TRY(ensure_small(c, (size_t)(4 * R + 8)));
   const int nb = krylov_blocks(nm);
   TRY(ensure_part(c, (size_t)nb * (R + 2)));
 
@@ -1427,22 +1429,60 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
     if (final_res) *final_res = 0.0;
     return AAO_OK;
   }
-  if (!use_guess) HIPCHK(c, hipMemsetAsync(u, 0, nm * sizeof(double), c->stream));
+  // Without a guess u is zero; it is first written by the solution update
+  // (set mode), so it needs no clearing pass.  Early error returns clear it.
+  bool u_zero = !use_guess;
+  auto clear_u = [&]() -> aao_status {
+    if (u_zero) {
+      HIPCHK(c, hipMemsetAsync(u, 0, nm * sizeof(double), c->stream));
+      u_zero = false;
+    }
+    return AAO_OK;
+  };
+  // The Arnoldi basis is kept unnormalised: W_i = s_i v_i with v_i orthonormal
+  // and s_i known on the host.  Projection coefficients W_i.w / s_i^2 come out
+  // of the reductions scaled by 1/s_i^2 (device table), H and the solution
+  // update take the s_i on the host; no vector is ever rescaled.  Scales far
+  // from 1 are normalised explicitly so 1/s^2 stays representable.
+  auto in_range = [](double v) { return v > 1e-120 && v < 1e120; };
+  auto set_is2 = [&](int i, double si) -> aao_status {
+    c->hsmall[o_is2 + i] = 1.0 / (si * si);
+    HIPCHK(c, hipMemcpyAsync(c->dsmall + o_is2 + i, c->hsmall + o_is2 + i, sizeof(double),
+                             hipMemcpyHostToDevice, c->stream));
+    return AAO_OK;
+  };
 
-  std::vector<double> H((size_t)(R + 1) * R), cs(R), sn(R), gv(R + 1), y(R);
+  std::vector<double> H((size_t)(R + 1) * R), cs(R), sn(R), gv(R + 1), y(R), sc(R + 1);
   int total = 0, nhist = 0;
   bool converged = false;
   bool first = true;
   while (true) {
-    // r0 = rhs - L u  (zero guess on the first cycle: r0 = rhs)
-    double beta;
-    double* v0 = c->V;
+    double beta, g0;
+    const double* v0 = nullptr;  // W_0 when it is not stored in V
     if (first && !use_guess) {
+      // r0 = rhs: the basis starts from the caller's array
       beta = bnorm;
-      HIPCHK(c, launch_scale_host(rhs, v0, nm, 1.0 / beta, c->stream));
+      g0 = beta;
+      v0 = rhs;
+      sc[0] = beta;
+      if (!in_range(beta)) {
+        HIPCHK(c, launch_scale_host(rhs, c->V, nm, 1.0 / beta, c->stream));
+        v0 = nullptr;
+        sc[0] = 1.0;
+      }
     } else {
-      TRY(apply_L(c, u, c->tmp));
-      TRY(sqnorm_dev(c, rhs, c->tmp, o_nrm));
+      // W_0 = L u - rhs = -r0 in place in V, with its norm in the same pass
+      TRY(apply_L(c, u, c->V));
+      c->hsmall[o_y] = 1.0;
+      HIPCHK(c, hipMemcpyAsync(c->dsmall + o_y, c->hsmall + o_y, sizeof(double),
+                               hipMemcpyHostToDevice, c->stream));
+      {
+        ProfScope ps(c, AAO_K_KRYLOV);
+        HIPCHK(c, launch_axpy_dot(rhs, 0, nullptr, 1, c->dsmall + o_y, c->V, nm, c->part, 2,
+                                  c->stream));
+        HIPCHK(c, launch_reduce_partials(c->part, nb, 1, c->dsmall + o_nrm, 0, nullptr,
+                                         c->stream));
+      }
       TRY(fetch_small(c, o_nrm, 1));
       beta = sqrt(c->hsmall[o_nrm]);
       if (!isfinite(beta)) return fail(c, AAO_ENAN, "iterate is not finite");
@@ -1450,50 +1490,62 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
         converged = true;
         break;
       }
-      // v0 = (rhs - tmp) / beta: tmp <- rhs - tmp via axpy with coefficient -1 then scale
-      HIPCHK(c, launch_scale_host(c->tmp, v0, nm, -1.0 / beta, c->stream));
-      // v0 += rhs / beta
-      c->hsmall[o_y] = 1.0 / beta;
-      HIPCHK(c, hipMemcpyAsync(c->dsmall + o_y, c->hsmall + o_y, sizeof(double),
-                               hipMemcpyHostToDevice, c->stream));
-      HIPCHK(c, launch_multi_axpy(rhs, 0, 1, c->dsmall + o_y, v0, nm, c->stream));
+      g0 = -beta;
+      sc[0] = beta;
+      if (!in_range(beta)) {
+        HIPCHK(c, launch_scale_host(c->V, c->V, nm, 1.0 / beta, c->stream));
+        sc[0] = 1.0;
+      }
     }
     first = false;
     if (total >= maxit) break;
+    TRY(set_is2(0, sc[0]));
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(gv.begin(), gv.end(), 0.0);
-    gv[0] = beta;
+    gv[0] = g0;
     int j = 0;
     bool stop = false;
     for (j = 0; j < R; ++j) {
-      double* vj = c->V + (int64_t)j * nm;
+      const double* wj = (j == 0 && v0) ? v0 : c->V + (int64_t)j * nm;
       double* zj = c->Z + (int64_t)j * nm;
       double* w = c->V + (int64_t)(j + 1) * nm;
-      TRY(apply_pinv(c, vj, zj));
+      TRY(apply_pinv(c, wj, zj));
       TRY(apply_L(c, zj, w));
       const int q = j + 1;
-      // CGS2: h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2; ||w||
+      const double* is2 = c->dsmall + o_is2;
+      // CGS2 on the unnormalised basis: c1 = (W^T w) / s^2; w -= W c1;
+      // c2 = (W^T w) / s^2; w -= W c2; ||w||^2
       {
-      ProfScope ps(c, AAO_K_KRYLOV);
-      HIPCHK(c, launch_multidot(c->V, nm, q, w, nm, c->part, c->stream));
-      HIPCHK(c, launch_reduce_partials(c->part, nb, q, c->dsmall + o_h1, 0, c->stream));
-      if (q <= 8) {
-        HIPCHK(c, launch_axpy_dot(c->V, nm, q, c->dsmall + o_h1, w, nm, c->part, 1, c->stream));
-        HIPCHK(c, launch_reduce_partials(c->part, nb, q, c->dsmall + o_h2, 0, c->stream));
-      } else {
-        HIPCHK(c, launch_axpy_dot(c->V, nm, q, c->dsmall + o_h1, w, nm, c->part, 0, c->stream));
-        HIPCHK(c, launch_multidot(c->V, nm, q, w, nm, c->part, c->stream));
-        HIPCHK(c, launch_reduce_partials(c->part, nb, q, c->dsmall + o_h2, 0, c->stream));
-      }
-      HIPCHK(c, launch_axpy_dot(c->V, nm, q, c->dsmall + o_h2, w, nm, c->part, 2, c->stream));
-      HIPCHK(c, launch_reduce_partials(c->part, nb, 1, c->dsmall + o_n2, 0, c->stream));
+        ProfScope ps(c, AAO_K_KRYLOV);
+        HIPCHK(c, launch_multidot(c->V, nm, v0, q, w, nm, c->part, c->stream));
+        HIPCHK(c, launch_reduce_partials(c->part, nb, q, c->dsmall + o_h1, 0, is2, c->stream));
+        if (q <= 8) {
+          HIPCHK(c, launch_axpy_dot(c->V, nm, v0, q, c->dsmall + o_h1, w, nm, c->part, 1,
+                                    c->stream));
+          HIPCHK(c, launch_reduce_partials(c->part, nb, q, c->dsmall + o_h2, 0, is2, c->stream));
+        } else {
+          HIPCHK(c, launch_axpy_dot(c->V, nm, v0, q, c->dsmall + o_h1, w, nm, c->part, 0,
+                                    c->stream));
+          HIPCHK(c, launch_multidot(c->V, nm, v0, q, w, nm, c->part, c->stream));
+          HIPCHK(c, launch_reduce_partials(c->part, nb, q, c->dsmall + o_h2, 0, is2, c->stream));
+        }
+        HIPCHK(c, launch_axpy_dot(c->V, nm, v0, q, c->dsmall + o_h2, w, nm, c->part, 2,
+                                  c->stream));
+        HIPCHK(c, launch_reduce_partials(c->part, nb, 1, c->dsmall + o_n2, 0, nullptr,
+                                         c->stream));
       }
       TRY(fetch_small(c, 0, o_n2 + 1));
-      double* Hj = &H[0];
-      for (int i = 0; i < q; ++i) Hj[(size_t)i * R + j] = c->hsmall[o_h1 + i] + c->hsmall[o_h2 + i];
-      const double hn = sqrt(std::max(c->hsmall[o_n2], 0.0));
-      if (!isfinite(hn)) return fail(c, AAO_ENAN, "Arnoldi vector is not finite");
-      Hj[(size_t)(j + 1) * R + j] = hn;
+      // H in the orthonormal basis: h_ij = (c1_i + c2_i) s_i / s_j, h_{j+1,j} = ||w|| / s_j
+      for (int i = 0; i < q; ++i)
+        H[(size_t)i * R + j] = (c->hsmall[o_h1 + i] + c->hsmall[o_h2 + i]) * sc[i] / sc[j];
+      const double wn = sqrt(std::max(c->hsmall[o_n2], 0.0));
+      if (!isfinite(wn)) {
+        TRY(clear_u());
+        return fail(c, AAO_ENAN, "Arnoldi vector is not finite");
+      }
+      const double hn = wn / sc[j];
+      H[(size_t)(j + 1) * R + j] = hn;
+      sc[j + 1] = wn;
       // apply previous rotations, then a new one (real Givens)
       for (int i = 0; i < j; ++i) {
         const double a = H[(size_t)i * R + j], b = H[(size_t)(i + 1) * R + j];
@@ -1512,27 +1564,37 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
       const double est = fabs(gv[j + 1]) / bnorm;
       if (res_hist && nhist < hist_cap) res_hist[nhist] = est;
       ++nhist;
-      const bool breakdown = (hn == 0.0);
+      const bool breakdown = (wn == 0.0);
       if (est <= tol || breakdown) converged = true;
       if (converged || total >= maxit) {
         stop = true;
         break;
       }
-      HIPCHK(c, launch_scale_host(w, w, nm, 1.0 / hn, c->stream));
+      if (!in_range(wn)) {
+        HIPCHK(c, launch_scale_host(w, w, nm, 1.0 / wn, c->stream));
+        sc[j + 1] = 1.0;
+      }
+      TRY(set_is2(j + 1, sc[j + 1]));
     }
     const int k = stop ? j + 1 : R;
-    // back substitution R y = g
+    // back substitution R y = g, then u (+)= sum_i (y_i / s_i) Z_i
     for (int i = k - 1; i >= 0; --i) {
       double s = gv[i];
       for (int l = i + 1; l < k; ++l) s -= H[(size_t)i * R + l] * y[l];
       y[i] = s / H[(size_t)i * R + i];
     }
-    for (int i = 0; i < k; ++i) c->hsmall[o_y + i] = y[i];
+    for (int i = 0; i < k; ++i) c->hsmall[o_y + i] = y[i] / sc[i];
     HIPCHK(c, hipMemcpyAsync(c->dsmall + o_y, c->hsmall + o_y, k * sizeof(double),
                              hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, launch_multi_axpy(c->Z, nm, k, c->dsmall + o_y, u, nm, c->stream));
+    {
+      ProfScope ps(c, AAO_K_KRYLOV);
+      HIPCHK(c, launch_multi_axpy(c->Z, nm, k, c->dsmall + o_y, u, nm, u_zero ? 1 : 0,
+                                  c->stream));
+    }
+    u_zero = false;
     if (converged || total >= maxit) break;
   }
+  TRY(clear_u());
   // explicit residual
   TRY(apply_L(c, u, c->tmp));
   TRY(sqnorm_dev(c, rhs, c->tmp, o_nrm));

@@ -132,25 +132,28 @@ hipError_t launch_ext_to_spec(const Geometry& g, const double* ext, void* spec, 
                               hipStream_t s);
 
 // ---------------------------------------------------------------- Krylov kernels
-// Partial dot products: part[b*q + i] = sum over block b's elements of V_i . w,
-// V_i = V + i*ldv.  nblk blocks.  Then reduce_partials sums over blocks.
+// Basis vectors: V_i = V + i*ldv, except V_0 = v0 when v0 is non-null.
+// Partial dot products: part[b*q + i] = sum over block b's elements of V_i . w.
+// krylov_blocks(len) blocks.  Then reduce_partials sums over blocks.
 int krylov_blocks(int64_t len);
-hipError_t launch_multidot(const double* V, int64_t ldv, int q, const double* w, int64_t len,
-                           double* part, hipStream_t s);
-// w -= sum_i h_i V_i, then (if q2 > 0) partial dots of V_i with the new w (q2 = q)
-// or (q2 < 0) partial squared norm of the new w.
-hipError_t launch_axpy_dot(const double* V, int64_t ldv, int q, const double* h, double* w,
-                           int64_t len, double* part, int mode, hipStream_t s);
+hipError_t launch_multidot(const double* V, int64_t ldv, const double* v0, int q,
+                           const double* w, int64_t len, double* part, hipStream_t s);
+// w -= sum_{i<q} h_i V_i, then mode 1: partial dots of V_i with the new w
+// (q <= 8); mode 2: partial squared norm of the new w; mode 0: nothing.
+hipError_t launch_axpy_dot(const double* V, int64_t ldv, const double* v0, int q,
+                           const double* h, double* w, int64_t len, double* part, int mode,
+                           hipStream_t s);
+// out[i] (+)= scale[i] * sum over blocks (scale may be null: 1)
 hipError_t launch_reduce_partials(const double* part, int nblk, int q, double* out,
-                                  int accumulate, hipStream_t s);
+                                  int accumulate, const double* scale, hipStream_t s);
 // y = alpha * x  (alpha read from device memory as 1/alpha_ptr[0] if inv != 0)
 hipError_t launch_scale(const double* x, double* y, int64_t len, const double* alpha_dev,
                         int inv, hipStream_t s);
 // y = alpha * x with alpha a host scalar
 hipError_t launch_scale_host(const double* x, double* y, int64_t len, double alpha, hipStream_t s);
-// x += sum_i c_i Z_i with c on device
+// x = (set ? 0 : x) + sum_i c_i Z_i with c on device
 hipError_t launch_multi_axpy(const double* Z, int64_t ldz, int q, const double* c, double* x,
-                             int64_t len, hipStream_t s);
+                             int64_t len, int set, hipStream_t s);
 // partial squared norm of (a - b) (b may be null -> ||a||^2)
 hipError_t launch_diffnorm(const double* a, const double* b, int64_t len, double* part,
                            hipStream_t s);

@@ -39,9 +39,17 @@ __device__ __forceinline__ void block_store(double (&acc)[Q], double* part, int 
   }
 }
 
+// Basis vector i: V + i*ldv, except vector 0 which is v0 when v0 is non-null
+// (the Krylov basis may start from a caller's array without a copy).
+__device__ __forceinline__ const double* basis(const double* V, int64_t ldv, const double* v0,
+                                               int i) {
+  return (i == 0 && v0) ? v0 : V + i * ldv;
+}
+
 // part[b*qtot + qoff + i] = partial sum of V_{qoff+i} . w
 template <int Q>
 __global__ __launch_bounds__(KT) void k_multidot(const double* __restrict__ V, int64_t ldv,
+                                                 const double* __restrict__ v0,
                                                  const double* __restrict__ w, int64_t len,
                                                  double* __restrict__ part, int qtot, int qoff) {
   double acc[Q];
@@ -54,13 +62,13 @@ __global__ __launch_bounds__(KT) void k_multidot(const double* __restrict__ V, i
     const double2 wv = w2[e];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const double2 v = reinterpret_cast<const double2*>(V + (qoff + i) * ldv)[e];
+      const double2 v = reinterpret_cast<const double2*>(basis(V, ldv, v0, qoff + i))[e];
       acc[i] += v.x * wv.x + v.y * wv.y;
     }
   }
   if ((len & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) acc[i] += V[(qoff + i) * ldv + len - 1] * w[len - 1];
+    for (int i = 0; i < Q; ++i) acc[i] += basis(V, ldv, v0, qoff + i)[len - 1] * w[len - 1];
   }
   block_store<Q>(acc, part, qtot, qoff);
 }
@@ -68,7 +76,8 @@ __global__ __launch_bounds__(KT) void k_multidot(const double* __restrict__ V, i
 // w -= sum_{i<q} h_i V_i; then MODE 1: partial dots of V_0..V_{Q-1} with the
 // new w (requires q == Q);  MODE 2: partial ||w||^2;  MODE 0: nothing.
 template <int Q, int MODE>
-__global__ __launch_bounds__(KT) void k_axpy(const double* __restrict__ V, int64_t ldv, int q,
+__global__ __launch_bounds__(KT) void k_axpy(const double* __restrict__ V, int64_t ldv,
+                                             const double* __restrict__ v0, int q,
                                              const double* __restrict__ h, double* __restrict__ w,
                                              int64_t len, double* __restrict__ part) {
   double acc[Q];
@@ -79,11 +88,11 @@ __global__ __launch_bounds__(KT) void k_axpy(const double* __restrict__ V, int64
   auto body = [&](double& wx, int64_t idx) {
     // scalar element update (used for the odd tail)
     double s = wx;
-    for (int i = 0; i < q; ++i) s -= h[i] * V[i * ldv + idx];
+    for (int i = 0; i < q; ++i) s -= h[i] * basis(V, ldv, v0, i)[idx];
     wx = s;
     if (MODE == 1) {
 #pragma unroll
-      for (int i = 0; i < Q; ++i) acc[i] += V[i * ldv + idx] * s;
+      for (int i = 0; i < Q; ++i) acc[i] += basis(V, ldv, v0, i)[idx] * s;
     } else if (MODE == 2) {
       acc[0] += s * s;
     }
@@ -93,7 +102,7 @@ __global__ __launch_bounds__(KT) void k_axpy(const double* __restrict__ V, int64
     double2 wv = w2[e];
     for (int i = 0; i < q; ++i) {
       const double hi = h[i];
-      const double2 v = reinterpret_cast<const double2*>(V + i * ldv)[e];
+      const double2 v = reinterpret_cast<const double2*>(basis(V, ldv, v0, i))[e];
       wv.x -= hi * v.x;
       wv.y -= hi * v.y;
     }
@@ -101,7 +110,7 @@ __global__ __launch_bounds__(KT) void k_axpy(const double* __restrict__ V, int64
     if (MODE == 1) {
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        const double2 v = reinterpret_cast<const double2*>(V + i * ldv)[e];
+        const double2 v = reinterpret_cast<const double2*>(basis(V, ldv, v0, i))[e];
         acc[i] += v.x * wv.x + v.y * wv.y;
       }
     } else if (MODE == 2) {
@@ -112,9 +121,11 @@ __global__ __launch_bounds__(KT) void k_axpy(const double* __restrict__ V, int64
   if (MODE != 0) block_store<Q>(acc, part, MODE == 1 ? Q : 1, 0);
 }
 
-// out[i] (+)= sum_b part[b*q + i], one block per output
+// out[i] (+)= scale_i * sum_b part[b*q + i] (scale_i = 1 when scale is null),
+// one block per output
 __global__ __launch_bounds__(KT) void k_reduce(const double* __restrict__ part, int nblk, int q,
-                                               double* __restrict__ out, int accumulate) {
+                                               double* __restrict__ out, int accumulate,
+                                               const double* __restrict__ scale) {
   const int i = blockIdx.x;
   double s = 0.0;
   for (int b = threadIdx.x; b < nblk; b += KT) s += part[(int64_t)b * q + i];
@@ -125,6 +136,7 @@ __global__ __launch_bounds__(KT) void k_reduce(const double* __restrict__ part, 
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int w = 0; w < KT / 64; ++w) t += red[w];
+    if (scale) t *= scale[i];
     out[i] = accumulate ? out[i] + t : t;
   }
 }
@@ -138,11 +150,13 @@ __global__ void k_scale(const double* __restrict__ x, double* __restrict__ y, in
     y[e] = a * x[e];
 }
 
+// x (+)= sum_i c_i Z_i; with set != 0 x is overwritten (not read)
 __global__ void k_multi_axpy(const double* __restrict__ Z, int64_t ldz, int q,
-                             const double* __restrict__ c, double* __restrict__ x, int64_t len) {
+                             const double* __restrict__ c, double* __restrict__ x, int64_t len,
+                             int set) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < len;
        e += (int64_t)gridDim.x * blockDim.x) {
-    double s = x[e];
+    double s = set ? 0.0 : x[e];
     for (int i = 0; i < q; ++i) s += c[i] * Z[i * ldz + e];
     x[e] = s;
   }
@@ -196,15 +210,16 @@ int krylov_blocks(int64_t len) {
   return (int)b;
 }
 
-hipError_t launch_multidot(const double* V, int64_t ldv, int q, const double* w, int64_t len,
-                           double* part, hipStream_t s) {
+hipError_t launch_multidot(const double* V, int64_t ldv, const double* v0, int q,
+                           const double* w, int64_t len, double* part, hipStream_t s) {
   const int nb = krylov_blocks(len);
   for (int q0 = 0; q0 < q; q0 += QMAX) {
     const int qq = (q - q0 < QMAX) ? q - q0 : QMAX;
     switch (qq) {
 #define CASE(Q)                                                                                \
   case Q:                                                                                      \
-    hipLaunchKernelGGL((k_multidot<Q>), dim3(nb), dim3(KT), 0, s, V, ldv, w, len, part, q, q0); \
+    hipLaunchKernelGGL((k_multidot<Q>), dim3(nb), dim3(KT), 0, s, V, ldv, v0, w, len, part, q, \
+                       q0);                                                                    \
     break;
       CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
@@ -213,30 +228,32 @@ hipError_t launch_multidot(const double* V, int64_t ldv, int q, const double* w,
   return hipGetLastError();
 }
 
-hipError_t launch_axpy_dot(const double* V, int64_t ldv, int q, const double* h, double* w,
-                           int64_t len, double* part, int mode, hipStream_t s) {
+hipError_t launch_axpy_dot(const double* V, int64_t ldv, const double* v0, int q,
+                           const double* h, double* w, int64_t len, double* part, int mode,
+                           hipStream_t s) {
   const int nb = krylov_blocks(len);
   if (mode == 1) {
     if (q > QMAX || q < 1) return hipErrorInvalidValue;
     switch (q) {
 #define CASE(Q)                                                                             \
   case Q:                                                                                   \
-    hipLaunchKernelGGL((k_axpy<Q, 1>), dim3(nb), dim3(KT), 0, s, V, ldv, q, h, w, len, part); \
+    hipLaunchKernelGGL((k_axpy<Q, 1>), dim3(nb), dim3(KT), 0, s, V, ldv, v0, q, h, w, len,    \
+                       part);                                                                 \
     break;
       CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     }
   } else if (mode == 2) {
-    hipLaunchKernelGGL((k_axpy<1, 2>), dim3(nb), dim3(KT), 0, s, V, ldv, q, h, w, len, part);
+    hipLaunchKernelGGL((k_axpy<1, 2>), dim3(nb), dim3(KT), 0, s, V, ldv, v0, q, h, w, len, part);
   } else {
-    hipLaunchKernelGGL((k_axpy<1, 0>), dim3(nb), dim3(KT), 0, s, V, ldv, q, h, w, len, part);
+    hipLaunchKernelGGL((k_axpy<1, 0>), dim3(nb), dim3(KT), 0, s, V, ldv, v0, q, h, w, len, part);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_partials(const double* part, int nblk, int q, double* out, int accumulate,
-                                  hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(q), dim3(KT), 0, s, part, nblk, q, out, accumulate);
+                                  const double* scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(q), dim3(KT), 0, s, part, nblk, q, out, accumulate, scale);
   return hipGetLastError();
 }
 
@@ -255,8 +272,9 @@ hipError_t launch_scale_host(const double* x, double* y, int64_t len, double alp
 }
 
 hipError_t launch_multi_axpy(const double* Z, int64_t ldz, int q, const double* c, double* x,
-                             int64_t len, hipStream_t s) {
-  hipLaunchKernelGGL(k_multi_axpy, dim3(simple_grid(len)), dim3(256), 0, s, Z, ldz, q, c, x, len);
+                             int64_t len, int set, hipStream_t s) {
+  hipLaunchKernelGGL(k_multi_axpy, dim3(simple_grid(len)), dim3(256), 0, s, Z, ldz, q, c, x, len,
+                     set);
   return hipGetLastError();
 }
 
