@@ -40,7 +40,10 @@ template <> struct Mf<float> {
 
 constexpr int FBK = 8;     // K slice (half indices t)
 constexpr int FC = 64;     // column (LEFT) / row (RIGHT) tile
-constexpr int PD = 1;      // LDS padding
+// LDS row padding: rows of 64 + 16 elements start 128 B (FP64) / 64 B (FP32)
+// apart modulo the bank width, so the four k-rows an MFMA operand read touches
+// fall on disjoint banks
+constexpr int PD = 16;
 
 template <typename T, int FR, bool LEFT, bool DIVIDE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_dst_fold(const T* __restrict__ in, T* __restrict__ out,
@@ -58,6 +61,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // RIGHT: As = data [pl][par][t][row], Bs = S^T tiles [mat][t][r]
   __shared__ T Sd[2][2][2][FBK][FC + PD];   // [buf][pl][par][t][c or row]
   __shared__ T Ss[2][2][FBK][FR + PD];      // [buf][mat][t][r]
+  __shared__ double tax[DIVIDE ? 1024 : 1]; // divide: tau mu along the product's axis
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -84,10 +88,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // S loads: 2 mats x FR r x FBK t, SPT consecutive t per thread
   const int s_mat = tid >> 7, s_r = (tid & 127) / STR, s_t = ((tid & 127) % STR) * SPT;
   const T* Sm = s_mat ? Soo : Soe;
-  // data loads: 2 planes x 2*FBK input indices x FC = 2048, 8 per thread
-  const int d_pl = tid >> 7;
-  int d_a, d_c;   // LEFT: input row (0..15) and 8 columns; RIGHT: data row (0..63) and 8 inputs
-  if (LEFT) { d_a = (tid & 127) >> 3; d_c = (tid & 7) * 8; }
+  // data loads: 2 planes x 2*FBK input indices x FC = 2048, 8 per thread.
+  // LEFT: wave w loads plane w/2, parity w%2: lane = column, one row of 64
+  // consecutive elements per load.  RIGHT: 2 threads per data row, 8
+  // consecutive inputs each.
+  const int d_pl = w >> 1, d_par = w & 1;
+  int d_a, d_c;   // RIGHT: data row (0..63) and first of 8 inputs
+  if (LEFT) { d_a = 0; d_c = 0; }
   else { d_a = (tid & 127) >> 1; d_c = (tid & 1) * 8; }
 
   auto fetch = [&](int t0) {
@@ -95,9 +102,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int e = 0; e < SPT; ++e) rs[e] = Sm[(int64_t)(r0 + s_r) * f.Hp + t0 + s_t + e];
     const T* src = in + (d_pl ? base1 : base0);
     if (LEFT) {
-      const T* p = src + (int64_t)(2 * t0 + d_a) * f.R + d0 + d_c;
+      const T* p = src + (int64_t)(2 * t0 + d_par) * f.R + d0 + lane;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) rd[e] = p[e];
+      for (int e = 0; e < 8; ++e) rd[e] = p[(int64_t)(2 * e) * f.R];
     } else {
       const T* p = src + (int64_t)(d0 + d_a) * f.R + 2 * t0 + d_c;
 #pragma unroll
@@ -108,9 +115,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
     for (int e = 0; e < SPT; ++e) Ss[buf][s_mat][s_t + e][s_r] = rs[e];
     if (LEFT) {
-      // input row 2t+par -> (par, t)
+      // input row 2(t0+e)+par -> (par, e)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) Sd[buf][d_pl][d_a & 1][d_a >> 1][d_c + e] = rd[e];
+      for (int e = 0; e < 8; ++e) Sd[buf][d_pl][d_par][e][lane] = rd[e];
     } else {
       // input column 2t+par of data row d_a
 #pragma unroll
@@ -129,6 +136,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
       for (int s = 0; s < NS; ++s) acc[a][b][s] = V{0, 0, 0, 0};
 
+  // divide: stage the axis table in LDS (read by the epilogue after the barriers)
+  if (DIVIDE) {
+    const double* ax_tab = LEFT ? (f.axis == 1 ? tmu2 : tmu3) : tmu1;
+    for (int i = tid; i < 2 * f.Hp; i += 256) tax[i] = ax_tab[i];
+  }
   fetch(0);
   stash(0);
   __syncthreads();
@@ -186,6 +198,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const double lre = DIVIDE ? lam[2 * k] : 0.0, lim = DIVIDE ? lam[2 * k + 1] : 0.0;
   // real pair: lambda_0 and lambda_{n/2} are real
   const double lre1 = (DIVIDE && real_pair) ? lam[2 * f.nk] : 0.0;
+  // divisor terms of the two non-product axes: constant per lane (LEFT) or
+  // per accumulator row v (RIGHT)
+  double cst[4] = {0.0, 0.0, 0.0, 0.0};
+  if (DIVIDE) {
+    if (LEFT) {
+      const int dl = d0 + w * 16 + lr;
+      const double c0 = f.axis == 1 ? tmu1[dl] + (tmu3 ? tmu3[o] : 0.0)
+                                    : tmu1[dl % f.P1] + tmu2[dl / f.P1];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) cst[v] = c0;
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int dr = d0 + w * 16 + Mf<T>::row(lk, v);
+        cst[v] = tmu2[dr % f.P2] + (tmu3 ? tmu3[dr / f.P2] : 0.0);
+      }
+    }
+  }
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
 #pragma unroll
@@ -216,10 +246,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
           vr = T(0);
           vi = T(0);
         } else if (DIVIDE) {
-          int j1 = i1, j2 = i2, j3 = i3;
-          if (LEFT) { if (f.axis == 1) j2 = a; else j3 = a; }
-          else j1 = a;
-          const double mu = tmu1[j1] + (tmu2 ? tmu2[j2] : 0.0) + (tmu3 ? tmu3[j3] : 0.0);
+          const double mu = cst[v] + tax[a];
           if (real_pair) {
             vr = vr / (T)(lre + mu);
             vi = vi / (T)(lre1 + mu);
