@@ -222,8 +222,19 @@ def learned_leg(tol, steps, oracle_check, train_fields=4, train_steps=1500, batc
         from oracle import heat
         p = heat.Problem(w.m1, w.dim, w.n, eps=w.epsilon, faces=faces)
         exact = p.exact(p.rhs(f, u0))
-    for inner in ("mg", "cnn", "dst_mean"):
-        s.set_inner(inner)
+    trained = s.cnn_get_params()
+    # "mg_sweep": the learned inner solve with a zero network, i.e. the V-cycle
+    # plus the red-black sweep that wraps the network (the control that isolates
+    # what the trained network itself contributes)
+    for inner in ("mg", "mg_sweep", "cnn", "dst_mean"):
+        if inner == "mg_sweep":
+            s.cnn_set_params(np.zeros_like(trained))
+            s.set_inner("cnn")
+        elif inner == "cnn":
+            s.cnn_set_params(trained)
+            s.set_inner("cnn")
+        else:
+            s.set_inner(inner)
         t, info, _, u, _ = time_solver(s, fd, u0d, tol, 50, steps, 1, [])
         rec = {"value": w.dof / t, "ms_per_step": t * 1e3, "gmres_iters": info["iters"],
                "rel_res": info["final_res"]}

@@ -122,9 +122,11 @@ aao_status aao_set_inner(aao_ctx *ctx, aao_inner inner, int cycles);
  * Section 4 and Section 5, Example 2) with a small network N that corrects the
  * V-cycle's result per frequency block k:
  *     e1 = V(r),  rho = r - B_k e1,  s = rms(rho),
- *     e  = S_r(e1 + s N(rho/s, log a; lambda_k))
- * with S_r one red-black Gauss-Seidel sweep for B_k e = r (the V-cycle's
- * smoother) started from its argument.
+ *     e  = S_r(e1 + s N(rho/s, log a; lambda_k) / (lambda_k + d))
+ * with d the diagonal of tau K_a at each node (the network's two output
+ * channels, a complex field, are divided pointwise by the diagonal of B_k) and
+ * S_r one red-black Gauss-Seidel sweep for B_k e = r (the V-cycle's smoother)
+ * started from its argument.
  * N: three 3x3 convolutions 3 -> 8 -> 8 -> 2 channels with ReLU, the two hidden
  * layers modulated by gamma = 1 + G phi, beta = H phi of the features
  * phi = (Re lambda_k, Im lambda_k, log|lambda_k|, 1); input channels
@@ -165,10 +167,10 @@ aao_status aao_cnn_num_pairs(const aao_ctx *ctx, int *count);
 /* `steps` Adam steps (lr; beta1 0.9, beta2 0.999, 1e-8) on minibatches of
  * `batch` pairs chosen by the caller: idx host [steps][batch] in [0, num_pairs).
  * The loss is the residual the inner solve leaves after the network and the
- * sweep: mean over the batch of ||rho_hat - B_k S(N(x))||^2 / ||rho_hat||^2,
- * rho_hat = rho/s the stored input residual and S the sweep for
- * B_k e = rho_hat started from N(x); its gradient runs back through the
- * sweep.  Per-step loss to host loss[steps] (may be null).  Parameters must be
+ * sweep: mean over the batch of ||rho_hat - B_k S(N(x) / (lambda_k + d))||^2
+ * / ||rho_hat||^2, rho_hat = rho/s the stored input residual and S the sweep
+ * for B_k e = rho_hat; its gradient runs back through the sweep and the
+ * diagonal scaling.  Per-step loss to host loss[steps] (may be null).  Parameters must be
  * set first (initial values are the caller's; drawing them is the caller's
  * business). */
 aao_status aao_cnn_train(aao_ctx *ctx, int steps, int batch, float lr, const int *idx,

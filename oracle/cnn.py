@@ -8,9 +8,11 @@ inner solve keeps that V-cycle and adds a small convolutional network N that
 maps the V-cycle's residual to a correction:
 
     e1 = V(r),  rho = r - B_k e1,  s = rms(rho),
-    e  = S_r(e1 + s * N(rho / s, log a; lambda_k)),
-where S_r is one red-black Gauss-Seidel sweep for B_k e = r started from its
-argument (it damps the high-frequency error the network leaves).
+    e  = S_r(e1 + s * N(rho / s, log a; lambda_k) / (lambda_k + d)),
+where d is the diagonal of tau K_a at each node (the network's two output
+channels are a complex field divided pointwise by the diagonal of B_k, so it
+learns a correction relative to a Jacobi step) and S_r is one red-black
+Gauss-Seidel sweep for B_k e = r started from its argument.
 
 N (parity unpinned as a model: its architecture is this build's choice, not the
 paper's; its arithmetic is pinned below):
@@ -20,9 +22,9 @@ paper's; its arithmetic is pinned below):
     y  = conv3x3(h2, W3) + b3                                       2 channels
 with phi = (Re lambda_k, Im lambda_k, log|lambda_k|, 1) (feature-wise linear
 modulation), zero padding, cross-correlation convention.  Training loss per
-block (residual_loss): ||rho_hat - B_k S(y)||^2 / ||rho_hat||^2, with rho_hat
-the normalised V-cycle residual and S the same sweep applied to the network
-output, averaged over the batch; Adam (Kingma & Ba) updates.  The plain
+block (residual_loss): ||rho_hat - B_k S(y / (lambda_k + d))||^2 / ||rho_hat||^2,
+with rho_hat the normalised V-cycle residual, y the network output and S the
+same sweep, averaged over the batch; Adam (Kingma & Ba) updates.  The plain
 error loss ||y - t||^2 / ||t||^2 (loss) is kept for the gradient pins.
 
 Parameter vector layout (float): W1[C][3][3][3], G1[C][4], H1[C][4],
@@ -189,8 +191,9 @@ def node_log_coefficient(ax: np.ndarray, ay: np.ndarray) -> np.ndarray:
 def inner_apply(params: np.ndarray, lvls, r: np.ndarray, lam: complex, loga: np.ndarray,
                 C: int = C_HIDDEN) -> np.ndarray:
     """The learned inner solve of one block: e1 = V(r), rho = r - B e1,
-    e = S_r(e1 + s N(rho/s)) with s the root-mean-square of rho over both planes
-    and S_r one red-black Gauss-Seidel sweep for B e = r."""
+    e = S_r(e1 + s N(rho/s) / (lambda + d)) with s the root-mean-square of rho
+    over both planes, d the diagonal of tau K_a and S_r one red-black
+    Gauss-Seidel sweep for B e = r."""
     from . import mg
     m, wx, wy = lvls[0]
     e1 = mg.vcycle(lvls, 0, r, lam)
@@ -200,13 +203,15 @@ def inner_apply(params: np.ndarray, lvls, r: np.ndarray, lam: complex, loga: np.
         return e1
     x = np.stack([rho.real / s, rho.imag / s, loga])[None]
     y, _ = forward(params, x, features(np.array([lam])), C)
-    return mg.rbgs(e1 + s * (y[0, 0] + 1j * y[0, 1]), r, lam, wx, wy)
+    corr = (y[0, 0] + 1j * y[0, 1]) / (lam + _diag(wx, wy))
+    return mg.rbgs(e1 + s * corr, r, lam, wx, wy)
 
 
 # ---------------------------------------------------------------- residual loss
-# The correction N is followed by one red-black Gauss-Seidel sweep S for
-# B e = rho (normalised units) and scored by the residual it leaves:
-#     L_b = ||rho_b - B S(N_b)||^2 / ||rho_b||^2,
+# The correction y_b / (lambda_b + d) (y_b the network output, d the diagonal
+# of tau K_a) is followed by one red-black Gauss-Seidel sweep S for B e = rho
+# (normalised units) and scored by the residual it leaves:
+#     L_b = ||rho_b - B S(y_b / (lambda_b + d))||^2 / ||rho_b||^2,
 # which is the error against the multigrid correction delta (B delta = rho)
 # measured in the norm ||B .||.  Arrays are real [B][2][H][W] (Re, Im); lam is
 # complex per batch entry; wx [H][W+1], wy [H+1][W] are tau/h^2 face weights.
@@ -257,10 +262,11 @@ def apply_B_batch(e, lam, wx, wy):
 
 
 def residual_loss(y, rho, lam, wx, wy):
-    """(mean_b ||rho_b - B S(y_b)||^2 / ||rho_b||^2, gradient in y)."""
+    """(mean_b ||rho_b - B S(y_b / (lambda_b + d))||^2 / ||rho_b||^2, gradient in y)."""
     Bn = y.shape[0]
     rn = (rho ** 2).sum(axis=(1, 2, 3))
-    e = sweep(y, rho, lam, wx, wy)
+    cdiag = lam[:, None, None] + _diag(wx, wy)[None]
+    e = sweep(_r(_c(y) / cdiag), rho, lam, wx, wy)
     q = rho - apply_B_batch(e, lam, wx, wy)
     val = float(np.mean((q ** 2).sum(axis=(1, 2, 3)) / rn))
     # gradient: dL/dq, then through B (B^H), then through the sweep (adjoint)
@@ -274,4 +280,5 @@ def residual_loss(y, rho, lam, wx, wy):
     # red half sweep: red' = (rho + W y_black)/den -> gradient to y at black points
     hr = h / den_c
     dy = np.where(black[None], _nbr(hr, wx, wy), 0.0)
-    return val, _r(dy)
+    # through the pointwise division by lambda + d: the adjoint divides by its conjugate
+    return val, _r(dy / np.conj(cdiag))

@@ -778,7 +778,7 @@ aao_status cnn_inner_t(aao_ctx* c, void* r, void* e) {
   HIPCHK(c, hipMemcpyAsync(n.phi, n.phik, 4 * nh * sizeof(float), hipMemcpyDeviceToDevice,
                            c->stream));
   TRY(cnn_forward_run(c, nh, m, m, false));
-  HIPCHK(c, cnn_unpack_add<T>(n.Y, n.ss, E, m, nh, c->stream));
+  HIPCHK(c, cnn_unpack_add<T>(n.Y, n.ss, E, c->lam, n.wxf, n.wyf, m, nh, c->stream));
   HIPCHK(c, mg_rbgs<T>(E, R, L0.wx, L0.wy, c->lam, m, nh, 0, 0, c->stream));
   HIPCHK(c, mg_rbgs<T>(E, R, L0.wx, L0.wy, c->lam, m, nh, 1, 0, c->stream));
   return AAO_OK;

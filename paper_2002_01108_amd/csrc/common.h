@@ -231,7 +231,7 @@ template <typename T>
 hipError_t cnn_pack_input(const MgGrid& v, const float* ss, const float* loga, float* X, int m,
                           int nh, int nch, hipStream_t s);
 template <typename T>
-hipError_t cnn_unpack_add(const float* Y, const float* ss, const MgGrid& v, int m, int nh,
-                          hipStream_t s);
+hipError_t cnn_unpack_add(const float* Y, const float* ss, const MgGrid& v, const double* lam,
+                          const float* wx, const float* wy, int m, int nh, hipStream_t s);
 
 }  // namespace aao

@@ -267,7 +267,9 @@ __device__ __forceinline__ void rs_nbr(const RsView& v, const float* re, const f
 // stage 3: g = -B^H dq                                              (into out)
 // stage 4: h = g + W (g / conj(den)) on red points, 0 on black      (adjoint of stage 1)
 // stage 5: dy = W (h / conj(den)) on black points, 0 on red         (adjoint of stage 0)
-// (`in` and `out` alias in stage 1, so neither is restrict-qualified.)
+// stage 6: out = in / (lambda + d)      (the network output scaled by the diagonal)
+// stage 7: out = in / conj(lambda + d)  (adjoint of stage 6)
+// (`in` and `out` alias in stages 1 and 7, so neither is restrict-qualified.)
 __global__ __launch_bounds__(PT) void k_resid(RsView v, int stage, const float* in,
                                               const float* __restrict__ rho, float* out,
                                               const float* __restrict__ rn, float invB,
@@ -313,6 +315,14 @@ __global__ __launch_bounds__(PT) void k_resid(RsView v, int stage, const float* 
       const float gr = ir[p], gi = ii[p];
       orr[p] = -((c * gr + li * gi) - sr);
       oi[p] = -((c * gi - li * gr) - si);
+    } else if (stage == 6) {
+      const float yr = ir[p], yi = ii[p];
+      orr[p] = (yr * c + yi * li) * inv;
+      oi[p] = (yi * c - yr * li) * inv;
+    } else if (stage == 7) {
+      const float gr = ir[p], gi = ii[p];
+      orr[p] = (gr * c - gi * li) * inv;
+      oi[p] = (gi * c + gr * li) * inv;
     }
   }
   if (stage == 2) {
@@ -447,10 +457,12 @@ __global__ void k_pack_input(MgGrid v, const float* __restrict__ ss,
   }
 }
 
-// e[k] += s_k * Y[k] on the valid region
+// e[k] += s_k * Y[k] / (lambda_k + d) on the valid region, d the diagonal of
+// tau K_a (sum of the four face weights wx [m][m+1], wy [m+1][m])
 template <typename T>
 __global__ void k_unpack_add(const float* __restrict__ Y, const float* __restrict__ ss, MgGrid v,
-                             int m, int nh) {
+                             const double* __restrict__ lam, const float* __restrict__ wx,
+                             const float* __restrict__ wy, int m, int nh) {
   const int64_t HW = (int64_t)m * m, total = (int64_t)nh * HW;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -458,9 +470,13 @@ __global__ void k_unpack_add(const float* __restrict__ Y, const float* __restric
     const int p = (int)(e - (int64_t)k * HW);
     const int j = p / m, i = p - j * m;
     const float s = sqrtf(ss[k] / (2.f * (float)HW));
+    const float d = wx[j * (m + 1) + i] + wx[j * (m + 1) + i + 1] + wy[j * m + i] + wy[(j + 1) * m + i];
+    const float c = (float)lam[2 * k] + d, li = (float)lam[2 * k + 1];
+    const float inv = s / (c * c + li * li);
+    const float yr = Y[((int64_t)k * 2 + 0) * HW + p], yi = Y[((int64_t)k * 2 + 1) * HW + p];
     T* q = (T*)v.p + k * v.bstride + (int64_t)j * v.pitch + i;
-    q[0] += (T)(s * Y[((int64_t)k * 2 + 0) * HW + p]);
-    q[v.pstride] += (T)(s * Y[((int64_t)k * 2 + 1) * HW + p]);
+    q[0] += (T)((yr * c + yi * li) * inv);
+    q[v.pstride] += (T)((yi * c - yr * li) * inv);
   }
 }
 
@@ -583,7 +599,8 @@ hipError_t cnn_resid_loss(const float* y, const float* rho, const float* rn, con
   const dim3 grid((unsigned)(B * nchunk)), blk(PT);
   const RsView v{wx, wy, phi, H, W};
   const float invB = 1.0f / (float)B;
-  hipLaunchKernelGGL(k_resid, grid, blk, 0, s, v, 0, y, rho, E, rn, invB, part, nchunk);
+  hipLaunchKernelGGL(k_resid, grid, blk, 0, s, v, 6, y, rho, G, rn, invB, part, nchunk);
+  hipLaunchKernelGGL(k_resid, grid, blk, 0, s, v, 0, G, rho, E, rn, invB, part, nchunk);
   hipLaunchKernelGGL(k_resid, grid, blk, 0, s, v, 1, E, rho, E, rn, invB, part, nchunk);
   hipLaunchKernelGGL(k_resid, grid, blk, 0, s, v, 2, E, rho, Q, rn, invB, part, nchunk);
   hipError_t e = hipGetLastError();
@@ -593,6 +610,7 @@ hipError_t cnn_resid_loss(const float* y, const float* rho, const float* rn, con
   hipLaunchKernelGGL(k_resid, grid, blk, 0, s, v, 3, Q, rho, G, rn, invB, part, nchunk);
   hipLaunchKernelGGL(k_resid_adj, grid, blk, 0, s, v, 4, G, Hb, nchunk);
   hipLaunchKernelGGL(k_resid_adj, grid, blk, 0, s, v, 5, Hb, dy, nchunk);
+  hipLaunchKernelGGL(k_resid, grid, blk, 0, s, v, 7, dy, rho, dy, rn, invB, part, nchunk);
   return hipGetLastError();
 }
 
@@ -634,10 +652,10 @@ hipError_t cnn_pack_input(const MgGrid& v, const float* ss, const float* loga, f
 }
 
 template <typename T>
-hipError_t cnn_unpack_add(const float* Y, const float* ss, const MgGrid& v, int m, int nh,
-                          hipStream_t s) {
+hipError_t cnn_unpack_add(const float* Y, const float* ss, const MgGrid& v, const double* lam,
+                          const float* wx, const float* wy, int m, int nh, hipStream_t s) {
   hipLaunchKernelGGL((k_unpack_add<T>), dim3(grid1((int64_t)nh * m * m)), dim3(256), 0, s, Y, ss,
-                     v, m, nh);
+                     v, lam, wx, wy, m, nh);
   return hipGetLastError();
 }
 
@@ -645,7 +663,8 @@ hipError_t cnn_unpack_add(const float* Y, const float* ss, const MgGrid& v, int 
   template hipError_t cnn_block_sumsq<T>(const MgGrid&, int, int, float*, float*, hipStream_t); \
   template hipError_t cnn_pack_input<T>(const MgGrid&, const float*, const float*, float*, int, \
                                         int, int, hipStream_t);                              \
-  template hipError_t cnn_unpack_add<T>(const float*, const float*, const MgGrid&, int, int,   \
+  template hipError_t cnn_unpack_add<T>(const float*, const float*, const MgGrid&,             \
+                                        const double*, const float*, const float*, int, int,    \
                                         hipStream_t);
 INST(double)
 INST(float)

@@ -99,7 +99,7 @@ def test_residual_loss_gradient_matches_central_differences():
 
 
 def test_residual_loss_of_exact_correction_is_zero():
-    """If y solves B y = rho, the sweep keeps it and the residual loss vanishes."""
+    """If y / (lambda + d) solves B e = rho, the sweep keeps it and the loss vanishes."""
     from oracle import mg
     _, rho, lam, wx, wy = _resid_setup(B=1, H=4, W=4)
     import scipy.sparse as sp
@@ -112,6 +112,9 @@ def test_residual_loss_of_exact_correction_is_zero():
         rows.append(mg.apply_B(e.reshape(H, W), lam[0], wx, wy).reshape(-1))
     Bm = np.array(rows).T
     sol = np.linalg.solve(Bm, (rho[0, 0] + 1j * rho[0, 1]).reshape(-1)).reshape(H, W)
+    # the loss divides the network output by lambda + d: feed the scaled solution
+    from oracle.cnn import _diag
+    sol = sol * (lam[0] + _diag(wx, wy))
     y = np.stack([sol.real, sol.imag])[None]
     assert cnn.residual_loss(y, rho, lam, wx, wy)[0] < 1e-24
 
