@@ -42,6 +42,8 @@ struct aao_ctx {
   double* Foo64[3] = {nullptr, nullptr, nullptr};
   float* Foe32[3] = {nullptr, nullptr, nullptr};
   float* Foo32[3] = {nullptr, nullptr, nullptr};
+  // two-level fold tables [4][P_d/4][P_d/4] (odd m_d, P_d % 128 == 0), else null
+  double* Fq64[3] = {nullptr, nullptr, nullptr};
 
   // spectrum workspace (ping-pong), sized for the current precision
   void* specA = nullptr;
@@ -335,6 +337,12 @@ hipError_t fold_product(aao_ctx* c, int d, const void* in, void* out, double* co
   const double* t1 = divtm ? divtm[0] : nullptr;
   const double* t2 = divtm && g.dim >= 2 ? divtm[1] : nullptr;
   const double* t3 = divtm && g.dim >= 3 ? divtm[2] : nullptr;
+  // the second fold halves the FP64 matrix-core work; with FP32 (twice the
+  // matrix-core rate) the extra loads and barrier of its K loop cost more
+  // than it saves, so FP32 keeps the one-level fold
+  if (c->Fq64[d] && c->prec == AAO_FP64)
+    return launch_dst_fold2<double>((const double*)in, (double*)out, c->Fq64[d], f, d != 0, lam,
+                                    t1, t2, t3, c->stream);
   if (c->prec == AAO_FP64)
     return launch_dst_fold<double>((const double*)in, (double*)out, c->Foe64[d], c->Foo64[d], f,
                                    d != 0, lam, t1, t2, t3, c->stream);
@@ -1010,6 +1018,24 @@ aao_status aao_setup(int dim, int m1, int m2, int m3, int n, double T, double ep
     if ((st = upload(c, &c->Foo64[d], fo)) != AAO_OK) return bail(st);
     if ((st = upload(c, &c->Foe32[d], fe32)) != AAO_OK) return bail(st);
     if ((st = upload(c, &c->Foo32[d], fo32)) != AAO_OK) return bail(st);
+    // second fold (odd m): S_{r, 2t'+b} = (-1)^r S_{r, 2t+b} for the mirror
+    // t' = h-1-t (b = 0) / h-2-t (b = 1); tables A+ A- B+ B- over pair indices
+    if (md % 2 == 1 && P % 128 == 0) {
+      const int Hq = P / 4;
+      std::vector<double> fq((size_t)4 * Hq * Hq, 0.0);
+      for (int q = 0; q < Hq; ++q)
+        for (int t = 0; t < Hq; ++t)
+          for (int b = 0; b < 2; ++b) {
+            const int mir = b ? hh - 2 - t : hh - 1 - t;
+            if (mir < t) continue;
+            const int col = 2 * t + b;
+            const size_t ip = ((size_t)(2 * b) * Hq + q) * Hq + t;      // + table
+            const size_t im = ((size_t)(2 * b + 1) * Hq + q) * Hq + t;  // - table
+            if (2 * q < hh) fq[ip] = S[(size_t)(2 * q) * P + col];
+            if (2 * q + 1 < hh && mir > t) fq[im] = S[(size_t)(2 * q + 1) * P + col];
+          }
+      if ((st = upload(c, &c->Fq64[d], fq)) != AAO_OK) return bail(st);
+    }
   }
   if ((st = ensure_spec(c)) != AAO_OK) return bail(st);
   if ((st = ensure_small(c, 256)) != AAO_OK) return bail(st);

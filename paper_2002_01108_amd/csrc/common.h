@@ -115,6 +115,15 @@ hipError_t launch_dst_fold(const T* in, T* out, const T* Soe, const T* Soo, cons
                            bool left, const double* lam, const double* tmu1, const double* tmu2,
                            const double* tmu3, hipStream_t s);
 
+// Two-level fold for odd m (P_d a multiple of 128): tabs = [4][Hq][Hq], Hq = P_d/4,
+// the quarter tables A+, A-, B+, B- (rows q: output rows 2q for +, 2q+1 for -;
+// columns: pair index t of the even (A) / odd (B) inputs).  Same arguments and
+// result as launch_dst_fold.  Instantiated for FP64.
+template <typename T>
+hipError_t launch_dst_fold2(const T* in, T* out, const T* tabs, const FoldArgs& f, bool left,
+                            const double* lam, const double* tmu1, const double* tmu2,
+                            const double* tmu3, hipStream_t s);
+
 // Shifted divide in the doubly transformed domain:
 // spec[k] <- spec[k] / (lambda_k + sum_d tmu_d[i_d]), complex, pads set to 0.
 hipError_t launch_divide_f64(const Geometry& g, double* spec, const double* lam,

@@ -306,6 +306,282 @@ hipError_t launch_fold_fr(const T* in, T* out, const T* Soe, const T* Soo, const
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------- two-level fold (odd m)
+// For odd m (h = (m+1)/2) the halves fold once more.  With a the even (b = 0)
+// or odd (b = 1) inputs x_{2t+b}, the mirror t' = h-1-t (b = 0) / h-2-t
+// (b = 1) satisfies S_{r, 2t'+b} = (-1)^r S_{r, 2t+b}, so with
+//   u^+-_t = x_{2t} +- x_{2t'},  v^+-_t = x_{2t+1} +- x_{2t'+1}  (t < t'; the
+//   middle t = t' keeps x alone in the + combination)
+// the even rows r = 2q use the + combinations and the odd rows r = 2q+1 the -
+// combinations: O_r = A^{+-}[q] . u^{+-},  E_r = B^{+-}[q] . v^{+-}, four
+// quarter-size products (tables [4][Hq][Hq], Hq = P/4: A+, A-, B+, B-) in
+// place of the two half-size ones, then y_r = O_r + E_r, y_{m-1-r} = O_r - E_r
+// as before.  Block tile: 32 quarter indices (64 rows r) x 64 columns; the
+// four +- combinations of a K slice are formed in registers and staged in one
+// LDS buffer (register prefetch of the next slice).
+constexpr int FQ = 32;
+
+template <typename T, bool LEFT, bool DIVIDE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_dst_fold2(
+    const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ tabs, FoldArgs f,
+    const double* __restrict__ lam, const double* __restrict__ tmu1,
+    const double* __restrict__ tmu2, const double* __restrict__ tmu3) {
+  using V = typename Mf<T>::V;
+  constexpr int NS = FQ / 16;
+  __shared__ T Sd[2][2][2][FBK][FC + PD];   // [pl][par][sign][t][c or row]
+  __shared__ T Ts[4][FBK][FQ + PD];         // [table][t][q]
+  __shared__ double tax[DIVIDE ? 1024 : 1];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int Hq = f.Hp / 2, h = (f.m + 1) / 2;
+
+  int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int nqt = Hq / FQ;
+  const int qt = bid % nqt;
+  bid /= nqt;
+  const int dt = bid % f.ndt;
+  bid /= f.ndt;
+  const int o = bid % f.nout;
+  const int k = bid / f.nout;
+  const int q0 = qt * FQ, d0 = dt * FC;
+  const bool real_pair = f.packed && k == 0;
+  const int64_t base0 = (int64_t)k * 2 * f.PS + (int64_t)o * f.OS;
+  const int64_t base1 = real_pair ? (int64_t)f.nk * 2 * f.PS + (int64_t)o * f.OS : base0 + f.PS;
+
+  // loads: LEFT: wave w = plane w/2, parity w%2, lane = column, e = t offset.
+  // RIGHT: 2 threads per data row; thread half takes t offsets 4 half + e/2 with
+  // parity e%2 (8 contiguous primary inputs, 8 contiguous mirrored ones).
+  const int d_pl = w >> 1;
+  const int r_row = (tid & 127) >> 1, r_half = tid & 1;
+  T xa[8], xb[8], rt_[4];
+  const int t_tab = tid >> 6, t_q = (tid & 63) >> 1, t_t = (tid & 1) * 4;
+
+  auto mirror = [&](int t, int par) { return par ? h - 2 - t : h - 1 - t; };
+  auto fetch = [&](int t0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      rt_[e] = tabs[((int64_t)t_tab * Hq + q0 + t_q) * Hq + t0 + t_t + e];
+    const T* src = in + (d_pl ? base1 : base0);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      int t, par;
+      int64_t pa, pb;
+      if (LEFT) {
+        par = w & 1;
+        t = t0 + e;
+        pa = (int64_t)(2 * t + par) * f.R + d0 + lane;
+      } else {
+        par = e & 1;
+        t = t0 + 4 * r_half + (e >> 1);
+        pa = (int64_t)(d0 + r_row) * f.R + 2 * t + par;
+      }
+      // the mirror input exists only for a proper pair (mirror > t); the
+      // clamped index keeps the address in range either way
+      const int mir = mirror(t, par);
+      const int mc = mir > t ? mir : t;
+      if (LEFT) pb = (int64_t)(2 * mc + par) * f.R + d0 + lane;
+      else pb = (int64_t)(d0 + r_row) * f.R + 2 * mc + par;
+      xa[e] = src[pa];
+      xb[e] = mir > t ? src[pb] : T(0);
+    }
+  };
+
+  V acc[4][2][NS];   // [table][plane][sub-tile]
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < NS; ++c) acc[a][b][c] = V{0, 0, 0, 0};
+
+  if (DIVIDE) {
+    const double* ax_tab = LEFT ? (f.axis == 1 ? tmu2 : tmu3) : tmu1;
+    for (int i = tid; i < 2 * f.Hp; i += 256) tax[i] = ax_tab[i];
+  }
+  const int nk = Hq / FBK;
+  fetch(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int t0 = kt * FBK;
+    __syncthreads();   // every wave is done reading the previous slice
+    // combine: + and - of each pair; the middle keeps x alone in +, beyond-
+    // the-pairs indices contribute zero (their table columns are zero too)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Ts[t_tab][t_t + e][t_q] = rt_[e];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      int lt, par;
+      if (LEFT) { par = w & 1; lt = e; }
+      else { par = e & 1; lt = 4 * r_half + (e >> 1); }
+      const int t = t0 + lt, mir = mirror(t, par);
+      const T a = xa[e], b = xb[e];
+      const int pos = LEFT ? lane : r_row;
+      Sd[d_pl][par][0][lt][pos] = mir >= t ? a + b : T(0);
+      Sd[d_pl][par][1][lt][pos] = mir > t ? a - b : T(0);
+    }
+    __syncthreads();
+    if (kt + 1 < nk) fetch(t0 + FBK);
+#pragma unroll
+    for (int ks = 0; ks < FBK / 4; ++ks) {
+      const int kk = ks * 4 + lk;
+      if (LEFT) {
+        T a[4][NS], b[2][2][2];   // a[table][i], b[pl][par][sign]
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+          for (int i = 0; i < NS; ++i) a[tb][i] = Ts[tb][kk][i * 16 + lr];
+#pragma unroll
+        for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+          for (int par = 0; par < 2; ++par)
+#pragma unroll
+            for (int sg = 0; sg < 2; ++sg) b[pl][par][sg] = Sd[pl][par][sg][kk][w * 16 + lr];
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+          for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+            for (int i = 0; i < NS; ++i)
+              acc[tb][pl][i] = Mf<T>::mfma(a[tb][i], b[pl][tb >> 1][tb & 1], acc[tb][pl][i]);
+      } else {
+        T a[2][2][2], b[4][NS];   // a[pl][par][sign], b[table][j]
+#pragma unroll
+        for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+          for (int par = 0; par < 2; ++par)
+#pragma unroll
+            for (int sg = 0; sg < 2; ++sg) a[pl][par][sg] = Sd[pl][par][sg][kk][w * 16 + lr];
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+          for (int j = 0; j < NS; ++j) b[tb][j] = Ts[tb][kk][j * 16 + lr];
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+          for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+            for (int j = 0; j < NS; ++j)
+              acc[tb][pl][j] = Mf<T>::mfma(a[pl][tb >> 1][tb & 1], b[tb][j], acc[tb][pl][j]);
+      }
+    }
+  }
+
+  // epilogue: row r = 2q + s2 takes tables s2 (O) and 2 + s2 (E);
+  // y_r = O + E, y_{m-1-r} = O - E, optional divide, zero padding
+  const int m = f.m;
+  T* ob0 = out + base0;
+  T* ob1 = out + base1;
+  const double lre = DIVIDE ? lam[2 * k] : 0.0, lim = DIVIDE ? lam[2 * k + 1] : 0.0;
+  const double lre1 = (DIVIDE && real_pair) ? lam[2 * f.nk] : 0.0;
+  double cst[4] = {0.0, 0.0, 0.0, 0.0};
+  if (DIVIDE) {
+    if (LEFT) {
+      const int dl = d0 + w * 16 + lr;
+      const double c0 = f.axis == 1 ? tmu1[dl] + (tmu3 ? tmu3[o] : 0.0)
+                                    : tmu1[dl % f.P1] + tmu2[dl / f.P1];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) cst[v] = c0;
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int dr = d0 + w * 16 + Mf<T>::row(lk, v);
+        cst[v] = tmu2[dr % f.P2] + (tmu3 ? tmu3[dr / f.P2] : 0.0);
+      }
+    }
+  }
+#pragma unroll
+  for (int sub = 0; sub < NS; ++sub) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int q, dpos;
+      if (LEFT) { q = q0 + sub * 16 + Mf<T>::row(lk, v); dpos = d0 + w * 16 + lr; }
+      else { q = q0 + sub * 16 + lr; dpos = d0 + w * 16 + Mf<T>::row(lk, v); }
+      int i1, i2, i3;
+      if (LEFT) {
+        if (f.axis == 1) { i1 = dpos; i2 = 0; i3 = o; }
+        else { i1 = dpos % f.P1; i2 = dpos / f.P1; i3 = 0; }
+      } else {
+        i1 = 0; i2 = dpos % f.P2; i3 = dpos / f.P2;
+      }
+      const bool dvalid = i1 < f.m1 && i2 < f.m2 && i3 < f.m3;
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2) {
+        const int r = 2 * q + s2;
+        if (r >= h) continue;
+        const T ore = acc[s2][0][sub][v], ere = acc[2 + s2][0][sub][v];
+        const T oim = acc[s2][1][sub][v], eim = acc[2 + s2][1][sub][v];
+        const int a_top = r, a_bot = m - 1 - r;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+          const int a = half ? a_bot : a_top;
+          if (half && a_bot <= a_top) break;
+          T vr = half ? ore - ere : ore + ere;
+          T vi = half ? oim - eim : oim + eim;
+          if (!dvalid) {
+            vr = T(0);
+            vi = T(0);
+          } else if (DIVIDE) {
+            const double mu = cst[v] + tax[a];
+            if (real_pair) {
+              vr = vr / (T)(lre + mu);
+              vi = vi / (T)(lre1 + mu);
+            } else {
+              const T cc = (T)(lre + mu), dd = (T)lim;
+              const T inv = T(1) / (cc * cc + dd * dd);
+              const T nr = (vr * cc + vi * dd) * inv;
+              const T ni = (vi * cc - vr * dd) * inv;
+              vr = nr;
+              vi = ni;
+            }
+          }
+          int64_t off;
+          if (LEFT) off = (int64_t)a * f.R + dpos;
+          else off = (int64_t)dpos * f.R + a;
+          ob0[off] = vr;
+          ob1[off] = vi;
+        }
+      }
+    }
+  }
+  if (qt == 0) {
+    const int np = 2 * f.Hp - m, cnt = 2 * np * FC;
+    for (int e = tid; e < cnt; e += 256) {
+      const int pl = e / (np * FC), rem = e % (np * FC);
+      int64_t off;
+      if (LEFT) off = (int64_t)(m + rem / FC) * f.R + d0 + rem % FC;
+      else off = (int64_t)(d0 + rem / np) * f.R + m + rem % np;
+      (pl ? ob1 : ob0)[off] = T(0);
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_fold2(const T* in, T* out, const T* tabs, const FoldArgs& f, bool left,
+                        const double* lam, const double* tmu1, const double* tmu2,
+                        const double* tmu3, hipStream_t s) {
+  const int64_t nblk = (int64_t)(f.Hp / 2 / FQ) * f.ndt * f.nout * f.nk;
+  if (nblk > 0x7fffffff || nblk < 1) return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)nblk), blk(256);
+  const bool div = lam != nullptr;
+  if (left) {
+    if (div)
+      hipLaunchKernelGGL((k_dst_fold2<T, true, true>), grid, blk, 0, s, in, out, tabs, f, lam,
+                         tmu1, tmu2, tmu3);
+    else
+      hipLaunchKernelGGL((k_dst_fold2<T, true, false>), grid, blk, 0, s, in, out, tabs, f, lam,
+                         tmu1, tmu2, tmu3);
+  } else {
+    if (div)
+      hipLaunchKernelGGL((k_dst_fold2<T, false, true>), grid, blk, 0, s, in, out, tabs, f, lam,
+                         tmu1, tmu2, tmu3);
+    else
+      hipLaunchKernelGGL((k_dst_fold2<T, false, false>), grid, blk, 0, s, in, out, tabs, f, lam,
+                         tmu1, tmu2, tmu3);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
 template <typename T>
@@ -318,6 +594,21 @@ hipError_t launch_dst_fold(const T* in, T* out, const T* Soe, const T* Soo, cons
     return launch_fold_fr<T, 64>(in, out, Soe, Soo, f, left, lam, tmu1, tmu2, tmu3, s);
   return launch_fold_fr<T, 32>(in, out, Soe, Soo, f, left, lam, tmu1, tmu2, tmu3, s);
 }
+
+template <typename T>
+hipError_t launch_dst_fold2(const T* in, T* out, const T* tabs, const FoldArgs& f, bool left,
+                            const double* lam, const double* tmu1, const double* tmu2,
+                            const double* tmu3, hipStream_t s) {
+  if (f.m % 2 == 0 || f.Hp % 64 || f.Hp < 64 || (f.m + 1) / 2 > f.Hp || f.ndt < 1 ||
+      f.nout < 1 || f.nk < 1)
+    return hipErrorInvalidValue;
+  return launch_fold2<T>(in, out, tabs, f, left, lam, tmu1, tmu2, tmu3, s);
+}
+
+template hipError_t launch_dst_fold2<double>(const double*, double*, const double*,
+                                             const FoldArgs&, bool, const double*,
+                                             const double*, const double*, const double*,
+                                             hipStream_t);
 
 template hipError_t launch_dst_fold<double>(const double*, double*, const double*, const double*,
                                             const FoldArgs&, bool, const double*, const double*,

@@ -50,6 +50,7 @@ GRIDS = [  # (dim, m1, n, eps): ragged tiles, several tiles, every FFT length cl
     (2, 100, 128, 1.0 / 11),
     (2, 65, 512, 0.05),
     (2, 128, 256, 1.0),
+    (2, 127, 32, 0.15),
     (3, 13, 16, 0.25),
     (3, 20, 64, 0.125),
 ]
