@@ -53,17 +53,37 @@ def parse():
     return ap.parse_args()
 
 
-def dst_flops_per_launch(w, prec):
-    """Algorithmic flops of one DST-I mode product over the n/2+1 kept
-    frequency blocks (2 real planes each), m/m_d vectors of length m_d per plane.
-    2D/3D with an FP64/FP32 preconditioner use the even/odd fold: two
-    h x ceil(m_d/2) and h x floor(m_d/2) products per vector (h = ceil(m_d/2)),
-    2 h m_d flops, so 4 (n/2+1) m h per launch.  Otherwise the dense product,
-    2 m_d^2 flops per vector: 4 (n/2+1) m m_d."""
-    nh = w.n // 2 + 1
+def dst_path(w, prec):
+    """Which DST-I product the library runs: 'fold2' (FP64, odd m, padded
+    length a multiple of 128), 'fold' (2D/3D FP64/FP32 otherwise), 'dense'."""
+    P = -(-w.m1 // 64) * 64
+    if w.dim >= 2 and prec == "fp64" and w.m1 % 2 == 1 and P % 128 == 0:
+        return "fold2"
     if w.dim >= 2 and prec in ("fp64", "fp32"):
-        return 4.0 * nh * w.m * ((w.m1 + 1) // 2)
-    return 4.0 * nh * w.m * w.m1
+        return "fold"
+    return "dense"
+
+
+def dst_flops_per_launch(w, prec):
+    """Algorithmic flops of one DST-I mode product (2 flops per multiply-add of
+    the products the path runs, over valid rows and columns only).  Real
+    vectors of length m_d per launch: n m / m_d on the folded paths (the two
+    real blocks k = 0, n/2 share one block), 2 (n/2+1) m / m_d on the dense one.
+      dense: m_d^2 MACs per vector;
+      fold:  h m_d (h = ceil(m_d/2): an h x ceil(m_d/2) and an h x floor(m_d/2) product);
+      fold2: the four quarter products, rows ceil(h/2) | floor(h/2) and columns
+             ceil(h/2), floor(h/2), ceil((h-1)/2), floor((h-1)/2)."""
+    md = w.m1
+    h = (md + 1) // 2
+    path = dst_path(w, prec)
+    if path == "dense":
+        return 2.0 * md * md * (2 * (w.n // 2 + 1)) * (w.m // md)
+    if path == "fold":
+        macs = h * md
+    else:
+        hp, hm = (h + 1) // 2, h // 2
+        macs = hp * hp + hm * hm + hp * (h // 2) + hm * ((h - 1) // 2)
+    return 2.0 * macs * w.n * (w.m // md)
 
 
 def time_solver(s, fd, u0d, tol, restart, steps, warmup, prof_classes):
@@ -275,19 +295,31 @@ def main():
     value = dof / t_step
 
     dst_ms, dst_n = prof["dst"]
-    folded = w.dim >= 2 and prec in ("fp64", "fp32")
+    path = dst_path(w, prec)
+    folded = path != "dense"
     flops = dst_flops_per_launch(w, prec)
+    nbytes = class_bytes(w, prec)["dst"]
     avg_s = dst_ms / 1e3 / max(dst_n, 1)
-    peak = {"fp64": PEAKS["fp64_TFs"], "fp32": PEAKS["fp32_TFs"],
-            "bf16x3": PEAKS["bf16_TFs"]}[prec]
-    achieved = flops / avg_s / 1e12 if dst_n else None
+    peak_fl = {"fp64": PEAKS["fp64_TFs"], "fp32": PEAKS["fp32_TFs"],
+               "bf16x3": PEAKS["bf16_TFs"]}[prec]
+    # the binding roofline is the one whose ideal time is longer
+    t_mfma = flops / (peak_fl * 1e12)
+    t_hbm = nbytes / (PEAKS["hbm_GBs"] * 1e9)
     traffic = measured_traffic("k_fold.hip", w.name, prec) if folded else None
-    roofline = {"kernel": f"{'dst_fold' if folded else 'dst_gemm'}_{prec} (one DST-I mode product)",
-                "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+    if t_hbm >= t_mfma:
+        achieved = nbytes / avg_s / 1e9 if dst_n else None
+        bound, peak, unit = "hbm", PEAKS["hbm_GBs"], "GB/s"
+    else:
+        achieved = flops / avg_s / 1e12 if dst_n else None
+        bound, peak, unit = "mfma", peak_fl, "TFLOP/s"
+    roofline = {"kernel": f"dst_{path}_{prec} (one DST-I mode product)",
+                "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak if achieved else None, "traffic": traffic,
                 "avg_launch_us": avg_s * 1e6, "launches": dst_n,
-                "flops_per_launch": flops,
-                "algorithmic_bytes_per_launch": class_bytes(w, prec)["dst"]}
+                "flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
+                "mfma_TFLOPs": flops / avg_s / 1e12 if dst_n else None,
+                "mfma_frac": flops / avg_s / 1e12 / peak_fl if dst_n else None,
+                "hbm_GBps": nbytes / avg_s / 1e9 if dst_n else None}
 
     out = {
         "metric": METRIC, "value": value, "unit": "unknowns/s", "n_gpus": 1,
