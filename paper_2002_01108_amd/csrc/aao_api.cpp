@@ -843,6 +843,25 @@ aao_status apply_L(aao_ctx* c, const double* x, double* y) {
 
 int64_t nm_of(const aao_ctx* c) { return (int64_t)c->g.n * c->g.m; }
 
+// Fused stencil passes (2D/3D).  epi 1: ||f - L x||^2 partials; epi 2: y = L x
+// with the partial dots of y and basis[0..q-1].  Partials go to c->part and are
+// reduced (optionally scaled) into dsmall[slot..].
+bool fused_stencil(const aao_ctx* c, int q) { return c->g.dim >= 2 && q <= 8; }
+
+aao_status stencil_fused(aao_ctx* c, int epi, const double* x, double* y, const double* f,
+                         const double* const* basis, int q, int slot, const double* scale) {
+  ProfScope ps(c, AAO_K_KRYLOV);
+  const int64_t nb = stencil_partials(c->g);
+  const int nq = epi == 2 ? q : 1;
+  TRY(ensure_part(c, (size_t)nb * nq));
+  const double* wx = c->var ? c->wface[0] : nullptr;
+  HIPCHK(c, launch_apply_L_epi(c->g, epi, x, y, f, basis, q, c->part, c->cst[0], c->cst[1],
+                               c->cst[2], wx, c->var ? c->wface[1] : nullptr,
+                               c->var ? c->wface[2] : nullptr, c->stream));
+  HIPCHK(c, launch_reduce_partials(c->part, (int)nb, nq, c->dsmall + slot, 0, scale, c->stream));
+  return AAO_OK;
+}
+
 // ||a - b||^2 (b may be null) reduced into dsmall[slot]
 aao_status sqnorm_dev(aao_ctx* c, const double* a, const double* b, int slot) {
   const int64_t len = nm_of(c);
@@ -1441,7 +1460,7 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
   const int o_is2 = 3 * R + 5;
   TRY(ensure_small(c, (size_t)(4 * R + 8)));
   const int nb = krylov_blocks(nm);
-  TRY(ensure_part(c, (size_t)nb * (R + 2)));
+  TRY(ensure_part(c, std::max((size_t)nb * (R + 2), (size_t)stencil_partials(c->g) * 8)));
 
   // ||rhs|| and finiteness
   TRY(sqnorm_dev(c, rhs, nullptr, o_nrm));
@@ -1536,15 +1555,25 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
       double* zj = c->Z + (int64_t)j * nm;
       double* w = c->V + (int64_t)(j + 1) * nm;
       TRY(apply_pinv(c, wj, zj));
-      TRY(apply_L(c, zj, w));
       const int q = j + 1;
       const double* is2 = c->dsmall + o_is2;
       // CGS2 on the unnormalised basis: c1 = (W^T w) / s^2; w -= W c1;
-      // c2 = (W^T w) / s^2; w -= W c2; ||w||^2
+      // c2 = (W^T w) / s^2; w -= W c2; ||w||^2.  The first projection's dots
+      // come out of the stencil pass that forms w = L z (2D/3D, q <= 8).
+      const bool fuse = fused_stencil(c, q);
+      if (fuse) {
+        const double* basis[8];
+        for (int i = 0; i < q; ++i) basis[i] = (i == 0 && v0) ? v0 : c->V + (int64_t)i * nm;
+        TRY(stencil_fused(c, 2, zj, w, nullptr, basis, q, o_h1, is2));
+      } else {
+        TRY(apply_L(c, zj, w));
+      }
       {
         ProfScope ps(c, AAO_K_KRYLOV);
-        HIPCHK(c, launch_multidot(c->V, nm, v0, q, w, nm, c->part, c->stream));
-        HIPCHK(c, launch_reduce_partials(c->part, nb, q, c->dsmall + o_h1, 0, is2, c->stream));
+        if (!fuse) {
+          HIPCHK(c, launch_multidot(c->V, nm, v0, q, w, nm, c->part, c->stream));
+          HIPCHK(c, launch_reduce_partials(c->part, nb, q, c->dsmall + o_h1, 0, is2, c->stream));
+        }
         if (q <= 8) {
           HIPCHK(c, launch_axpy_dot(c->V, nm, v0, q, c->dsmall + o_h1, w, nm, c->part, 1,
                                     c->stream));
@@ -1621,9 +1650,13 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
     if (converged || total >= maxit) break;
   }
   TRY(clear_u());
-  // explicit residual
-  TRY(apply_L(c, u, c->tmp));
-  TRY(sqnorm_dev(c, rhs, c->tmp, o_nrm));
+  // explicit residual ||rhs - L u||
+  if (fused_stencil(c, 1)) {
+    TRY(stencil_fused(c, 1, u, nullptr, rhs, nullptr, 1, o_nrm, nullptr));
+  } else {
+    TRY(apply_L(c, u, c->tmp));
+    TRY(sqnorm_dev(c, rhs, c->tmp, o_nrm));
+  }
   TRY(fetch_small(c, o_nrm, 1));
   const double fres = sqrt(c->hsmall[o_nrm]) / bnorm;
   if (final_res) *final_res = fres;

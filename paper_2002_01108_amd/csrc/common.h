@@ -59,6 +59,17 @@ hipError_t launch_apply_L(const Geometry& g, const double* x, double* y, double 
 hipError_t launch_apply_L_var(const Geometry& g, const double* x, double* y, const double* ax,
                               const double* ay, const double* az, hipStream_t s);
 
+// Fused stencil passes (2D/3D only; AAO dim 1 uses the plain kernel).
+// epi 1: partial sums of (f - L x)^2, one per block, y unused (may be null);
+// epi 2: y = L x and partial dots of y with basis[0..q-1] (q <= 8), q per block.
+// Constant coefficient: c1..c3 with ax = null; variable: ax, ay, az face weights.
+// part must hold stencil_partials(g) * q doubles.
+int64_t stencil_partials(const Geometry& g);
+hipError_t launch_apply_L_epi(const Geometry& g, int epi, const double* x, double* y,
+                              const double* f, const double* const* basis, int q, double* part,
+                              double c1, double c2, double c3, const double* ax,
+                              const double* ay, const double* az, hipStream_t s);
+
 // Step 1: Gamma_eps scaling + forward time DFT (theta = e^{+2 pi i/n}) of a real
 // [n][m] array into split re/im planes spec[k][2][PS], k = 0..n/2.
 // gam[j] = eps^{j/n} / sqrt(n); tw = theta^e, e = 0..n-1.

@@ -97,11 +97,25 @@ __global__ __launch_bounds__(TX * TY) void k_apply_L(
 // x^{k-1} from registers.  Four waves stack in y.
 constexpr int XW = 62;
 
-template <int DIM, bool VAR, int TY, int TC>
+// EPI selects what the block does with L x besides (or instead of) storing it:
+//   0: y = L x;
+//   1: no store; partial sum of (f - L x)^2 per block into part[blockIdx.x]
+//      (the explicit residual norm of a solve, without a residual array);
+//   2: y = L x and the partial dot products of y with up to 8 basis vectors
+//      into part[blockIdx.x * q + i] (the first Gram-Schmidt projection of an
+//      Arnoldi step, without re-reading y).
+struct StencilEpi {
+  const double* f;        // EPI 1
+  const double* w[8];     // EPI 2: basis vectors
+  int q;                  // EPI 2: how many
+  double* part;
+};
+
+template <int DIM, bool VAR, int TY, int TC, int EPI>
 __global__ __launch_bounds__(256) void k_apply_L25(
     const double* __restrict__ x, double* __restrict__ y, int n, int m1, int m2, int m3, int nxt,
     int nyt, int nct, double c1, double c2, double c3, const double* __restrict__ ax,
-    const double* __restrict__ ay, const double* __restrict__ az) {
+    const double* __restrict__ ay, const double* __restrict__ az, StencilEpi ep) {
   const int nblk = nxt * nyt * m3 * nct;
   int b = xcd_remap(blockIdx.x, nblk);
   const int bx = b % nxt; b /= nxt;
@@ -113,7 +127,11 @@ __global__ __launch_bounds__(256) void k_apply_L25(
   const bool inx = i1 >= 0 && i1 < m1;
   const bool writer = lane >= 1 && lane <= XW && inx;
   const int j0 = (by * 4 + wave) * TY;
-  if (j0 >= m2) return;
+  // a wave past the last row has nothing to do, but stays for the block reduction
+  const bool wave_on = j0 < m2;
+  double red_acc[EPI == 2 ? 8 : 1];
+#pragma unroll
+  for (int i = 0; i < (EPI == 2 ? 8 : 1); ++i) red_acc[i] = 0.0;
   const int64_t m = (int64_t)m1 * m2 * m3;
   const int64_t pl = (int64_t)m1 * m2;
   const int64_t base = (int64_t)i3 * pl + i1;
@@ -148,7 +166,7 @@ __global__ __launch_bounds__(256) void k_apply_L25(
   const bool zlo = DIM >= 3 && i3 > 0, zhi = DIM >= 3 && i3 < m3 - 1;
 
   const int k0 = bc * TC;
-  const int k1 = min(n, k0 + TC);
+  const int k1 = wave_on ? min(n, k0 + TC) : k0;
   double prev[TY];
 #pragma unroll
   for (int t = 0; t < TY; ++t) {
@@ -180,31 +198,80 @@ __global__ __launch_bounds__(256) void k_apply_L25(
       double acc = dg[t] * c - wxm[t] * left - wxp[t] * right - wym[t] * r[t] -
                    wyp[t] * r[t + 2] - prev[t];
       if (DIM >= 3) acc -= wzm[t] * zl[t] + wzp[t] * zh[t];
-      if (writer && j0 + t < m2) yk[(int64_t)(j0 + t) * m1] = acc;
+      const bool out_ok = writer && j0 + t < m2;
+      const int64_t off = (int64_t)k * m + base + (int64_t)(j0 + t) * m1;
+      if (EPI != 1 && out_ok) yk[(int64_t)(j0 + t) * m1] = acc;
+      if (EPI == 1 && out_ok) {
+        const double d = ep.f[off] - acc;
+        red_acc[0] += d * d;
+      }
+      if (EPI == 2 && out_ok) {
+        // one basis load at a time keeps the register window of the rows small
+#pragma unroll 1
+        for (int i = 0; i < ep.q; ++i) {
+          const double wv = ep.w[i][off] * acc;
+          switch (i) {
+            case 0: red_acc[0] += wv; break;
+            case 1: red_acc[1] += wv; break;
+            case 2: red_acc[2] += wv; break;
+            case 3: red_acc[3] += wv; break;
+            case 4: red_acc[4] += wv; break;
+            case 5: red_acc[5] += wv; break;
+            case 6: red_acc[6] += wv; break;
+            default: red_acc[7] += wv; break;
+          }
+        }
+      }
       prev[t] = c;
     }
   }
+  if (EPI != 0) {
+    // block reduction: wave sums, then one value per output from LDS
+    constexpr int NQ = EPI == 2 ? 8 : 1;
+    __shared__ double red[NQ][4];
+    const int nq = EPI == 2 ? ep.q : 1;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      if (i >= nq) break;
+      double v = red_acc[i];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+      if (lane == 0) red[i][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < nq)
+      ep.part[(int64_t)blockIdx.x * nq + threadIdx.x] =
+          red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+  }
 }
 
-template <int DIM, bool VAR>
+constexpr int TY25 = 8, TC25 = 8;
+
+int64_t blocks25(const Geometry& g) {
+  const int nxt = (g.m1 + XW - 1) / XW;
+  const int nyt = (g.m2 + 4 * TY25 - 1) / (4 * TY25);
+  const int nct = (g.n + TC25 - 1) / TC25;
+  return (int64_t)nxt * nyt * g.m3 * nct;
+}
+
+template <int DIM, bool VAR, int EPI>
 hipError_t launch25(const Geometry& g, const double* x, double* y, double c1, double c2,
                     double c3, const double* ax, const double* ay, const double* az,
-                    hipStream_t s) {
-  constexpr int TY = 8, TC = 8;
+                    const StencilEpi& ep, hipStream_t s) {
   const int nxt = (g.m1 + XW - 1) / XW;
-  const int nyt = (g.m2 + 4 * TY - 1) / (4 * TY);
-  const int nct = (g.n + TC - 1) / TC;
-  const int64_t nblk = (int64_t)nxt * nyt * g.m3 * nct;
+  const int nyt = (g.m2 + 4 * TY25 - 1) / (4 * TY25);
+  const int nct = (g.n + TC25 - 1) / TC25;
+  const int64_t nblk = blocks25(g);
   if (nblk <= 0 || nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_apply_L25<DIM, VAR, TY, TC>), dim3((unsigned)nblk), dim3(256), 0, s, x, y,
-                     g.n, g.m1, g.m2, g.m3, nxt, nyt, nct, c1, c2, c3, ax, ay, az);
+  hipLaunchKernelGGL((k_apply_L25<DIM, VAR, TY25, TC25, EPI>), dim3((unsigned)nblk), dim3(256), 0,
+                     s, x, y, g.n, g.m1, g.m2, g.m3, nxt, nyt, nct, c1, c2, c3, ax, ay, az, ep);
   return hipGetLastError();
 }
 
 template <int DIM, bool VAR>
 hipError_t launch(const Geometry& g, const double* x, double* y, double c1, double c2, double c3,
                   const double* ax, const double* ay, const double* az, hipStream_t s) {
-  if (DIM >= 2) return launch25<DIM, VAR>(g, x, y, c1, c2, c3, ax, ay, az, s);
+  if (DIM >= 2) return launch25<DIM, VAR, 0>(g, x, y, c1, c2, c3, ax, ay, az, StencilEpi{}, s);
   const int nbx = (g.m1 + TX - 1) / TX;
   const int nby = (g.m2 + TY - 1) / TY;
   const int nbt = (g.n + TCHUNK - 1) / TCHUNK;
@@ -225,6 +292,30 @@ hipError_t launch_apply_L(const Geometry& g, const double* x, double* y, double 
     case 3: return launch<3, false>(g, x, y, c1, c2, c3, nullptr, nullptr, nullptr, s);
   }
   return hipErrorInvalidValue;
+}
+
+int64_t stencil_partials(const Geometry& g) { return g.dim >= 2 ? blocks25(g) : 0; }
+
+hipError_t launch_apply_L_epi(const Geometry& g, int epi, const double* x, double* y,
+                              const double* f, const double* const* basis, int q, double* part,
+                              double c1, double c2, double c3, const double* ax,
+                              const double* ay, const double* az, hipStream_t s) {
+  if (g.dim < 2 || (epi == 2 && (q < 1 || q > 8)) || (epi != 1 && epi != 2))
+    return hipErrorInvalidValue;
+  StencilEpi ep{};
+  ep.f = f;
+  ep.q = epi == 2 ? q : 1;
+  for (int i = 0; i < 8; ++i) ep.w[i] = (epi == 2 && i < q) ? basis[i] : nullptr;
+  ep.part = part;
+  const bool var = ax != nullptr;
+#define L25(D, V, E) launch25<D, V, E>(g, x, y, c1, c2, c3, ax, ay, az, ep, s)
+  if (g.dim == 2) {
+    if (var) return epi == 1 ? L25(2, true, 1) : L25(2, true, 2);
+    return epi == 1 ? L25(2, false, 1) : L25(2, false, 2);
+  }
+  if (var) return epi == 1 ? L25(3, true, 1) : L25(3, true, 2);
+  return epi == 1 ? L25(3, false, 1) : L25(3, false, 2);
+#undef L25
 }
 
 hipError_t launch_apply_L_var(const Geometry& g, const double* x, double* y, const double* ax,
