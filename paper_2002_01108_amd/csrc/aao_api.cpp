@@ -1575,25 +1575,35 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
           HIPCHK(c, launch_reduce_partials(c->part, nb, q, c->dsmall + o_h1, 0, is2, c->stream));
         }
         if (q <= 8) {
+          // w' = w - W c1 with the dots W^T w' and ||w'||^2 in the same pass;
+          // the second correction w'' = w' - W c2 is applied only if another
+          // Arnoldi step follows, and ||w''||^2 = ||w'||^2 - sum_i c2_i^2 s_i^2
+          // (W_i orthogonal) needs no pass of its own
           HIPCHK(c, launch_axpy_dot(c->V, nm, v0, q, c->dsmall + o_h1, w, nm, c->part, 1,
                                     c->stream));
           HIPCHK(c, launch_reduce_partials(c->part, nb, q, c->dsmall + o_h2, 0, is2, c->stream));
+          HIPCHK(c, launch_reduce_partials(c->part + (int64_t)nb * q, nb, 1, c->dsmall + o_n2, 0,
+                                           nullptr, c->stream));
         } else {
           HIPCHK(c, launch_axpy_dot(c->V, nm, v0, q, c->dsmall + o_h1, w, nm, c->part, 0,
                                     c->stream));
           HIPCHK(c, launch_multidot(c->V, nm, v0, q, w, nm, c->part, c->stream));
           HIPCHK(c, launch_reduce_partials(c->part, nb, q, c->dsmall + o_h2, 0, is2, c->stream));
+          HIPCHK(c, launch_axpy_dot(c->V, nm, v0, q, c->dsmall + o_h2, w, nm, c->part, 2,
+                                    c->stream));
+          HIPCHK(c, launch_reduce_partials(c->part, nb, 1, c->dsmall + o_n2, 0, nullptr,
+                                           c->stream));
         }
-        HIPCHK(c, launch_axpy_dot(c->V, nm, v0, q, c->dsmall + o_h2, w, nm, c->part, 2,
-                                  c->stream));
-        HIPCHK(c, launch_reduce_partials(c->part, nb, 1, c->dsmall + o_n2, 0, nullptr,
-                                         c->stream));
       }
       TRY(fetch_small(c, 0, o_n2 + 1));
-      // H in the orthonormal basis: h_ij = (c1_i + c2_i) s_i / s_j, h_{j+1,j} = ||w|| / s_j
+      // H in the orthonormal basis: h_ij = (c1_i + c2_i) s_i / s_j, h_{j+1,j} = ||w''|| / s_j
       for (int i = 0; i < q; ++i)
         H[(size_t)i * R + j] = (c->hsmall[o_h1 + i] + c->hsmall[o_h2 + i]) * sc[i] / sc[j];
-      const double wn = sqrt(std::max(c->hsmall[o_n2], 0.0));
+      double wn2 = c->hsmall[o_n2];
+      const bool deferred = q <= 8;   // second correction not yet applied
+      if (deferred)
+        for (int i = 0; i < q; ++i) wn2 -= c->hsmall[o_h2 + i] * c->hsmall[o_h2 + i] * sc[i] * sc[i];
+      const double wn = sqrt(std::max(wn2, 0.0));
       if (!isfinite(wn)) {
         TRY(clear_u());
         return fail(c, AAO_ENAN, "Arnoldi vector is not finite");
@@ -1624,6 +1634,11 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
       if (converged || total >= maxit) {
         stop = true;
         break;
+      }
+      if (deferred) {
+        ProfScope ps(c, AAO_K_KRYLOV);
+        HIPCHK(c, launch_axpy_dot(c->V, nm, v0, q, c->dsmall + o_h2, w, nm, c->part, 0,
+                                  c->stream));
       }
       if (!in_range(wn)) {
         HIPCHK(c, launch_scale_host(w, w, nm, 1.0 / wn, c->stream));

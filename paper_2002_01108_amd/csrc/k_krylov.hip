@@ -74,13 +74,15 @@ __global__ __launch_bounds__(KT) void k_multidot(const double* __restrict__ V, i
 }
 
 // w -= sum_{i<q} h_i V_i; then MODE 1: partial dots of V_0..V_{Q-1} with the
-// new w (requires q == Q);  MODE 2: partial ||w||^2;  MODE 0: nothing.
+// new w (requires q == Q) into part[b*Q + i] and its partial squared norm into
+// part[gridDim.x*Q + b];  MODE 2: partial ||w||^2;  MODE 0: nothing.
 template <int Q, int MODE>
 __global__ __launch_bounds__(KT) void k_axpy(const double* __restrict__ V, int64_t ldv,
                                              const double* __restrict__ v0, int q,
                                              const double* __restrict__ h, double* __restrict__ w,
                                              int64_t len, double* __restrict__ part) {
   double acc[Q];
+  double nrm[1] = {0.0};
 #pragma unroll
   for (int i = 0; i < Q; ++i) acc[i] = 0.0;
   const int64_t npair = len >> 1;
@@ -93,6 +95,7 @@ __global__ __launch_bounds__(KT) void k_axpy(const double* __restrict__ V, int64
     if (MODE == 1) {
 #pragma unroll
       for (int i = 0; i < Q; ++i) acc[i] += basis(V, ldv, v0, i)[idx] * s;
+      nrm[0] += s * s;
     } else if (MODE == 2) {
       acc[0] += s * s;
     }
@@ -113,12 +116,17 @@ __global__ __launch_bounds__(KT) void k_axpy(const double* __restrict__ V, int64
         const double2 v = reinterpret_cast<const double2*>(basis(V, ldv, v0, i))[e];
         acc[i] += v.x * wv.x + v.y * wv.y;
       }
+      nrm[0] += wv.x * wv.x + wv.y * wv.y;
     } else if (MODE == 2) {
       acc[0] += wv.x * wv.x + wv.y * wv.y;
     }
   }
   if ((len & 1) && blockIdx.x == 0 && threadIdx.x == 0) body(w[len - 1], len - 1);
   if (MODE != 0) block_store<Q>(acc, part, MODE == 1 ? Q : 1, 0);
+  if (MODE == 1) {
+    __syncthreads();   // block_store's LDS is reused
+    block_store<1>(nrm, part + (int64_t)gridDim.x * Q, 1, 0);
+  }
 }
 
 // out[i] (+)= scale_i * sum_b part[b*q + i] (scale_i = 1 when scale is null),
