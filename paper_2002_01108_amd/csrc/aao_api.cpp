@@ -846,7 +846,7 @@ int64_t nm_of(const aao_ctx* c) { return (int64_t)c->g.n * c->g.m; }
 // Fused stencil passes (2D/3D).  epi 1: ||f - L x||^2 partials; epi 2: y = L x
 // with the partial dots of y and basis[0..q-1].  Partials go to c->part and are
 // reduced (optionally scaled) into dsmall[slot..].
-bool fused_stencil(const aao_ctx* c, int q) { return c->g.dim >= 2 && q <= 8; }
+bool fused_stencil(const aao_ctx* c, int q) { return c->g.dim >= 2 && q <= kStencilDotsMax; }
 
 aao_status stencil_fused(aao_ctx* c, int epi, const double* x, double* y, const double* f,
                          const double* const* basis, int q, int slot, const double* scale) {
@@ -1562,7 +1562,7 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
       // come out of the stencil pass that forms w = L z (2D/3D, q <= 8).
       const bool fuse = fused_stencil(c, q);
       if (fuse) {
-        const double* basis[8];
+        const double* basis[kStencilDotsMax];
         for (int i = 0; i < q; ++i) basis[i] = (i == 0 && v0) ? v0 : c->V + (int64_t)i * nm;
         TRY(stencil_fused(c, 2, zj, w, nullptr, basis, q, o_h1, is2));
       } else {

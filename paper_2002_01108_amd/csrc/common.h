@@ -61,9 +61,11 @@ hipError_t launch_apply_L_var(const Geometry& g, const double* x, double* y, con
 
 // Fused stencil passes (2D/3D only; AAO dim 1 uses the plain kernel).
 // epi 1: partial sums of (f - L x)^2, one per block, y unused (may be null);
-// epi 2: y = L x and partial dots of y with basis[0..q-1] (q <= 8), q per block.
+// epi 2: y = L x and partial dots of y with basis[0..q-1] (q <= kStencilDotsMax),
+// q per block.
 // Constant coefficient: c1..c3 with ax = null; variable: ax, ay, az face weights.
 // part must hold stencil_partials(g) * q doubles.
+constexpr int kStencilDotsMax = 4;
 int64_t stencil_partials(const Geometry& g);
 hipError_t launch_apply_L_epi(const Geometry& g, int epi, const double* x, double* y,
                               const double* f, const double* const* basis, int q, double* part,

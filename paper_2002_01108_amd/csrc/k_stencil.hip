@@ -101,17 +101,16 @@ constexpr int XW = 62;
 //   0: y = L x;
 //   1: no store; partial sum of (f - L x)^2 per block into part[blockIdx.x]
 //      (the explicit residual norm of a solve, without a residual array);
-//   2: y = L x and the partial dot products of y with up to 8 basis vectors
-//      into part[blockIdx.x * q + i] (the first Gram-Schmidt projection of an
+//   2: y = L x and the partial dot products of y with Q (<= 4) basis vectors
+//      into part[blockIdx.x * Q + i] (the first Gram-Schmidt projection of an
 //      Arnoldi step, without re-reading y).
 struct StencilEpi {
   const double* f;        // EPI 1
-  const double* w[8];     // EPI 2: basis vectors
-  int q;                  // EPI 2: how many
+  const double* w[4];     // EPI 2: basis vectors
   double* part;
 };
 
-template <int DIM, bool VAR, int TY, int TC, int EPI>
+template <int DIM, bool VAR, int TY, int TC, int EPI, int Q>
 __global__ __launch_bounds__(256) void k_apply_L25(
     const double* __restrict__ x, double* __restrict__ y, int n, int m1, int m2, int m3, int nxt,
     int nyt, int nct, double c1, double c2, double c3, const double* __restrict__ ax,
@@ -129,9 +128,10 @@ __global__ __launch_bounds__(256) void k_apply_L25(
   const int j0 = (by * 4 + wave) * TY;
   // a wave past the last row has nothing to do, but stays for the block reduction
   const bool wave_on = j0 < m2;
-  double red_acc[EPI == 2 ? 8 : 1];
+  constexpr int NQ = EPI == 2 ? Q : 1;
+  double red_acc[NQ];
 #pragma unroll
-  for (int i = 0; i < (EPI == 2 ? 8 : 1); ++i) red_acc[i] = 0.0;
+  for (int i = 0; i < NQ; ++i) red_acc[i] = 0.0;
   const int64_t m = (int64_t)m1 * m2 * m3;
   const int64_t pl = (int64_t)m1 * m2;
   const int64_t base = (int64_t)i3 * pl + i1;
@@ -189,6 +189,17 @@ __global__ __launch_bounds__(256) void k_apply_L25(
       zl[t] = (ok && zlo) ? xk[(int64_t)j * m1 - pl] : 0.0;
       zh[t] = (ok && zhi) ? xk[(int64_t)j * m1 + pl] : 0.0;
     }
+    // epilogue operands are loaded together with the rows so their latency overlaps
+    double eo[NQ][TY];
+    if (EPI != 0) {
+#pragma unroll
+      for (int t = 0; t < TY; ++t) {
+        const bool ok = writer && j0 + t < m2;
+        const int64_t off = (int64_t)k * m + base + (int64_t)(j0 + t) * m1;
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) eo[i][t] = ok ? (EPI == 1 ? ep.f : ep.w[i])[off] : 0.0;
+      }
+    }
     double* yk = y + (int64_t)k * m + base;
 #pragma unroll
     for (int t = 0; t < TY; ++t) {
@@ -199,48 +210,31 @@ __global__ __launch_bounds__(256) void k_apply_L25(
                    wyp[t] * r[t + 2] - prev[t];
       if (DIM >= 3) acc -= wzm[t] * zl[t] + wzp[t] * zh[t];
       const bool out_ok = writer && j0 + t < m2;
-      const int64_t off = (int64_t)k * m + base + (int64_t)(j0 + t) * m1;
       if (EPI != 1 && out_ok) yk[(int64_t)(j0 + t) * m1] = acc;
       if (EPI == 1 && out_ok) {
-        const double d = ep.f[off] - acc;
+        const double d = eo[0][t] - acc;
         red_acc[0] += d * d;
       }
       if (EPI == 2 && out_ok) {
-        // one basis load at a time keeps the register window of the rows small
-#pragma unroll 1
-        for (int i = 0; i < ep.q; ++i) {
-          const double wv = ep.w[i][off] * acc;
-          switch (i) {
-            case 0: red_acc[0] += wv; break;
-            case 1: red_acc[1] += wv; break;
-            case 2: red_acc[2] += wv; break;
-            case 3: red_acc[3] += wv; break;
-            case 4: red_acc[4] += wv; break;
-            case 5: red_acc[5] += wv; break;
-            case 6: red_acc[6] += wv; break;
-            default: red_acc[7] += wv; break;
-          }
-        }
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) red_acc[i] += eo[i][t] * acc;
       }
       prev[t] = c;
     }
   }
   if (EPI != 0) {
     // block reduction: wave sums, then one value per output from LDS
-    constexpr int NQ = EPI == 2 ? 8 : 1;
     __shared__ double red[NQ][4];
-    const int nq = EPI == 2 ? ep.q : 1;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
-      if (i >= nq) break;
       double v = red_acc[i];
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
       if (lane == 0) red[i][wave] = v;
     }
     __syncthreads();
-    if (threadIdx.x < nq)
-      ep.part[(int64_t)blockIdx.x * nq + threadIdx.x] =
+    if (threadIdx.x < NQ)
+      ep.part[(int64_t)blockIdx.x * NQ + threadIdx.x] =
           red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
   }
 }
@@ -254,7 +248,7 @@ int64_t blocks25(const Geometry& g) {
   return (int64_t)nxt * nyt * g.m3 * nct;
 }
 
-template <int DIM, bool VAR, int EPI>
+template <int DIM, bool VAR, int EPI, int Q = 1>
 hipError_t launch25(const Geometry& g, const double* x, double* y, double c1, double c2,
                     double c3, const double* ax, const double* ay, const double* az,
                     const StencilEpi& ep, hipStream_t s) {
@@ -263,8 +257,8 @@ hipError_t launch25(const Geometry& g, const double* x, double* y, double c1, do
   const int nct = (g.n + TC25 - 1) / TC25;
   const int64_t nblk = blocks25(g);
   if (nblk <= 0 || nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_apply_L25<DIM, VAR, TY25, TC25, EPI>), dim3((unsigned)nblk), dim3(256), 0,
-                     s, x, y, g.n, g.m1, g.m2, g.m3, nxt, nyt, nct, c1, c2, c3, ax, ay, az, ep);
+  hipLaunchKernelGGL((k_apply_L25<DIM, VAR, TY25, TC25, EPI, Q>), dim3((unsigned)nblk), dim3(256),
+                     0, s, x, y, g.n, g.m1, g.m2, g.m3, nxt, nyt, nct, c1, c2, c3, ax, ay, az, ep);
   return hipGetLastError();
 }
 
@@ -300,21 +294,30 @@ hipError_t launch_apply_L_epi(const Geometry& g, int epi, const double* x, doubl
                               const double* f, const double* const* basis, int q, double* part,
                               double c1, double c2, double c3, const double* ax,
                               const double* ay, const double* az, hipStream_t s) {
-  if (g.dim < 2 || (epi == 2 && (q < 1 || q > 8)) || (epi != 1 && epi != 2))
+  if (g.dim < 2 || (epi == 2 && (q < 1 || q > kStencilDotsMax)) || (epi != 1 && epi != 2))
     return hipErrorInvalidValue;
   StencilEpi ep{};
   ep.f = f;
-  ep.q = epi == 2 ? q : 1;
-  for (int i = 0; i < 8; ++i) ep.w[i] = (epi == 2 && i < q) ? basis[i] : nullptr;
+  for (int i = 0; i < 4; ++i) ep.w[i] = (epi == 2 && i < q) ? basis[i] : nullptr;
   ep.part = part;
   const bool var = ax != nullptr;
-#define L25(D, V, E) launch25<D, V, E>(g, x, y, c1, c2, c3, ax, ay, az, ep, s)
-  if (g.dim == 2) {
-    if (var) return epi == 1 ? L25(2, true, 1) : L25(2, true, 2);
-    return epi == 1 ? L25(2, false, 1) : L25(2, false, 2);
+#define L25(D, V, E, Q) launch25<D, V, E, Q>(g, x, y, c1, c2, c3, ax, ay, az, ep, s)
+#define DOTS(D, V)                        \
+  switch (q) {                            \
+    case 1: return L25(D, V, 2, 1);       \
+    case 2: return L25(D, V, 2, 2);       \
+    case 3: return L25(D, V, 2, 3);       \
+    default: return L25(D, V, 2, 4);      \
   }
-  if (var) return epi == 1 ? L25(3, true, 1) : L25(3, true, 2);
-  return epi == 1 ? L25(3, false, 1) : L25(3, false, 2);
+  if (g.dim == 2) {
+    if (epi == 1) return var ? L25(2, true, 1, 1) : L25(2, false, 1, 1);
+    if (var) { DOTS(2, true) }
+    DOTS(2, false)
+  }
+  if (epi == 1) return var ? L25(3, true, 1, 1) : L25(3, false, 1, 1);
+  if (var) { DOTS(3, true) }
+  DOTS(3, false)
+#undef DOTS
 #undef L25
 }
 
