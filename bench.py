@@ -157,13 +157,13 @@ def kernel_table(w, prec, prof):
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-def measured_traffic(kernel_file, workload, prec):
+def measured_traffic(kernel_file, workload, prec, dst_kind):
     """HBM bytes per launch of the DST kernel from the committed rocprofv3
     FETCH_SIZE/WRITE_SIZE summary, if it was taken on the current source of
     that kernel (sha256 recorded in the summary); else None."""
     import hashlib
     import re
-    path = os.path.join(PROFILES, f"pmc_dst_fold_{prec}_{workload}.md")
+    path = os.path.join(PROFILES, f"pmc_dst_{dst_kind}_{prec}_{workload}.md")
     src = os.path.join(ROOT, "paper_2002_01108_amd", "csrc", kernel_file)
     if not (os.path.exists(path) and os.path.exists(src)):
         return None
@@ -305,7 +305,7 @@ def main():
     # the binding roofline is the one whose ideal time is longer
     t_mfma = flops / (peak_fl * 1e12)
     t_hbm = nbytes / (PEAKS["hbm_GBs"] * 1e9)
-    traffic = measured_traffic("k_fold.hip", w.name, prec) if folded else None
+    traffic = measured_traffic("k_fold.hip", w.name, prec, path) if folded else None
     if t_hbm >= t_mfma:
         achieved = nbytes / avg_s / 1e9 if dst_n else None
         bound, peak, unit = "hbm", PEAKS["hbm_GBs"], "GB/s"
