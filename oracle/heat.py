@@ -51,6 +51,24 @@ def stiffness(m1: int, dim: int) -> sp.csr_matrix:
     raise ValueError(dim)
 
 
+def stiffness_rect(ms) -> sp.csr_matrix:
+    """K_h on a rectangular grid of (0,1)^d with ms = (m1[, m2[, m3]]) interior
+    nodes per axis (spacing 1/(m_d+1) along axis d), x fastest: the Kronecker
+    sum of the 1D operators (the 3/5/7-point stencil with per-axis spacing)."""
+    ms = tuple(int(v) for v in ms)
+    Ks = [laplacian_1d(v) for v in ms]
+    Is = [sp.identity(v, format="csr") for v in ms]
+    out = None
+    for d in range(len(ms)):
+        # factors ordered slowest (last axis) to fastest (x)
+        term = None
+        for e in range(len(ms) - 1, -1, -1):
+            f = Ks[e] if e == d else Is[e]
+            term = f if term is None else sp.kron(term, f)
+        out = term if out is None else out + term
+    return out.tocsr()
+
+
 def stiffness_faces(m1: int, dim: int, faces) -> sp.csr_matrix:
     """Flux-form finite-difference discretisation K_a of -div(a grad u)
     (Section 2, the K of eq. (stepsystem) for a variable a(x)):

@@ -291,3 +291,57 @@ def test_bf16x3_fgmres_recovers_fp64(dim, m1, n):
     assert info["status"] == 0
     assert info["final_res"] <= 1e-10
     assert rel(host(u), exact) <= 1e-8
+
+
+# ---------------------------------------------------------------------------
+# rectangular grids: every axis has its own length and spacing 1/(m_d + 1);
+# mixes the one- and two-level folded products (odd/even lengths, paddings of
+# 64 and 128) across the axes
+RECT = [  # (dim, (m1, m2[, m3]), n, eps)
+    (2, (37, 20), 16, 0.2),
+    (2, (101, 65), 8, 0.15),
+    (2, (64, 127), 8, 0.1),
+    (3, (13, 9, 5), 8, 0.25),
+    (3, (65, 20, 33), 4, 0.2),
+]
+
+
+def rect_solver(dim, ms, n, eps, precision="fp64"):
+    from paper_2002_01108_amd import Solver
+    ms = list(ms) + [1] * (3 - len(ms))
+    return Solver(dim, ms[0], n, T=1.0, eps=eps, precision=precision, m2=ms[1], m3=ms[2])
+
+
+@pytest.mark.parametrize("dim,ms,n,eps", RECT)
+def test_rect_apply_A_and_Pinv(dim, ms, n, eps):
+    K = heat.stiffness_rect(ms)
+    m = K.shape[0]
+    tau = 1.0 / n
+    s = rect_solver(dim, ms, n, eps)
+    v = _rand((n, m), 40 + dim)
+    assert rel(host(s.apply_A(dev(v))), heat.apply_L(K, tau, v)) < 1e-12
+    assert rel(host(s.apply_Pinv(dev(v))), heat.apply_Pinv(K, tau, eps, v)) < 1e-11
+
+
+@pytest.mark.parametrize("dim,ms,n,eps", [RECT[1], RECT[4]])
+def test_rect_solve_matches_sequential_be(dim, ms, n, eps):
+    K = heat.stiffness_rect(ms)
+    m = K.shape[0]
+    tau = 1.0 / n
+    s = rect_solver(dim, ms, n, eps)
+    rhs = _rand((n, m), 50 + dim)
+    u, info = s.solve(dev(rhs), tol=1e-12, maxit=50)
+    assert info["status"] == 0
+    assert rel(host(u), heat.sequential_be(K, tau, rhs)) < 1e-10
+
+
+@pytest.mark.parametrize("dim,ms,n,eps", [RECT[1], RECT[3]])
+def test_rect_fp32_Pinv(dim, ms, n, eps):
+    """FP32 preconditioner: backward error against the oracle's P_eps (the
+    forward error also carries cond(P_eps) ~ 1 + 4 d tau / h^2 on white noise)."""
+    K = heat.stiffness_rect(ms)
+    tau = 1.0 / n
+    s = rect_solver(dim, ms, n, eps, precision="fp32")
+    v = _rand((n, K.shape[0]), 60 + dim)
+    z = host(s.apply_Pinv(dev(v)))
+    assert rel(heat.apply_P(K, tau, eps, z), v) < 3e-5

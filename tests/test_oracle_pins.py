@@ -397,3 +397,23 @@ def test_manufactured_source_is_consistent():
     fy = (a(X, Y + d / 2) * (u(X, Y + d, t) - u(X, Y, t)) - a(X, Y - d / 2) * (u(X, Y, t) - u(X, Y - d, t))) / d ** 2
     want = ut - fx - fy
     assert np.allclose(W.manufactured_f(m1, t).reshape(m1, m1), want, atol=1e-5)
+
+
+def test_rectangular_stiffness_eigenvalues_and_square_case():
+    """K_h on a rectangular grid: its eigenvalues are the sums of the 1D FD
+    eigenvalues 4/h_d^2 sin^2(j pi h_d / 2) with each axis' own spacing (closed
+    form), and a square grid reproduces the square-grid operator."""
+    ms = (7, 4, 3)
+    K = heat.stiffness_rect(ms).toarray()
+    got = np.sort(np.linalg.eigvalsh(K))
+    one = [4.0 * (m + 1) ** 2 * np.sin(np.arange(1, m + 1) * np.pi / (2 * (m + 1))) ** 2
+           for m in ms]
+    want = np.sort((one[0][None, None, :] + one[1][None, :, None]
+                    + one[2][:, None, None]).ravel())
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-9)
+    # x fastest: the first coupling is along x with spacing 1/(m1+1)
+    assert K[0, 1] == pytest.approx(-(ms[0] + 1) ** 2)
+    assert K[0, ms[0]] == pytest.approx(-(ms[1] + 1) ** 2)
+    assert K[0, ms[0] * ms[1]] == pytest.approx(-(ms[2] + 1) ** 2)
+    sq = heat.stiffness(5, 2) - heat.stiffness_rect((5, 5))
+    assert abs(sq).max() < 1e-9
