@@ -42,8 +42,10 @@ struct aao_ctx {
   double* Foo64[3] = {nullptr, nullptr, nullptr};
   float* Foe32[3] = {nullptr, nullptr, nullptr};
   float* Foo32[3] = {nullptr, nullptr, nullptr};
-  // two-level fold tables [4][P_d/4][P_d/4] (odd m_d, P_d % 128 == 0), else null
+  // two-level fold tables [4][P_d/4][P_d/4] (odd m_d, P_d % 128 == 0), else null,
+  // and their transposes [table][t][q] for the fused forward-divide-inverse kernel
   double* Fq64[3] = {nullptr, nullptr, nullptr};
+  double* FqT64[3] = {nullptr, nullptr, nullptr};
 
   // spectrum workspace (ping-pong), sized for the current precision
   void* specA = nullptr;
@@ -297,9 +299,7 @@ hipError_t run_time_inv(aao_ctx* c, const void* spec, double* z) {
 // `divtm` the shifted divide by lambda_k + sum_d divtm_d runs in its epilogue.
 bool use_fold(const aao_ctx* c) { return c->g.dim >= 2 && c->prec != AAO_BF16X3; }
 
-hipError_t fold_product(aao_ctx* c, int d, const void* in, void* out, double* const* divtm,
-                        bool real_ends) {
-  ProfScope ps(c, AAO_K_DST);
+FoldArgs fold_args(const aao_ctx* c, int d, bool real_ends) {
   const Geometry& g = c->g;
   FoldArgs f;
   f.PS = g.PS;
@@ -333,6 +333,34 @@ hipError_t fold_product(aao_ctx* c, int d, const void* in, void* out, double* co
     f.R = (int64_t)g.P2 * g.P1;
     f.ndt = g.P2 * g.P1 / 64;
   }
+  return f;
+}
+
+// The fused forward-divide-inverse kernel applies along the last axis when it
+// has the two-level fold tables and a padded length of 128 or 256 (FP64).
+bool use_fused_last(const aao_ctx* c) {
+  const int d = c->g.dim - 1;
+  const int Ps[3] = {c->g.P1, c->g.P2, c->g.P3};
+  return c->g.dim >= 2 && c->prec == AAO_FP64 && c->FqT64[d] && (Ps[d] == 128 || Ps[d] == 256);
+}
+
+hipError_t fused_last(aao_ctx* c, const void* in, void* out, double* const* divtm,
+                      bool real_ends) {
+  ProfScope ps(c, AAO_K_DST);
+  const Geometry& g = c->g;
+  const int d = g.dim - 1;
+  FoldArgs f = fold_args(c, d, real_ends);
+  f.ndt = f.ndt * 64 / 16;   // 16-column tiles
+  return launch_dst_fold2_fused((const double*)in, (double*)out, c->FqT64[d], f, c->lam,
+                                divtm[0], g.dim >= 2 ? divtm[1] : nullptr,
+                                g.dim >= 3 ? divtm[2] : nullptr, c->stream);
+}
+
+hipError_t fold_product(aao_ctx* c, int d, const void* in, void* out, double* const* divtm,
+                        bool real_ends) {
+  ProfScope ps(c, AAO_K_DST);
+  const Geometry& g = c->g;
+  const FoldArgs f = fold_args(c, d, real_ends);
   const double* lam = divtm ? c->lam : nullptr;
   const double* t1 = divtm ? divtm[0] : nullptr;
   const double* t2 = divtm && g.dim >= 2 ? divtm[1] : nullptr;
@@ -428,12 +456,17 @@ aao_status dst_solve(aao_ctx* c, void** cur, void** other, bool mean, bool real_
   const int dim = c->g.dim;
   if (use_fold(c)) {
     double* const* tm = mean ? c->tmu_mean : c->tmu;
+    const bool fuse = use_fused_last(c);
     for (int d = 0; d < dim; ++d) {
+      if (fuse && d == dim - 1) break;
       HIPCHK(c, fold_product(c, d, *cur, *other, d == dim - 1 ? tm : nullptr, real_ends));
       std::swap(*cur, *other);
     }
     for (int d = dim - 1; d >= 0; --d) {
-      HIPCHK(c, fold_product(c, d, *cur, *other, nullptr, real_ends));
+      if (fuse && d == dim - 1)
+        HIPCHK(c, fused_last(c, *cur, *other, tm, real_ends));
+      else
+        HIPCHK(c, fold_product(c, d, *cur, *other, nullptr, real_ends));
       std::swap(*cur, *other);
     }
     return AAO_OK;
@@ -1054,6 +1087,12 @@ aao_status aao_setup(int dim, int m1, int m2, int m3, int n, double T, double ep
             if (2 * q + 1 < hh && mir > t) fq[im] = S[(size_t)(2 * q + 1) * P + col];
           }
       if ((st = upload(c, &c->Fq64[d], fq)) != AAO_OK) return bail(st);
+      std::vector<double> fqt(fq.size());
+      for (int tb = 0; tb < 4; ++tb)
+        for (int q = 0; q < Hq; ++q)
+          for (int t = 0; t < Hq; ++t)
+            fqt[((size_t)tb * Hq + t) * Hq + q] = fq[((size_t)tb * Hq + q) * Hq + t];
+      if ((st = upload(c, &c->FqT64[d], fqt)) != AAO_OK) return bail(st);
     }
   }
   if ((st = ensure_spec(c)) != AAO_OK) return bail(st);

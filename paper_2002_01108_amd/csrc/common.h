@@ -137,6 +137,14 @@ hipError_t launch_dst_fold2(const T* in, T* out, const T* tabs, const FoldArgs& 
                             const double* lam, const double* tmu1, const double* tmu2,
                             const double* tmu3, hipStream_t s);
 
+// Forward product, shifted divide and inverse product along one LEFT axis (the
+// last forward axis: y in 2D, z in 3D) in one kernel: FP64, odd m, P_d = 128 or
+// 256, f.ndt = columns / 16.  tt = the two-level fold tables transposed,
+// [4][Hq][Hq] as [table][t][q].  lam and tmu1..tmu3 as for the divide.
+hipError_t launch_dst_fold2_fused(const double* in, double* out, const double* tt,
+                                  const FoldArgs& f, const double* lam, const double* tmu1,
+                                  const double* tmu2, const double* tmu3, hipStream_t s);
+
 // Shifted divide in the doubly transformed domain:
 // spec[k] <- spec[k] / (lambda_k + sum_d tmu_d[i_d]), complex, pads set to 0.
 hipError_t launch_divide_f64(const Geometry& g, double* spec, const double* lam,
@@ -168,9 +176,6 @@ hipError_t launch_axpy_dot(const double* V, int64_t ldv, const double* v0, int q
 // out[i] (+)= scale[i] * sum over blocks (scale may be null: 1)
 hipError_t launch_reduce_partials(const double* part, int nblk, int q, double* out,
                                   int accumulate, const double* scale, hipStream_t s);
-// y = alpha * x  (alpha read from device memory as 1/alpha_ptr[0] if inv != 0)
-hipError_t launch_scale(const double* x, double* y, int64_t len, const double* alpha_dev,
-                        int inv, hipStream_t s);
 // y = alpha * x with alpha a host scalar
 hipError_t launch_scale_host(const double* x, double* y, int64_t len, double alpha, hipStream_t s);
 // x = (set ? 0 : x) + sum_i c_i Z_i with c on device
@@ -179,8 +184,6 @@ hipError_t launch_multi_axpy(const double* Z, int64_t ldz, int q, const double* 
 // partial squared norm of (a - b) (b may be null -> ||a||^2)
 hipError_t launch_diffnorm(const double* a, const double* b, int64_t len, double* part,
                            hipStream_t s);
-// nan/inf count partials
-hipError_t launch_nancheck(const double* a, int64_t len, double* part, hipStream_t s);
 // y = tau*f, y[0:m] += u0
 hipError_t launch_build_rhs(const double* f, const double* u0, double* y, int64_t nm, int64_t m,
                             double tau, hipStream_t s);

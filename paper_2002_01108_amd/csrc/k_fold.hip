@@ -14,6 +14,8 @@
 // Block tile: FR half-indices r x 64 columns (LEFT) or 64 rows x FR r (RIGHT),
 // FR = 64 when P_d/2 allows it (else 32), K slice 8, LDS double buffer, 4 waves
 // of 16 columns (rows) each.  Padding positions are written as zero.
+#include <type_traits>
+
 #include "common.h"
 
 namespace aao {
@@ -582,6 +584,218 @@ hipError_t launch_fold2(const T* in, T* out, const T* tabs, const FoldArgs& f, b
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------- fused y-fwd, divide, y-inv
+// Along the axis of the shifted divide (y in 2D, z in 3D) the forward product,
+// the divide and the inverse product run in one kernel for FP64 with odd m and
+// P = 4 HQ (two-level fold).  A block owns 16 columns (x, or the flattened
+// (y, x) for z) of one plane pair: it stages the whole column tile in LDS, each
+// wave forms the forward quarter products for 16 quarter indices q, and the
+// epilogue of the forward product already yields the inverse product's inputs:
+// the rows 2q and m-1-2q (even pair) and 2q+1 and m-2-2q (odd pair) come out of
+// the same accumulators, so after the divide u+- = y_2q +- y_(m-1-2q) and
+// v+- = y_(2q+1) +- y_(m-2-2q) are formed in registers and stored to LDS in
+// place of the column tile.  The inverse product then reads them directly.
+// Tables are the same quarter tables, transposed ([table][t][q]) so that lanes
+// read consecutive q.
+constexpr int FCF = 16;
+
+template <int HQ>
+__global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(2))) void k_dst_fold2_fused(
+    const double* __restrict__ in, double* __restrict__ out, const double* __restrict__ tt,
+    FoldArgs f, const double* __restrict__ lam, const double* __restrict__ tmu1,
+    const double* __restrict__ tmu2, const double* __restrict__ tmu3) {
+  using V = d4;
+  constexpr int P = 4 * HQ, NT = 64 * (HQ / 16);
+  // column tile X[pl][row][c], later the inverse inputs C[pl][combo][q][c]
+  __shared__ double X[2][P][FCF];
+  __shared__ double tax[P];
+  double (*Cc)[4][HQ][FCF] = reinterpret_cast<double (*)[4][HQ][FCF]>(&X[0][0][0]);
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int m = f.m, h = (m + 1) / 2;
+
+  int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int dt = bid % f.ndt;
+  bid /= f.ndt;
+  const int o = bid % f.nout;
+  const int k = bid / f.nout;
+  const int d0 = dt * FCF, q0 = w * 16;
+  const bool real_pair = f.packed && k == 0;
+  const int64_t base0 = (int64_t)k * 2 * f.PS + (int64_t)o * f.OS;
+  const int64_t base1 = real_pair ? (int64_t)f.nk * 2 * f.PS + (int64_t)o * f.OS : base0 + f.PS;
+
+  // stage the column tile (16 contiguous columns per row, two per thread and
+  // load) and the axis table
+  for (int e = tid; e < P * FCF; e += NT) {
+    const int pl = e / (P * FCF / 2), rem = e % (P * FCF / 2);
+    const int row = rem / (FCF / 2), c = 2 * (rem % (FCF / 2));
+    const double2 v =
+        *reinterpret_cast<const double2*>(in + (pl ? base1 : base0) + (int64_t)row * f.R + d0 + c);
+    X[pl][row][c] = v.x;
+    X[pl][row][c + 1] = v.y;
+  }
+  {
+    const double* ax_tab = f.axis == 1 ? tmu2 : tmu3;
+    for (int i = tid; i < P; i += NT) tax[i] = ax_tab[i];
+  }
+  __syncthreads();
+
+  auto mirror = [&](int t, int par) { return par ? h - 2 - t : h - 1 - t; };
+  V acc[4][2];
+  auto clear = [&]() {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = V{0, 0, 0, 0};
+  };
+  // one quarter product over all t; PHASE 0 forms +- from the raw tile, PHASE 1
+  // reads the stored combinations
+  // table fragments come from L2: a three-slot register ring keeps the loads
+  // two K steps ahead of the matrix-core work
+  auto load_a = [&](int ks, double (&a)[4]) {
+    const int t = 4 * ks + lk;
+#pragma unroll
+    for (int tb = 0; tb < 4; ++tb) a[tb] = tt[((int64_t)tb * HQ + t) * HQ + q0 + lr];
+  };
+  auto product = [&](auto phase_tag) {
+    constexpr int PHASE = decltype(phase_tag)::value;
+    clear();
+    double a0[4], a1[4], a2[4];
+    load_a(0, a0);
+    load_a(1, a1);
+#pragma unroll 1
+    for (int ks = 0; ks < HQ / 4; ++ks) {
+      const int t = 4 * ks + lk;
+      if (ks + 2 < HQ / 4) load_a(ks + 2, a2);
+      double a[4], b[2][2][2];   // a[table], b[pl][par][sign]
+#pragma unroll
+      for (int tb = 0; tb < 4; ++tb) {
+        a[tb] = a0[tb];
+        a0[tb] = a1[tb];
+        a1[tb] = a2[tb];
+      }
+#pragma unroll
+      for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+          if (PHASE == 0) {
+            const int mir = mirror(t, par);
+            const double xa = X[pl][2 * t + par][lr];
+            const double xb = mir > t ? X[pl][2 * (mir > t ? mir : t) + par][lr] : 0.0;
+            b[pl][par][0] = mir >= t ? xa + xb : 0.0;
+            b[pl][par][1] = mir > t ? xa - xb : 0.0;
+          } else {
+            b[pl][par][0] = Cc[pl][2 * par][t][lr];
+            b[pl][par][1] = Cc[pl][2 * par + 1][t][lr];
+          }
+        }
+#pragma unroll
+      for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+        for (int pl = 0; pl < 2; ++pl)
+          acc[tb][pl] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[tb], b[pl][tb >> 1][tb & 1],
+                                                             acc[tb][pl], 0, 0, 0);
+    }
+  };
+
+  // ---- forward product
+  product(std::integral_constant<int, 0>{});
+
+  // column position and the divisor terms that do not depend on the row
+  const int dl = d0 + lr;
+  int i1, i2, i3;
+  if (f.axis == 1) { i1 = dl; i2 = 0; i3 = o; }
+  else { i1 = dl % f.P1; i2 = dl / f.P1; i3 = 0; }
+  const bool dvalid = i1 < f.m1 && i2 < f.m2 && i3 < f.m3;
+  const double cst = f.axis == 1 ? tmu1[dl] + (tmu3 ? tmu3[o] : 0.0)
+                                 : tmu1[dl % f.P1] + tmu2[dl / f.P1];
+  const double lre = lam[2 * k], lim = lam[2 * k + 1];
+  const double lre1 = real_pair ? lam[2 * f.nk] : 0.0;
+  auto divide = [&](double& vr, double& vi, int a) {
+    if (!dvalid) { vr = 0.0; vi = 0.0; return; }
+    const double mu = cst + tax[a];
+    if (real_pair) {
+      vr = vr / (lre + mu);
+      vi = vi / (lre1 + mu);
+    } else {
+      const double cc = lre + mu, dd = lim;
+      const double inv = 1.0 / (cc * cc + dd * dd);
+      const double nr = (vr * cc + vi * dd) * inv;
+      const double ni = (vi * cc - vr * dd) * inv;
+      vr = nr;
+      vi = ni;
+    }
+  };
+  // epilogue -> divide -> inverse inputs, held in registers until the tile is free
+  double cmb[4][2][4];   // [v][plane][combo u+, u-, v+, v-]
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int q = q0 + lk + 4 * v;
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int r = 2 * q + s2;   // s2 = 0: even pair (u), 1: odd pair (v)
+      const int rb = m - 1 - r;
+      double tr = 0.0, ti = 0.0, br = 0.0, bi = 0.0;   // top row r and bottom row rb
+      if (r < h) {
+        const double ore = acc[s2][0][v], ere = acc[2 + s2][0][v];
+        const double oim = acc[s2][1][v], eim = acc[2 + s2][1][v];
+        tr = ore + ere;
+        ti = oim + eim;
+        divide(tr, ti, r);
+        if (rb > r) {
+          br = ore - ere;
+          bi = oim - eim;
+          divide(br, bi, rb);
+        }
+      }
+      // pair (r, rb): + and -; the middle (rb == r) keeps y_r alone in +
+      const bool pair = r < h && rb > r, mid = r < h && rb == r;
+      cmb[v][0][2 * s2] = pair ? tr + br : (mid ? tr : 0.0);
+      cmb[v][0][2 * s2 + 1] = pair ? tr - br : 0.0;
+      cmb[v][1][2 * s2] = pair ? ti + bi : (mid ? ti : 0.0);
+      cmb[v][1][2 * s2 + 1] = pair ? ti - bi : 0.0;
+    }
+  }
+  __syncthreads();   // every wave is done reading the column tile
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) Cc[pl][cb][q0 + lk + 4 * v][lr] = cmb[v][pl][cb];
+  __syncthreads();
+
+  // ---- inverse product and output rows
+  product(std::integral_constant<int, 1>{});
+  double* ob0 = out + base0;
+  double* ob1 = out + base1;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int q = q0 + lk + 4 * v;
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int r = 2 * q + s2, rb = m - 1 - r;
+      if (r >= h) continue;
+      const double ore = acc[s2][0][v], ere = acc[2 + s2][0][v];
+      const double oim = acc[s2][1][v], eim = acc[2 + s2][1][v];
+      const int64_t offt = (int64_t)r * f.R + dl, offb = (int64_t)rb * f.R + dl;
+      ob0[offt] = dvalid ? ore + ere : 0.0;
+      ob1[offt] = dvalid ? oim + eim : 0.0;
+      if (rb > r) {
+        ob0[offb] = dvalid ? ore - ere : 0.0;
+        ob1[offb] = dvalid ? oim - eim : 0.0;
+      }
+    }
+  }
+  // padding rows m .. P-1 of this column tile
+  for (int e = tid; e < 2 * (P - m) * FCF; e += NT) {
+    const int pl = e / ((P - m) * FCF), rem = e % ((P - m) * FCF);
+    (pl ? ob1 : ob0)[(int64_t)(m + rem / FCF) * f.R + d0 + rem % FCF] = 0.0;
+  }
+}
+
 }  // namespace
 
 template <typename T>
@@ -603,6 +817,24 @@ hipError_t launch_dst_fold2(const T* in, T* out, const T* tabs, const FoldArgs& 
       f.nout < 1 || f.nk < 1)
     return hipErrorInvalidValue;
   return launch_fold2<T>(in, out, tabs, f, left, lam, tmu1, tmu2, tmu3, s);
+}
+
+hipError_t launch_dst_fold2_fused(const double* in, double* out, const double* tt,
+                                  const FoldArgs& f, const double* lam, const double* tmu1,
+                                  const double* tmu2, const double* tmu3, hipStream_t s) {
+  const int P = 2 * f.Hp;
+  if (f.m % 2 == 0 || (P != 128 && P != 256) || (f.m + 1) / 2 > f.Hp || f.ndt < 1 ||
+      f.nout < 1 || f.nk < 1 || (f.axis != 1 && f.axis != 2) || !lam)
+    return hipErrorInvalidValue;
+  const int64_t nblk = (int64_t)f.ndt * f.nout * f.nk;
+  if (nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
+  if (P == 256)
+    hipLaunchKernelGGL((k_dst_fold2_fused<64>), dim3((unsigned)nblk), dim3(256), 0, s, in, out, tt,
+                       f, lam, tmu1, tmu2, tmu3);
+  else
+    hipLaunchKernelGGL((k_dst_fold2_fused<32>), dim3((unsigned)nblk), dim3(128), 0, s, in, out, tt,
+                       f, lam, tmu1, tmu2, tmu3);
+  return hipGetLastError();
 }
 
 template hipError_t launch_dst_fold2<double>(const double*, double*, const double*,

@@ -150,9 +150,7 @@ __global__ __launch_bounds__(KT) void k_reduce(const double* __restrict__ part, 
 }
 
 __global__ void k_scale(const double* __restrict__ x, double* __restrict__ y, int64_t len,
-                        double alpha, const double* __restrict__ alpha_dev, int inv) {
-  double a = alpha;
-  if (alpha_dev) a = inv ? 1.0 / alpha_dev[0] : alpha_dev[0];
+                        double a) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < len;
        e += (int64_t)gridDim.x * blockDim.x)
     y[e] = a * x[e];
@@ -180,15 +178,6 @@ __global__ __launch_bounds__(KT) void k_diffnorm(const double* __restrict__ a,
     const double d = b ? a[e] - b[e] : a[e];
     acc[0] += d * d;
   }
-  block_store<1>(acc, part, 1, 0);
-}
-
-__global__ __launch_bounds__(KT) void k_nancheck(const double* __restrict__ a, int64_t len,
-                                                 double* __restrict__ part) {
-  double acc[1] = {0.0};
-  for (int64_t e = blockIdx.x * (int64_t)KT + threadIdx.x; e < len;
-       e += (int64_t)gridDim.x * KT)
-    if (!isfinite(a[e])) acc[0] += 1.0;
   block_store<1>(acc, part, 1, 0);
 }
 
@@ -265,17 +254,9 @@ hipError_t launch_reduce_partials(const double* part, int nblk, int q, double* o
   return hipGetLastError();
 }
 
-hipError_t launch_scale(const double* x, double* y, int64_t len, const double* alpha_dev, int inv,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_scale, dim3(simple_grid(len)), dim3(256), 0, s, x, y, len, 0.0, alpha_dev,
-                     inv);
-  return hipGetLastError();
-}
-
 hipError_t launch_scale_host(const double* x, double* y, int64_t len, double alpha,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_scale, dim3(simple_grid(len)), dim3(256), 0, s, x, y, len, alpha,
-                     (const double*)nullptr, 0);
+  hipLaunchKernelGGL(k_scale, dim3(simple_grid(len)), dim3(256), 0, s, x, y, len, alpha);
   return hipGetLastError();
 }
 
@@ -289,11 +270,6 @@ hipError_t launch_multi_axpy(const double* Z, int64_t ldz, int q, const double* 
 hipError_t launch_diffnorm(const double* a, const double* b, int64_t len, double* part,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_diffnorm, dim3(krylov_blocks(len)), dim3(KT), 0, s, a, b, len, part);
-  return hipGetLastError();
-}
-
-hipError_t launch_nancheck(const double* a, int64_t len, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_nancheck, dim3(krylov_blocks(len)), dim3(KT), 0, s, a, len, part);
   return hipGetLastError();
 }
 
