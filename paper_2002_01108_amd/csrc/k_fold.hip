@@ -331,7 +331,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const double* __restrict__ tmu2, const double* __restrict__ tmu3) {
   using V = typename Mf<T>::V;
   constexpr int NS = FQ / 16;
-  __shared__ T Sd[2][2][2][FBK][FC + PD];   // [pl][par][sign][t][c or row]
+  // RIGHT stores its slice transposed (16 lanes along a row write 16 different
+  // LDS rows); one extra element of padding spreads those rows over the banks
+  constexpr int PDS = LEFT ? PD : PD + 1;
+  __shared__ T Sd[2][2][2][FBK][FC + PDS];   // [pl][par][sign][t][c or row]
   __shared__ T Ts[4][FBK][FQ + PD];         // [table][t][q]
   __shared__ double tax[DIVIDE ? 1024 : 1];
 
@@ -353,10 +356,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int64_t base1 = real_pair ? (int64_t)f.nk * 2 * f.PS + (int64_t)o * f.OS : base0 + f.PS;
 
   // loads: LEFT: wave w = plane w/2, parity w%2, lane = column, e = t offset.
-  // RIGHT: 2 threads per data row; thread half takes t offsets 4 half + e/2 with
-  // parity e%2 (8 contiguous primary inputs, 8 contiguous mirrored ones).
+  // RIGHT: 16 lanes along a data row take the slice's 16 inputs 2 t0 .. 2 t0 + 15
+  // (and the 16 mirrored ones, contiguous in reverse), 4 rows per wave; load e
+  // covers (plane, row) = g + 16 e.
   const int d_pl = w >> 1;
-  const int r_row = (tid & 127) >> 1, r_half = tid & 1;
+  const int r_c = tid & 15, r_g = tid >> 4;
   T xa[8], xb[8], rt_[4];
   const int t_tab = tid >> 6, t_q = (tid & 63) >> 1, t_t = (tid & 1) * 4;
 
@@ -365,26 +369,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
     for (int e = 0; e < 4; ++e)
       rt_[e] = tabs[((int64_t)t_tab * Hq + q0 + t_q) * Hq + t0 + t_t + e];
-    const T* src = in + (d_pl ? base1 : base0);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      int t, par;
+      int t, par, pl;
       int64_t pa, pb;
       if (LEFT) {
+        pl = d_pl;
         par = w & 1;
         t = t0 + e;
         pa = (int64_t)(2 * t + par) * f.R + d0 + lane;
       } else {
-        par = e & 1;
-        t = t0 + 4 * r_half + (e >> 1);
-        pa = (int64_t)(d0 + r_row) * f.R + 2 * t + par;
+        const int idx = r_g + 16 * e;
+        pl = idx >> 6;
+        par = r_c & 1;
+        t = t0 + (r_c >> 1);
+        pa = (int64_t)(d0 + (idx & 63)) * f.R + 2 * t0 + r_c;
       }
       // the mirror input exists only for a proper pair (mirror > t); the
       // clamped index keeps the address in range either way
       const int mir = mirror(t, par);
       const int mc = mir > t ? mir : t;
       if (LEFT) pb = (int64_t)(2 * mc + par) * f.R + d0 + lane;
-      else pb = (int64_t)(d0 + r_row) * f.R + 2 * mc + par;
+      else pb = (int64_t)(d0 + ((r_g + 16 * e) & 63)) * f.R + 2 * mc + par;
+      const T* src = in + (pl ? base1 : base0);
       xa[e] = src[pa];
       xb[e] = mir > t ? src[pb] : T(0);
     }
@@ -413,14 +420,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int e = 0; e < 4; ++e) Ts[t_tab][t_t + e][t_q] = rt_[e];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      int lt, par;
-      if (LEFT) { par = w & 1; lt = e; }
-      else { par = e & 1; lt = 4 * r_half + (e >> 1); }
+      int lt, par, pl, pos;
+      if (LEFT) { par = w & 1; lt = e; pl = d_pl; pos = lane; }
+      else {
+        const int idx = r_g + 16 * e;
+        par = r_c & 1; lt = r_c >> 1; pl = idx >> 6; pos = idx & 63;
+      }
       const int t = t0 + lt, mir = mirror(t, par);
       const T a = xa[e], b = xb[e];
-      const int pos = LEFT ? lane : r_row;
-      Sd[d_pl][par][0][lt][pos] = mir >= t ? a + b : T(0);
-      Sd[d_pl][par][1][lt][pos] = mir > t ? a - b : T(0);
+      Sd[pl][par][0][lt][pos] = mir >= t ? a + b : T(0);
+      Sd[pl][par][1][lt][pos] = mir > t ? a - b : T(0);
     }
     __syncthreads();
     if (kt + 1 < nk) fetch(t0 + FBK);
