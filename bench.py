@@ -64,10 +64,21 @@ def dst_path(w, prec):
     return "dense"
 
 
-def dst_flops_per_launch(w, prec):
+def dst_launch_mix(w, prec):
+    """(launches, products) of the DST class per application of P^{-1}: one
+    product per spatial axis each way, 2 dim in all.  On the two-level fold
+    path with a last-axis padded length of 128 or 256 the last axis' forward
+    product, shifted divide and inverse product run as one launch."""
+    products = 2 * w.dim
+    P = -(-w.m1 // 64) * 64
+    fused = dst_path(w, prec) == "fold2" and P in (128, 256)
+    return products - (1 if fused else 0), products
+
+
+def dst_product_flops(w, prec):
     """Algorithmic flops of one DST-I mode product (2 flops per multiply-add of
     the products the path runs, over valid rows and columns only).  Real
-    vectors of length m_d per launch: n m / m_d on the folded paths (the two
+    vectors of length m_d per product: n m / m_d on the folded paths (the two
     real blocks k = 0, n/2 share one block), 2 (n/2+1) m / m_d on the dense one.
       dense: m_d^2 MACs per vector;
       fold:  h m_d (h = ceil(m_d/2): an h x ceil(m_d/2) and an h x floor(m_d/2) product);
@@ -84,6 +95,13 @@ def dst_flops_per_launch(w, prec):
         hp, hm = (h + 1) // 2, h // 2
         macs = hp * hp + hm * hm + hp * (h // 2) + hm * ((h - 1) // 2)
     return 2.0 * macs * w.n * (w.m // md)
+
+
+def dst_flops_per_launch(w, prec):
+    """Average algorithmic flops per launch of the DST class: the products of
+    one P^{-1} spread over its launches (a fused launch runs two)."""
+    launches, products = dst_launch_mix(w, prec)
+    return dst_product_flops(w, prec) * products / launches
 
 
 def time_solver(s, fd, u0d, tol, restart, steps, warmup, prof_classes):
@@ -312,7 +330,10 @@ def main():
     else:
         achieved = flops / avg_s / 1e12 if dst_n else None
         bound, peak, unit = "mfma", peak_fl, "TFLOP/s"
-    roofline = {"kernel": f"dst_{path}_{prec} (one DST-I mode product)",
+    launches, products = dst_launch_mix(w, prec)
+    mix = (f"{products} DST-I mode products in {launches} launches per P^-1"
+           + (", the last axis' forward, divide and inverse fused" if launches < products else ""))
+    roofline = {"kernel": f"dst_{path}_{prec} ({mix})",
                 "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak if achieved else None, "traffic": traffic,
                 "avg_launch_us": avg_s * 1e6, "launches": dst_n,

@@ -636,19 +636,40 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
   const int64_t base1 = real_pair ? (int64_t)f.nk * 2 * f.PS + (int64_t)o * f.OS : base0 + f.PS;
 
   // stage the column tile (16 contiguous columns per row, two per thread and
-  // load) and the axis table
-  for (int e = tid; e < P * FCF; e += NT) {
+  // load) and the axis table; all loads of a thread are issued before the
+  // first LDS store so that their latencies overlap
+  constexpr int NLD = P * FCF / NT;   // double2 loads per thread (16)
+  double2 xv[NLD];
+#pragma unroll
+  for (int i = 0; i < NLD; ++i) {
+    const int e = tid + i * NT;
     const int pl = e / (P * FCF / 2), rem = e % (P * FCF / 2);
     const int row = rem / (FCF / 2), c = 2 * (rem % (FCF / 2));
-    const double2 v =
-        *reinterpret_cast<const double2*>(in + (pl ? base1 : base0) + (int64_t)row * f.R + d0 + c);
-    X[pl][row][c] = v.x;
-    X[pl][row][c + 1] = v.y;
+    xv[i] = *reinterpret_cast<const double2*>(in + (pl ? base1 : base0) + (int64_t)row * f.R + d0 + c);
+  }
+#pragma unroll
+  for (int i = 0; i < NLD; ++i) {
+    const int e = tid + i * NT;
+    const int pl = e / (P * FCF / 2), rem = e % (P * FCF / 2);
+    const int row = rem / (FCF / 2), c = 2 * (rem % (FCF / 2));
+    X[pl][row][c] = xv[i].x;
+    X[pl][row][c + 1] = xv[i].y;
   }
   {
     const double* ax_tab = f.axis == 1 ? tmu2 : tmu3;
     for (int i = tid; i < P; i += NT) tax[i] = ax_tab[i];
   }
+  // column position and the divisor terms that do not depend on the row
+  // (loaded here, ahead of the forward product)
+  const int dl = d0 + lr;
+  int i1, i2, i3;
+  if (f.axis == 1) { i1 = dl; i2 = 0; i3 = o; }
+  else { i1 = dl % f.P1; i2 = dl / f.P1; i3 = 0; }
+  const bool dvalid = i1 < f.m1 && i2 < f.m2 && i3 < f.m3;
+  const double cst = f.axis == 1 ? tmu1[dl] + (tmu3 ? tmu3[o] : 0.0)
+                                 : tmu1[dl % f.P1] + tmu2[dl / f.P1];
+  const double lre = lam[2 * k], lim = lam[2 * k + 1];
+  const double lre1 = real_pair ? lam[2 * f.nk] : 0.0;
   __syncthreads();
 
   auto mirror = [&](int t, int par) { return par ? h - 2 - t : h - 1 - t; };
@@ -712,16 +733,6 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
   // ---- forward product
   product(std::integral_constant<int, 0>{});
 
-  // column position and the divisor terms that do not depend on the row
-  const int dl = d0 + lr;
-  int i1, i2, i3;
-  if (f.axis == 1) { i1 = dl; i2 = 0; i3 = o; }
-  else { i1 = dl % f.P1; i2 = dl / f.P1; i3 = 0; }
-  const bool dvalid = i1 < f.m1 && i2 < f.m2 && i3 < f.m3;
-  const double cst = f.axis == 1 ? tmu1[dl] + (tmu3 ? tmu3[o] : 0.0)
-                                 : tmu1[dl % f.P1] + tmu2[dl / f.P1];
-  const double lre = lam[2 * k], lim = lam[2 * k + 1];
-  const double lre1 = real_pair ? lam[2 * f.nk] : 0.0;
   auto divide = [&](double& vr, double& vi, int a) {
     if (!dvalid) { vr = 0.0; vi = 0.0; return; }
     const double mu = cst + tax[a];

@@ -12,8 +12,9 @@
 // untangled after the forward transform and re-tangled before the inverse.
 // The FFT is a Stockham autosort sequence of radix-16 (last: smaller) passes;
 // each thread keeps its butterfly's points in registers and the passes
-// exchange through one LDS tile of n x CW complex values.  The first pass of
-// both kernels and the last pass of the inverse go straight to HBM.
+// exchange through one LDS tile of n x CW complex values.  The forward runs its
+// first pass on the values it loaded; the inverse stages the half spectrum in
+// LDS and its last pass goes straight to HBM.
 //
 // Output of Step 1 (input of Step 3) is the split-plane spectrum layout:
 //   spec[k][0][i3][i2][i1] = Re, spec[k][1][i3][i2][i1] = Im, planes padded to
@@ -101,7 +102,8 @@ __device__ __forceinline__ cplx<T> twiddle(const cplx<T>* __restrict__ tw, int e
 }
 
 // One Stockham pass (accumulated length NS -> NS*R) from the LDS tile.
-// Results go back to LDS unless FINAL, in which case sink(index, value) gets them.
+// Results go back to LDS unless FINAL, in which case sink(i0, di, value) gets
+// the one at index i0 + di (di a compile-time multiple of NS, i0 per thread).
 template <typename T, int N, int TH, int SIGN, int NS, bool FINAL, typename Sink>
 __device__ __forceinline__ void lds_pass(cplx<T>* lds, const cplx<T>* __restrict__ tw, int t,
                                          int c, Sink&& sink) {
@@ -119,7 +121,7 @@ __device__ __forceinline__ void lds_pass(cplx<T>* lds, const cplx<T>* __restrict
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const C d = lds[(j + r * NB) * CW + c];
-      v[q][r] = (r == 0) ? d : twiddle<T, SIGN>(tw, (r * e) & (N - 1), d);
+      v[q][r] = (r == 0 || NS == 1) ? d : twiddle<T, SIGN>(tw, (r * e) & (N - 1), d);
     }
   }
   if constexpr (!FINAL) __syncthreads();
@@ -131,7 +133,7 @@ __device__ __forceinline__ void lds_pass(cplx<T>* lds, const cplx<T>* __restrict
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if constexpr (FINAL)
-        sink(idxD + r * NS, v[q][r]);
+        sink(idxD, r * NS, v[q][r]);
       else
         lds[(idxD + r * NS) * CW + c] = v[q][r];
     }
@@ -168,123 +170,213 @@ template <int N, int NS> struct LastNS {
 };
 template <int N> struct LastNS<N, N> { static constexpr int value = N; };
 
+// ---------------------------------------------------------------- strip loop
+// Both kernels are persistent over column strips: the grid holds as many
+// blocks as fit on the chip at once (a multiple of 8), block b runs on XCD
+// b % 8 (round-robin dispatch), and XCD x walks a contiguous range of strips so
+// that neighbouring column segments share its L2.  Each block loads the next
+// strip's inputs into registers while the LDS passes of the current one run.
+struct StripRange {
+  int first, end, step;
+};
+__device__ __forceinline__ StripRange xcd_strips(int nstrip) {
+  const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8, per = gridDim.x / 8;
+  const int q = nstrip / 8, r = nstrip % 8;
+  const int lo = xcd * q + (xcd < r ? xcd : r);
+  return {lo + slot, lo + q + (xcd < r ? 1 : 0), per};
+}
+
 // ---------------------------------------------------------------- forward (Step 1)
 template <typename T, int N, int TH>
-__global__ __launch_bounds__(TH) void k_time_fwd(
+__global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(2))) void k_time_fwd(
     const double* __restrict__ x, T* __restrict__ spec, const T* __restrict__ gam,
     const cplx<T>* __restrict__ tw, int m1, int m2, int m3, int P1, int P2, int64_t PS,
-    int nseg) {
+    int nseg, int nstrip) {
   using C = cplx<T>;
   constexpr int R1 = Cfg<N, TH>::R1, TPC = Cfg<N, TH>::TPC, CW = Cfg<N, TH>::CW;
   __shared__ C lds[N * CW];
+  __shared__ C twl[N];
+  __shared__ T gl[N];
   const int tid = threadIdx.x;
   const int c = tid % CW, t = tid / CW;
-  // neighbouring column segments share cache lines: keep them in one XCD
-  int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int sg = b % nseg;
-  b /= nseg;
-  const int i2 = b % P2;
-  const int i3 = b / P2;
-  // the two real columns of complex column c are i1a and i1a + CW, so every
-  // load and store instruction of a wave covers contiguous addresses
-  const int i1a = sg * 2 * CW + c, i1b = i1a + CW;
-  const bool rowvalid = (i2 < m2) && (i3 < m3);
-  const bool va = rowvalid && i1a < m1;
-  const bool vb = rowvalid && i1b < m1;
   const int64_t m = (int64_t)m1 * m2 * m3;
-  const int64_t xoff = rowvalid ? ((int64_t)i3 * m2 + i2) * m1 + i1a : 0;
-  const int64_t poff = ((int64_t)i3 * P2 + i2) * P1;
-
-  C v[R1];
-#pragma unroll
-  for (int r = 0; r < R1; ++r) {
-    const int j = t + r * TPC;
-    const double* xp = x + (int64_t)j * m + xoff;
-    const T a = va ? (T)xp[0] : T(0);
-    const T bb = vb ? (T)xp[CW] : T(0);
-    const T gj = gam[j];
-    v[r] = {a * gj, bb * gj};
+  for (int j = tid; j < N; j += TH) {
+    gl[j] = gam[j];
+    twl[j] = tw[j];
   }
-  dft<T, R1, +1>(v);
-#pragma unroll
-  for (int r = 0; r < R1; ++r) lds[(t * R1 + r) * CW + c] = v[r];
-  lds_passes_all<T, N, TH, +1, R1>(lds, tw, t, c);
 
-  // untangle: A(k) = (C(k) + conj C(n-k))/2, B(k) = (C(k) - conj C(n-k))/(2i)
-  for (int k = t; k <= N / 2; k += TPC) {
-    const C ck = lds[k * CW + c];
-    const C cn = lds[((N - k) & (N - 1)) * CW + c];
-    const T half = T(0.5);
-    T* pr = spec + (int64_t)k * 2 * PS + poff;
-    T* pi = pr + PS;
-    if (i1a < P1) {
-      pr[i1a] = va ? (ck.x + cn.x) * half : T(0);
-      pi[i1a] = va ? (ck.y - cn.y) * half : T(0);
+  // strip b: column segment sg of spatial row (i2, i3); the two real columns of
+  // complex column c are i1a and i1a + CW, so every load and store instruction
+  // of a wave covers contiguous addresses
+  // The prefetched values stay raw until the next strip starts: a select or
+  // conversion right after the load would make the wave wait for it there.
+  double ra[R1], rb[R1];
+  bool pva = false, pvb = false;   // validity of the prefetched columns
+  auto load = [&](int b) {
+    const int sg = b % nseg, row = b / nseg, i2 = row % P2, i3 = row / P2;
+    const int i1a = sg * 2 * CW + c;
+    const bool rowvalid = (i2 < m2) && (i3 < m3);
+    pva = rowvalid && i1a < m1;
+    pvb = rowvalid && i1a + CW < m1;
+    // Loads are unconditional: lanes outside the grid read a clamped in-range
+    // point, dropped by the select at use.  Addresses are a per-lane base plus
+    // a wave-uniform stride per row, so no per-row 64-bit offset stays live
+    // across strips.
+    const int64_t rowoff = ((int64_t)min(i3, m3 - 1) * m2 + min(i2, m2 - 1)) * m1 + (int64_t)t * m;
+    const double* xa = x + rowoff + min(i1a, m1 - 1);
+    const double* xb = x + rowoff + min(i1a + CW, m1 - 1);
+    const int64_t step = (int64_t)TPC * m;
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      ra[r] = xa[r * step];
+      rb[r] = xb[r * step];
     }
-    if (i1b < P1) {
-      pr[i1b] = vb ? (ck.y + cn.y) * half : T(0);
-      pi[i1b] = vb ? (cn.x - ck.x) * half : T(0);
+  };
+
+  const StripRange sr = xcd_strips(nstrip);
+  if (sr.first < sr.end) load(sr.first);
+  __syncthreads();  // gl, twl
+  for (int b = sr.first; b < sr.end; b += sr.step) {
+    C v[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const T gj = gl[t + r * TPC];
+      v[r] = {pva ? (T)ra[r] * gj : T(0), pvb ? (T)rb[r] * gj : T(0)};
+    }
+    if (b + sr.step < sr.end) load(b + sr.step);
+    dft<T, R1, +1>(v);
+    __syncthreads();  // the previous strip's untangle has read lds
+#pragma unroll
+    for (int r = 0; r < R1; ++r) lds[(t * R1 + r) * CW + c] = v[r];
+    lds_passes_all<T, N, TH, +1, R1>(lds, twl, t, c);
+
+    // untangle: A(k) = (C(k) + conj C(n-k))/2, B(k) = (C(k) - conj C(n-k))/(2i)
+    const int sg = b % nseg, row = b / nseg, i2 = row % P2, i3 = row / P2;
+    const int i1a = sg * 2 * CW + c, i1b = i1a + CW;
+    const bool rowvalid = (i2 < m2) && (i3 < m3);
+    const bool va = rowvalid && i1a < m1, vb = rowvalid && i1b < m1;
+    const int64_t poff = ((int64_t)i3 * P2 + i2) * P1;
+    for (int k = t; k <= N / 2; k += TPC) {
+      const C ck = lds[k * CW + c];
+      const C cn = lds[((N - k) & (N - 1)) * CW + c];
+      const T half = T(0.5);
+      T* pr = spec + (int64_t)k * 2 * PS + poff;
+      T* pi = pr + PS;
+      if (i1a < P1) {
+        pr[i1a] = va ? (ck.x + cn.x) * half : T(0);
+        pi[i1a] = va ? (ck.y - cn.y) * half : T(0);
+      }
+      if (i1b < P1) {
+        pr[i1b] = vb ? (ck.y + cn.y) * half : T(0);
+        pi[i1b] = vb ? (cn.x - ck.x) * half : T(0);
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------- inverse (Step 3)
+// Each spectrum value is loaded once: block k <= n/2 gives C(k) = A(k) + i B(k)
+// and, through A(n-k) = conj A(k), C(n-k) = conj A(k) + i conj B(k); both are
+// staged in LDS, then the Stockham passes run from LDS, the last to HBM.
+// No register cap beyond the launch bound: with 256 threads the kernel runs
+// one wave per SIMD without spilling, which measures faster than two waves
+// with spills (spill reloads share the counter the prefetched loads wait on).
 template <typename T, int N, int TH>
 __global__ __launch_bounds__(TH) void k_time_inv(
     const T* __restrict__ spec, double* __restrict__ z, const T* __restrict__ ginv,
     const cplx<T>* __restrict__ tw, int m1, int m2, int m3, int P1, int P2, int64_t PS,
-    int nseg) {
+    int nseg, int nstrip) {
   using C = cplx<T>;
-  constexpr int R1 = Cfg<N, TH>::R1, TPC = Cfg<N, TH>::TPC, CW = Cfg<N, TH>::CW;
-  __shared__ C lds[(R1 == N) ? 1 : N * CW];
+  constexpr int TPC = Cfg<N, TH>::TPC, CW = Cfg<N, TH>::CW;
+  constexpr int KI = (N / 2) / TPC + 1;  // loads per thread cover k = t + TPC i <= n/2
+  __shared__ C lds[N * CW];
+  __shared__ C twl[N];
+  __shared__ T gl[N];
   const int tid = threadIdx.x;
   const int c = tid % CW, t = tid / CW;
-  // neighbouring column segments share cache lines: keep them in one XCD
-  int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int sg = b % nseg;
-  b /= nseg;
-  const int i2 = b % m2;
-  const int i3 = b / m2;
-  const int i1a = sg * 2 * CW + c, i1b = i1a + CW;   // as in the forward kernel
-  const bool va = i1a < m1;
-  const bool vb = i1b < m1;
   const int64_t m = (int64_t)m1 * m2 * m3;
-  const int64_t zoff = ((int64_t)i3 * m2 + i2) * m1 + i1a;
-  const int64_t poff = ((int64_t)i3 * P2 + i2) * P1;
+  for (int j = tid; j < N; j += TH) {
+    gl[j] = ginv[j];
+    twl[j] = tw[j];
+  }
 
-  // first pass input: C(k) = A(k) + i B(k) over the full range via A(n-k) = conj A(k)
-  C v[R1];
+  // raw prefetched values; selects are applied when the next strip starts
+  T ar[KI], ai[KI], br[KI], bi[KI];
+  bool pva = false, pvb = false;
+  auto load = [&](int b) {
+    const int sg = b % nseg, row = b / nseg, i2 = row % m2, i3 = row / m2;
+    const int i1a = sg * 2 * CW + c;
+    pva = i1a < m1;
+    pvb = i1a + CW < m1;
+    // unconditional loads from clamped in-range addresses (columns past m1,
+    // blocks past n/2); the imaginary planes of blocks 0 and n/2 are read but
+    // never used
+    const int64_t rowoff = ((int64_t)i3 * P2 + i2) * P1 + (int64_t)t * 2 * PS;
+    const T* pa = spec + rowoff + min(i1a, m1 - 1);
+    const T* pb = spec + rowoff + min(i1a + CW, m1 - 1);
+    const int64_t step = (int64_t)TPC * 2 * PS;
 #pragma unroll
-  for (int r = 0; r < R1; ++r) {
-    const int k = t + r * TPC;
-    const bool upper = k > N / 2;
-    const int kk = upper ? N - k : k;
-    const T* pr = spec + (int64_t)kk * 2 * PS + poff;
-    const T* pi = pr + PS;
-    const T ar = va ? pr[i1a] : T(0);
-    const T br = vb ? pr[i1b] : T(0);
-    const bool realblk = (kk == 0) || (kk == N / 2);
-    const T ai = (va && !realblk) ? pi[i1a] : T(0);
-    const T bi = (vb && !realblk) ? pi[i1b] : T(0);
-    v[r] = upper ? C{ar + bi, br - ai} : C{ar - bi, ai + br};
-  }
-  dft<T, R1, -1>(v);
-  auto store = [&](int j, C val) {
-    const T g = ginv[j];
-    double* zp = z + (int64_t)j * m + zoff;
-    if (va) zp[0] = (double)(val.x * g);
-    if (vb) zp[CW] = (double)(val.y * g);
+    for (int i = 0; i < KI; ++i) {
+      // k = t + TPC i <= n/2 always holds except on the last load (t > 0);
+      // keeping the other offsets wave-uniform keeps them out of VGPRs
+      const int64_t o = (i < KI - 1 || t == 0) ? i * step : 0;
+      ar[i] = pa[o];
+      ai[i] = pa[o + PS];
+      br[i] = pb[o];
+      bi[i] = pb[o + PS];
+    }
   };
-  if constexpr (R1 == N) {
+
+  const StripRange sr = xcd_strips(nstrip);
+  if (sr.first < sr.end) load(sr.first);
+  for (int b = sr.first; b < sr.end; b += sr.step) {
+    __syncthreads();  // the previous strip's last pass has read lds
 #pragma unroll
-    for (int r = 0; r < R1; ++r) store(r, v[r]);  // single pass: t == 0, outputs in order
-  } else {
-#pragma unroll
-    for (int r = 0; r < R1; ++r) lds[(t * R1 + r) * CW + c] = v[r];
-    lds_passes_but_last<T, N, TH, -1, R1>(lds, tw, t, c);
-    constexpr int NSL = LastNS<N, R1>::value;
-    lds_pass<T, N, TH, -1, NSL, true>(lds, tw, t, c, store);
+    for (int i = 0; i < KI; ++i) {
+      const int k = t + TPC * i;
+      if (k <= N / 2) {
+        const bool cplxblk = k != 0 && k != N / 2;
+        const T a0 = pva ? ar[i] : T(0), b0 = pvb ? br[i] : T(0);
+        const T a1 = (pva && cplxblk) ? ai[i] : T(0), b1 = (pvb && cplxblk) ? bi[i] : T(0);
+        lds[k * CW + c] = C{a0 - b1, a1 + b0};
+        if (cplxblk) lds[(N - k) * CW + c] = C{a0 + b1, b0 - a1};
+      }
+    }
+    if (b + sr.step < sr.end) load(b + sr.step);
+
+    const int sg = b % nseg, row = b / nseg, i2 = row % m2, i3 = row / m2;
+    const int i1a = sg * 2 * CW + c;
+    const bool va = i1a < m1, vb = i1a + CW < m1;
+    double* zb = z + ((int64_t)i3 * m2 + i2) * m1 + i1a;
+    auto store = [&](int j0, int dj, C val) {
+      const T g = gl[j0 + dj];
+      double* zp = zb + (int64_t)j0 * m + dj * m;
+      if (va) zp[0] = (double)(val.x * g);
+      if (vb) zp[CW] = (double)(val.y * g);
+    };
+    lds_passes_but_last<T, N, TH, -1, 1>(lds, twl, t, c);
+    constexpr int NSL = LastNS<N, 1>::value;
+    lds_pass<T, N, TH, -1, NSL, true>(lds, twl, t, c, store);
   }
+}
+
+// Blocks of one kernel resident on the whole chip at once, rounded down to a
+// multiple of 8 (the strip walk assumes it); -1 if the runtime cannot say.
+template <typename K>
+int persistent_grid(K kernel, int threads) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
+    return -1;
+  const int g = (cus * per_cu) / 8 * 8;
+  return g >= 8 ? g : -1;
+}
+
+// grid for nstrip strips: the resident count, or fewer when there are fewer strips
+inline int strip_grid(int resident, int64_t nstrip) {
+  const int64_t cover = (nstrip + 7) / 8 * 8;
+  return cover < resident ? (int)cover : resident;
 }
 
 template <typename T, int N, int TH>
@@ -292,9 +384,12 @@ hipError_t launch_fwd_n(const Geometry& g, const double* x, T* spec, const T* ga
                         const cplx<T>* tw, hipStream_t s) {
   constexpr int CW = Cfg<N, TH>::CW;
   const int nseg = (g.P1 + 2 * CW - 1) / (2 * CW);
-  const int64_t nblk = (int64_t)nseg * g.P2 * g.P3;
-  hipLaunchKernelGGL((k_time_fwd<T, N, TH>), dim3((unsigned)nblk), dim3(TH), 0, s, x, spec, gam,
-                     tw, g.m1, g.m2, g.m3, g.P1, g.P2, g.PS, nseg);
+  const int64_t ns = (int64_t)nseg * g.P2 * g.P3;
+  if (ns > INT32_MAX) return hipErrorInvalidValue;
+  static const int resident = persistent_grid(k_time_fwd<T, N, TH>, TH);
+  if (resident < 8) return hipErrorInvalidDeviceFunction;
+  hipLaunchKernelGGL((k_time_fwd<T, N, TH>), dim3(strip_grid(resident, ns)), dim3(TH), 0, s,
+                     x, spec, gam, tw, g.m1, g.m2, g.m3, g.P1, g.P2, g.PS, nseg, (int)ns);
   return hipGetLastError();
 }
 
@@ -303,9 +398,12 @@ hipError_t launch_inv_n(const Geometry& g, const T* spec, double* z, const T* gi
                         const cplx<T>* tw, hipStream_t s) {
   constexpr int CW = Cfg<N, TH>::CW;
   const int nseg = (g.m1 + 2 * CW - 1) / (2 * CW);
-  const int64_t nblk = (int64_t)nseg * g.m2 * g.m3;
-  hipLaunchKernelGGL((k_time_inv<T, N, TH>), dim3((unsigned)nblk), dim3(TH), 0, s, spec, z,
-                     ginv, tw, g.m1, g.m2, g.m3, g.P1, g.P2, g.PS, nseg);
+  const int64_t ns = (int64_t)nseg * g.m2 * g.m3;
+  if (ns > INT32_MAX) return hipErrorInvalidValue;
+  static const int resident = persistent_grid(k_time_inv<T, N, TH>, TH);
+  if (resident < 8) return hipErrorInvalidDeviceFunction;
+  hipLaunchKernelGGL((k_time_inv<T, N, TH>), dim3(strip_grid(resident, ns)), dim3(TH), 0, s,
+                     spec, z, ginv, tw, g.m1, g.m2, g.m3, g.P1, g.P2, g.PS, nseg, (int)ns);
   return hipGetLastError();
 }
 
