@@ -616,10 +616,11 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
     const double* __restrict__ tmu2, const double* __restrict__ tmu3) {
   using V = d4;
   constexpr int P = 4 * HQ, NT = 64 * (HQ / 16);
-  // column tile X[pl][row][c], later the inverse inputs C[pl][combo][q][c]
-  __shared__ double X[2][P][FCF];
+  // the operands of one quarter-product pass, Cc[pl][combo][t][c]: combo
+  // 2 par + sign holds x_{2t+par} + x_{2t'+par} (sign 0) or - (sign 1); first
+  // the forward product's inputs, then the inverse product's
+  __shared__ double Cc[2][4][HQ][FCF];
   __shared__ double tax[P];
-  double (*Cc)[4][HQ][FCF] = reinterpret_cast<double (*)[4][HQ][FCF]>(&X[0][0][0]);
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -635,25 +636,35 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
   const int64_t base0 = (int64_t)k * 2 * f.PS + (int64_t)o * f.OS;
   const int64_t base1 = real_pair ? (int64_t)f.nk * 2 * f.PS + (int64_t)o * f.OS : base0 + f.PS;
 
-  // stage the column tile (16 contiguous columns per row, two per thread and
-  // load) and the axis table; all loads of a thread are issued before the
-  // first LDS store so that their latencies overlap
-  constexpr int NLD = P * FCF / NT;   // double2 loads per thread (16)
-  double2 xv[NLD];
+  // Stage the forward product's operands: for quarter index t and parity par
+  // the rows 2t+par and 2t'+par (16 contiguous columns each, two per thread
+  // and load) combine into the + and - operands once here, so the product
+  // loop only reads LDS.  All loads of a thread are issued before the first
+  // LDS store so that their latencies overlap.
+  auto mirror = [&](int t, int par) { return par ? h - 2 - t : h - 1 - t; };
+  constexpr int NST = 2 * 2 * HQ * (FCF / 2) / NT;   // (pl, par, t, column pair) per thread
+  double2 xa[NST], xb[NST];
 #pragma unroll
-  for (int i = 0; i < NLD; ++i) {
-    const int e = tid + i * NT;
-    const int pl = e / (P * FCF / 2), rem = e % (P * FCF / 2);
-    const int row = rem / (FCF / 2), c = 2 * (rem % (FCF / 2));
-    xv[i] = *reinterpret_cast<const double2*>(in + (pl ? base1 : base0) + (int64_t)row * f.R + d0 + c);
+  for (int i = 0; i < NST; ++i) {
+    const int e = tid + i * NT, c2 = e % (FCF / 2), r = e / (FCF / 2);
+    const int t = r % HQ, par = (r / HQ) & 1, pl = r / (2 * HQ);
+    const int mir = mirror(t, par), mc = mir > t ? mir : t;   // in range either way
+    const double* src = in + (pl ? base1 : base0) + d0 + 2 * c2;
+    xa[i] = *reinterpret_cast<const double2*>(src + (int64_t)(2 * t + par) * f.R);
+    xb[i] = *reinterpret_cast<const double2*>(src + (int64_t)(2 * mc + par) * f.R);
   }
 #pragma unroll
-  for (int i = 0; i < NLD; ++i) {
-    const int e = tid + i * NT;
-    const int pl = e / (P * FCF / 2), rem = e % (P * FCF / 2);
-    const int row = rem / (FCF / 2), c = 2 * (rem % (FCF / 2));
-    X[pl][row][c] = xv[i].x;
-    X[pl][row][c + 1] = xv[i].y;
+  for (int i = 0; i < NST; ++i) {
+    const int e = tid + i * NT, c2 = e % (FCF / 2), r = e / (FCF / 2);
+    const int t = r % HQ, par = (r / HQ) & 1, pl = r / (2 * HQ);
+    const int mir = mirror(t, par);
+    // a proper pair gives + and -; the middle (t' = t) keeps x alone in +;
+    // beyond the pairs both are zero (those rows are another t's mirrors)
+    const bool pair = mir > t, mid = mir == t;
+    Cc[pl][2 * par][t][2 * c2] = pair ? xa[i].x + xb[i].x : (mid ? xa[i].x : 0.0);
+    Cc[pl][2 * par][t][2 * c2 + 1] = pair ? xa[i].y + xb[i].y : (mid ? xa[i].y : 0.0);
+    Cc[pl][2 * par + 1][t][2 * c2] = pair ? xa[i].x - xb[i].x : 0.0;
+    Cc[pl][2 * par + 1][t][2 * c2 + 1] = pair ? xa[i].y - xb[i].y : 0.0;
   }
   {
     const double* ax_tab = f.axis == 1 ? tmu2 : tmu3;
@@ -672,7 +683,6 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
   const double lre1 = real_pair ? lam[2 * f.nk] : 0.0;
   __syncthreads();
 
-  auto mirror = [&](int t, int par) { return par ? h - 2 - t : h - 1 - t; };
   V acc[4][2];
   auto clear = [&]() {
 #pragma unroll
@@ -680,58 +690,44 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = V{0, 0, 0, 0};
   };
-  // one quarter product over all t; PHASE 0 forms +- from the raw tile, PHASE 1
-  // reads the stored combinations
-  // table fragments come from L2: a three-slot register ring keeps the loads
-  // two K steps ahead of the matrix-core work
+  // one quarter-product pass over all t from the staged operands; table
+  // fragments come from L2 through a three-slot register ring, loaded two K
+  // steps ahead of the matrix-core work (the loop is unrolled so the ring
+  // slots are fixed registers and no copy waits for a load in flight)
   auto load_a = [&](int ks, double (&a)[4]) {
     const int t = 4 * ks + lk;
 #pragma unroll
     for (int tb = 0; tb < 4; ++tb) a[tb] = tt[((int64_t)tb * HQ + t) * HQ + q0 + lr];
   };
-  auto product = [&](auto phase_tag) {
-    constexpr int PHASE = decltype(phase_tag)::value;
+  auto product = [&]() {
+    constexpr int NK = HQ / 4;
     clear();
-    double a0[4], a1[4], a2[4];
-    load_a(0, a0);
-    load_a(1, a1);
-#pragma unroll 1
-    for (int ks = 0; ks < HQ / 4; ++ks) {
-      const int t = 4 * ks + lk;
-      if (ks + 2 < HQ / 4) load_a(ks + 2, a2);
-      double a[4], b[2][2][2];   // a[table], b[pl][par][sign]
+    double ring[3][4];
+    load_a(0, ring[0]);
+    load_a(1, ring[1]);
 #pragma unroll
-      for (int tb = 0; tb < 4; ++tb) {
-        a[tb] = a0[tb];
-        a0[tb] = a1[tb];
-        a1[tb] = a2[tb];
-      }
+    for (int ks = 0; ks < NK; ++ks) {
+      const int t = 4 * ks + lk;
+      if (ks + 2 < NK) load_a(ks + 2, ring[(ks + 2) % 3]);
+      double b[2][2][2];   // b[pl][par][sign]
 #pragma unroll
       for (int pl = 0; pl < 2; ++pl)
 #pragma unroll
         for (int par = 0; par < 2; ++par) {
-          if (PHASE == 0) {
-            const int mir = mirror(t, par);
-            const double xa = X[pl][2 * t + par][lr];
-            const double xb = mir > t ? X[pl][2 * (mir > t ? mir : t) + par][lr] : 0.0;
-            b[pl][par][0] = mir >= t ? xa + xb : 0.0;
-            b[pl][par][1] = mir > t ? xa - xb : 0.0;
-          } else {
-            b[pl][par][0] = Cc[pl][2 * par][t][lr];
-            b[pl][par][1] = Cc[pl][2 * par + 1][t][lr];
-          }
+          b[pl][par][0] = Cc[pl][2 * par][t][lr];
+          b[pl][par][1] = Cc[pl][2 * par + 1][t][lr];
         }
 #pragma unroll
       for (int tb = 0; tb < 4; ++tb)
 #pragma unroll
         for (int pl = 0; pl < 2; ++pl)
-          acc[tb][pl] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[tb], b[pl][tb >> 1][tb & 1],
+          acc[tb][pl] = __builtin_amdgcn_mfma_f64_16x16x4f64(ring[ks % 3][tb], b[pl][tb >> 1][tb & 1],
                                                              acc[tb][pl], 0, 0, 0);
     }
   };
 
   // ---- forward product
-  product(std::integral_constant<int, 0>{});
+  product();
 
   auto divide = [&](double& vr, double& vi, int a) {
     if (!dvalid) { vr = 0.0; vi = 0.0; return; }
@@ -778,7 +774,7 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
       cmb[v][1][2 * s2 + 1] = pair ? ti - bi : 0.0;
     }
   }
-  __syncthreads();   // every wave is done reading the column tile
+  __syncthreads();   // every wave is done reading the forward operands
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -788,7 +784,7 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
   __syncthreads();
 
   // ---- inverse product and output rows
-  product(std::integral_constant<int, 1>{});
+  product();
   double* ob0 = out + base0;
   double* ob1 = out + base1;
 #pragma unroll
