@@ -368,6 +368,13 @@ hipError_t fold_product(aao_ctx* c, int d, const void* in, void* out, double* co
   // the second fold halves the FP64 matrix-core work; with FP32 (twice the
   // matrix-core rate) the extra loads and barrier of its K loop cost more
   // than it saves, so FP32 keeps the one-level fold
+  // along x without a divide (P1 = 128 or 256): whole rows per block
+  if (d == 0 && !divtm && g.dim >= 2 && c->prec == AAO_FP64 && c->FqT64[0] &&
+      (g.P1 == 128 || g.P1 == 256)) {
+    FoldArgs fr = f;
+    fr.ndt = g.P2 * g.P3 / 16;
+    return launch_dst_fold2_rows((const double*)in, (double*)out, c->FqT64[0], fr, c->stream);
+  }
   if (c->Fq64[d] && c->prec == AAO_FP64)
     return launch_dst_fold2<double>((const double*)in, (double*)out, c->Fq64[d], f, d != 0, lam,
                                     t1, t2, t3, c->stream);

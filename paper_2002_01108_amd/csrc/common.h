@@ -36,6 +36,39 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
   return xcd * q + (xcd < r ? xcd : r) + slot;
 }
 
+// Persistent grids: as many blocks as fit on the chip at once (a multiple of
+// 8); block b runs on XCD b % 8 (round-robin dispatch), and XCD x walks a
+// contiguous range of the n work items so that neighbouring items share its
+// L2.  Work item loops are uniform per block (barriers inside are fine).
+struct StripRange {
+  int first, end, step;
+};
+__device__ __forceinline__ StripRange xcd_strips(int n) {
+  const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8, per = gridDim.x / 8;
+  const int q = n / 8, r = n % 8;
+  const int lo = xcd * q + (xcd < r ? xcd : r);
+  return {lo + slot, lo + q + (xcd < r ? 1 : 0), per};
+}
+
+// Blocks of one kernel resident on the whole chip at once, rounded down to a
+// multiple of 8 (the walk above assumes it); -1 if the runtime cannot say.
+template <typename K>
+int persistent_grid(K kernel, int threads) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
+    return -1;
+  const int g = (cus * per_cu) / 8 * 8;
+  return g >= 8 ? g : -1;
+}
+
+// grid for n work items: the resident count, or fewer when there are fewer items
+inline int strip_grid(int resident, int64_t n) {
+  const int64_t cover = (n + 7) / 8 * 8;
+  return cover < resident ? (int)cover : resident;
+}
+
 // ---------------------------------------------------------------- geometry
 // Spatial grid: m1 (x, fastest), m2 (y), m3 (z); unused dims are 1.
 // Spectrum planes are padded: P_d = round_up(m_d, 64) for used dims, 1 otherwise.
@@ -144,6 +177,10 @@ hipError_t launch_dst_fold2(const T* in, T* out, const T* tabs, const FoldArgs& 
 hipError_t launch_dst_fold2_fused(const double* in, double* out, const double* tt,
                                   const FoldArgs& f, const double* lam, const double* tmu1,
                                   const double* tmu2, const double* tmu3, hipStream_t s);
+// Two-level folded product along x (axis 0, no divide) with 16 whole rows per
+// block, FP64, odd m, P1 = 128 or 256; f.ndt counts 16-row tiles per plane.
+hipError_t launch_dst_fold2_rows(const double* in, double* out, const double* tt,
+                                 const FoldArgs& f, hipStream_t s);
 
 // Shifted divide in the doubly transformed domain:
 // spec[k] <- spec[k] / (lambda_k + sum_d tmu_d[i_d]), complex, pads set to 0.

@@ -812,6 +812,159 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
   }
 }
 
+// ---------------------------------------------------------------- rows kernel (x axis)
+// Along x, the contiguous axis, for FP64 with odd m and P = 4 HQ: a block owns
+// 16 whole x-rows of one plane pair.  Loads run along the rows; element j of
+// a row (j = 2t + par < P/2) pairs with its mirror m-1-j, the fold's + and -
+// operands are formed in registers and stored in LDS as [combo][row][t]; the
+// matrix cores take the data as the A operand (16 rows x 4 t) and the
+// transposed quarter tables as B, so the outputs come out row-major and go
+// back through LDS for stores that also run along the rows.  S is its own
+// inverse, so the kernel serves the forward and the inverse product.
+// LDS strides: operand rows HQ + 2 apart and operand planes 8 elements more
+// than a multiple of 32, so that the staging stores and the MFMA operand reads
+// of a half-wave fall on distinct banks; output rows P + 1 apart likewise.
+template <int HQ>
+__global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(2))) void k_dst_fold2_rows(
+    const double* __restrict__ in, double* __restrict__ out, const double* __restrict__ tt,
+    FoldArgs f, int ntiles) {
+  using V = d4;
+  constexpr int P = 4 * HQ, NT = 64 * (HQ / 16), NV = 16;
+  constexpr int S = HQ + 2, PLS = NV * S + 8, YS = P + 1;
+  constexpr int OPS = 2 * 4 * PLS, OUTS = 2 * NV * YS;
+  static_assert(NT == P, "one thread per row element in the store loop, two rows per load step");
+  __shared__ double lds[OPS > OUTS ? OPS : OUTS];
+  auto cc = [&](int pl, int cb, int v, int t) -> double& { return lds[(pl * 4 + cb) * PLS + v * S + t]; };
+  auto yy = [&](int pl, int v, int a) -> double& { return lds[(pl * NV + v) * YS + a]; };
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int m = f.m, h = (m + 1) / 2, q0 = w * 16;
+
+  // tile b: rows d0 .. d0 + 15 (d0 = 16 (b % ndt)) of frequency block k = b / ndt
+  auto bases = [&](int b, int& d0, int64_t& base0, int64_t& base1) {
+    const int k = b / f.ndt;
+    d0 = (b % f.ndt) * NV;
+    base0 = (int64_t)k * 2 * f.PS;
+    base1 = (f.packed && k == 0) ? (int64_t)f.nk * 2 * f.PS : base0 + f.PS;
+  };
+  // element j < P/2 of a row (j = 2t + par) pairs with its mirror m-1-j; the
+  // next tile's raw values are loaded while the current tile is processed
+  // Thread tid takes element j = tid % (P/2) of rows v = tid / (P/2) + 2 i'
+  // (NT = P: two rows per step), plane pl = i / (NST/2): a per-lane offset plus
+  // wave-uniform ones, so no per-row 64-bit offsets stay live across tiles.
+  constexpr int NST = 2 * NV * (P / 2) / NT;   // (pl, row pair) steps per thread
+  const int jl = tid % (P / 2), vl = tid / (P / 2);
+  const int jml = m - 1 - jl, jcl = jml > jl ? jml : jl;   // mirror, in range either way
+  double xa[NST], xb[NST];
+  auto load = [&](int b) {
+    int d0;
+    int64_t base0, base1;
+    bases(b, d0, base0, base1);
+    const double* row = in + (int64_t)(d0 + vl) * f.R;
+#pragma unroll
+    for (int i = 0; i < NST; ++i) {
+      const double* src = row + (i < NST / 2 ? base0 : base1) + (int64_t)(2 * (i % (NST / 2))) * f.R;
+      xa[i] = src[jl];
+      xb[i] = src[jcl];
+    }
+  };
+  auto load_b = [&](int ks, double (&bq)[4]) {
+    const int t = 4 * ks + lk;
+#pragma unroll
+    for (int tb = 0; tb < 4; ++tb) bq[tb] = tt[((int64_t)tb * HQ + t) * HQ + q0 + lr];
+  };
+
+  const StripRange sr = xcd_strips(ntiles);
+  if (sr.first < sr.end) load(sr.first);
+  for (int b = sr.first; b < sr.end; b += sr.step) {
+    int d0;
+    int64_t base0, base1;
+    bases(b, d0, base0, base1);
+    __syncthreads();   // the previous tile's stores have read the LDS
+    {
+      // a proper pair gives + and -; the middle (jm = j) keeps x alone in +;
+      // beyond the pairs both are zero (those elements are other j's mirrors)
+      const int t = jl >> 1, par = jl & 1;
+      const bool pair = jml > jl, mid = jml == jl;
+#pragma unroll
+      for (int i = 0; i < NST; ++i) {
+        const int v = vl + 2 * (i % (NST / 2)), pl = i / (NST / 2);
+        cc(pl, 2 * par, v, t) = pair ? xa[i] + xb[i] : (mid ? xa[i] : 0.0);
+        cc(pl, 2 * par + 1, v, t) = pair ? xa[i] - xb[i] : 0.0;
+      }
+    }
+    if (b + sr.step < sr.end) load(b + sr.step);
+    __syncthreads();
+
+    // quarter products: acc[tb][pl] = data(combo tb) x table tb; table
+    // fragments through a two-slot register ring one K step ahead (the loop
+    // is unrolled by two so the slots are fixed registers)
+    V acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) acc[a][c] = V{0, 0, 0, 0};
+    {
+      constexpr int NK = HQ / 4;
+      static_assert(NK % 2 == 0, "ring of two");
+      double ring[2][4];
+      load_b(0, ring[0]);
+#pragma unroll 2
+      for (int ks = 0; ks < NK; ++ks) {
+        const int t = 4 * ks + lk;
+        if (ks + 1 < NK) load_b(ks + 1, ring[(ks + 1) % 2]);
+        double a[2][4];   // a[pl][combo]
+#pragma unroll
+        for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) a[pl][cb] = cc(pl, cb, lr, t);
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+          for (int pl = 0; pl < 2; ++pl)
+            acc[tb][pl] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[pl][tb], ring[ks % 2][tb],
+                                                               acc[tb][pl], 0, 0, 0);
+      }
+    }
+    __syncthreads();   // every wave is done reading the operands
+
+    // epilogue: lane element i is row v = lk + 4 i, quarter index q = q0 + lr;
+    // output r = 2q + s2 takes tables s2 (O) and 2 + s2 (E): y_r = O + E,
+    // y_{m-1-r} = O - E
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int v = lk + 4 * i, q = q0 + lr;
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2) {
+        const int r = 2 * q + s2, rb = m - 1 - r;
+        if (r >= h) continue;
+#pragma unroll
+        for (int pl = 0; pl < 2; ++pl) {
+          const double O = acc[s2][pl][i], E = acc[2 + s2][pl][i];
+          yy(pl, v, r) = O + E;
+          if (rb > r) yy(pl, v, rb) = O - E;
+        }
+      }
+    }
+    __syncthreads();
+
+    // stores along the rows (thread tid writes element a = tid of every row);
+    // padding positions and rows outside the grid get zero.  The 16 rows of a
+    // tile share i3 (P2 is a multiple of 16).
+    double* ob0 = out + base0;
+    double* ob1 = out + base1;
+    const int i2_0 = d0 % f.P2, i3 = d0 / f.P2;
+    const bool avalid = tid < m && i3 < f.m3;
+#pragma unroll
+    for (int it = 0; it < 2 * NV; ++it) {
+      const int v = it % NV, pl = it / NV;
+      const bool valid = avalid && i2_0 + v < f.m2;
+      (pl ? ob1 : ob0)[(int64_t)(d0 + v) * f.R + tid] = valid ? yy(pl, v, tid) : 0.0;
+    }
+  }
+}
+
 }  // namespace
 
 template <typename T>
@@ -850,6 +1003,28 @@ hipError_t launch_dst_fold2_fused(const double* in, double* out, const double* t
   else
     hipLaunchKernelGGL((k_dst_fold2_fused<32>), dim3((unsigned)nblk), dim3(128), 0, s, in, out, tt,
                        f, lam, tmu1, tmu2, tmu3);
+  return hipGetLastError();
+}
+
+hipError_t launch_dst_fold2_rows(const double* in, double* out, const double* tt,
+                                 const FoldArgs& f, hipStream_t s) {
+  const int P = 2 * f.Hp;
+  if (f.m % 2 == 0 || (P != 128 && P != 256) || f.m > P || f.R != P || f.axis != 0 ||
+      f.ndt < 1 || f.nk < 1 || f.P2 < 1 || f.P2 % 16)
+    return hipErrorInvalidValue;
+  const int64_t ntiles = (int64_t)f.ndt * f.nk;
+  if (ntiles > 0x7fffffff) return hipErrorInvalidConfiguration;
+  if (P == 256) {
+    static const int resident = persistent_grid(k_dst_fold2_rows<64>, 256);
+    if (resident < 8) return hipErrorInvalidDeviceFunction;
+    hipLaunchKernelGGL((k_dst_fold2_rows<64>), dim3(strip_grid(resident, ntiles)), dim3(256), 0,
+                       s, in, out, tt, f, (int)ntiles);
+  } else {
+    static const int resident = persistent_grid(k_dst_fold2_rows<32>, 128);
+    if (resident < 8) return hipErrorInvalidDeviceFunction;
+    hipLaunchKernelGGL((k_dst_fold2_rows<32>), dim3(strip_grid(resident, ntiles)), dim3(128), 0,
+                       s, in, out, tt, f, (int)ntiles);
+  }
   return hipGetLastError();
 }
 

@@ -14,7 +14,9 @@
 // each thread keeps its butterfly's points in registers and the passes
 // exchange through one LDS tile of n x CW complex values.  The forward runs its
 // first pass on the values it loaded; the inverse stages the half spectrum in
-// LDS and its last pass goes straight to HBM.
+// LDS and its last pass goes straight to HBM.  Both kernels are persistent over
+// the column strips (xcd_strips): each block loads the next strip's inputs into
+// registers while the LDS passes of the current one run.
 //
 // Output of Step 1 (input of Step 3) is the split-plane spectrum layout:
 //   spec[k][0][i3][i2][i1] = Re, spec[k][1][i3][i2][i1] = Im, planes padded to
@@ -169,22 +171,6 @@ template <int N, int NS> struct LastNS {
   static constexpr int value = (NS * R >= N) ? NS : LastNS<N, (NS * R >= N ? N : NS * R)>::value;
 };
 template <int N> struct LastNS<N, N> { static constexpr int value = N; };
-
-// ---------------------------------------------------------------- strip loop
-// Both kernels are persistent over column strips: the grid holds as many
-// blocks as fit on the chip at once (a multiple of 8), block b runs on XCD
-// b % 8 (round-robin dispatch), and XCD x walks a contiguous range of strips so
-// that neighbouring column segments share its L2.  Each block loads the next
-// strip's inputs into registers while the LDS passes of the current one run.
-struct StripRange {
-  int first, end, step;
-};
-__device__ __forceinline__ StripRange xcd_strips(int nstrip) {
-  const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8, per = gridDim.x / 8;
-  const int q = nstrip / 8, r = nstrip % 8;
-  const int lo = xcd * q + (xcd < r ? xcd : r);
-  return {lo + slot, lo + q + (xcd < r ? 1 : 0), per};
-}
 
 // ---------------------------------------------------------------- forward (Step 1)
 template <typename T, int N, int TH>
@@ -358,25 +344,6 @@ __global__ __launch_bounds__(TH) void k_time_inv(
     constexpr int NSL = LastNS<N, 1>::value;
     lds_pass<T, N, TH, -1, NSL, true>(lds, twl, t, c, store);
   }
-}
-
-// Blocks of one kernel resident on the whole chip at once, rounded down to a
-// multiple of 8 (the strip walk assumes it); -1 if the runtime cannot say.
-template <typename K>
-int persistent_grid(K kernel, int threads) {
-  int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
-    return -1;
-  const int g = (cus * per_cu) / 8 * 8;
-  return g >= 8 ? g : -1;
-}
-
-// grid for nstrip strips: the resident count, or fewer when there are fewer strips
-inline int strip_grid(int resident, int64_t nstrip) {
-  const int64_t cover = (nstrip + 7) / 8 * 8;
-  return cover < resident ? (int)cover : resident;
 }
 
 template <typename T, int N, int TH>
