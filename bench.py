@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--variants", default="fp32,bf16x3",
                     help="comma list of extra preconditioner precisions to time")
+    ap.add_argument("--no-table1", action="store_true",
+                    help="skip the BEC vs block-circulant comparison of Section 5, Table 1")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the variable-coefficient learned/multigrid leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -228,6 +230,42 @@ def cpu_baseline(w, f, u0, sample_steps):
                       f"{dt:.1f} s"}
 
 
+def table1_leg(steps):
+    """Section 5, Example 1 (Table 1): heat equation with a = 1e-5, u0 =
+    x(x-1)y(y-1), f = 0, 63^2 interior points, N = 64 and 128, left-
+    preconditioned GMRES(50) from zero to a 1e-7 drop of the preconditioned
+    residual, BEC (eps = min(0.5, 0.5 tau)) against block circulant (eps = 1).
+    u_t = a Laplace(u) on (0, 1] is run as the unit-coefficient system on
+    (0, a] (the same backward-Euler equations).  Iterations, time per solve and
+    the true residual; the paper prints 2 / 13 iterations for both N."""
+    import torch
+    import workloads as W
+    from paper_2002_01108_amd import Solver
+    m1, a = 63, 1e-5
+    x = W.node_coords(m1)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    u0 = torch.from_numpy((X * (X - 1) * Y * (Y - 1)).reshape(-1)).cuda()
+    out = {}
+    for n in (64, 128):
+        f = torch.zeros((n, m1 * m1), dtype=torch.float64, device="cuda")
+        for name, eps in (("bec", min(0.5, 0.5 / n)), ("bc", 1.0)):
+            s = Solver(2, m1, n, T=a, eps=eps, precision="fp64")
+            s.set_side("left")
+            rhs = s.build_rhs(f, u0)
+            u = s.new()
+            info = s.solve(rhs, tol=1e-7, maxit=200, restart=50, u=u)[1]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                info = s.solve(rhs, tol=1e-7, maxit=200, restart=50, u=u)[1]
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            out[f"N{n}_{name}"] = {"gmres_iters": info["iters"], "ms_per_solve": dt * 1e3,
+                                   "rel_res": info["final_res"],
+                                   "unknowns_per_s": n * m1 * m1 / dt}
+    return out
+
+
 def learned_leg(tol, steps, oracle_check, train_fields=4, train_steps=1500, batch=8):
     """Variable-coefficient workload: train the learned inner solve on the GPU,
     then time FGMRES with it against the multigrid fallback and the
@@ -391,6 +429,8 @@ def main():
         variants[vp] = rec
     if variants:
         out["variants"] = variants
+    if not args.no_table1:
+        out["table1"] = table1_leg(max(1, args.steps // 2))
     if not args.no_learned:
         # the variable-coefficient system is worse conditioned: RES 1e-9 keeps the
         # error against the oracle at the 1e-8 level the comparison is made at

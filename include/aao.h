@@ -117,6 +117,19 @@ typedef enum {
 } aao_inner;
 aao_status aao_set_inner(aao_ctx *ctx, aao_inner inner, int cycles);
 
+/* Side of the preconditioner in aao_solve.
+ *  - AAO_RIGHT (default): flexible GMRES on L P^{-1} w = rhs, u = P^{-1} w; the
+ *    stopping test is on the true residual ||rhs - L u|| / ||rhs||.
+ *  - AAO_LEFT: GMRES on P^{-1} L u = P^{-1} rhs (Section 3, eq.
+ *    (preconditionedsystem)), stopping on the preconditioned residual
+ *    ||P^{-1}(rhs - L u)|| / ||P^{-1} rhs|| as in the experiments of Section 5;
+ *    it needs a fixed preconditioner (any aao_set_inner choice is one) and
+ *    costs one extra P^{-1} per solve.  final_res still reports the true
+ *    residual.
+ * Returns AAO_EINVAL for an unknown side. */
+typedef enum { AAO_RIGHT = 0, AAO_LEFT = 1 } aao_side;
+aao_status aao_set_side(aao_ctx *ctx, aao_side side);
+
 /* ---- learned inner solve (AAO_INNER_CNN) ----------------------------------
  * Extends the paper's inner solve of Step 2 (one multigrid V-cycle per block,
  * Section 4 and Section 5, Example 2) with a small network N that corrects the
@@ -208,7 +221,8 @@ aao_status aao_step3(aao_ctx *ctx, const double *zt, double *z);
  *  - u: device [n][m]; on entry the initial guess if use_guess != 0 (ignored
  *    otherwise, zero guess); on exit the last iterate.
  *  - Stops when the relative residual ||rhs - L u|| / ||rhs|| (tracked by the
- *    Givens recurrence) is <= tol, or after maxit Arnoldi steps in total.
+ *    Givens recurrence; with aao_set_side(AAO_LEFT) the preconditioned one) is
+ *    <= tol, or after maxit Arnoldi steps in total.
  *  - restart: Krylov basis size (>= 1); the context allocates 2*(restart+1)
  *    vectors of n*m doubles and keeps them for later calls.
  *  - iters (host, may be null): total Arnoldi steps.

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libaao.so")
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ENAN, ESTATE = 0, 1, -1, -2, -3, -4, -5
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 INNERS = {"dst": 0, "dst_mean": 1, "mg": 2, "cnn": 3}
+SIDES = {"right": 0, "left": 1}
 
 # exported symbols and their signatures: (restype, argtypes)
 _c_int, _c_double, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
@@ -43,6 +44,7 @@ SIGNATURES = {
     "aao_query": (_c_int, [_vp, _pint]),
     "aao_set_coefficient": (_c_int, [_vp, _pdbl, _pdbl, _pdbl]),
     "aao_set_inner": (_c_int, [_vp, _c_int, _c_int]),
+    "aao_set_side": (_c_int, [_vp, _c_int]),
     "aao_cnn_param_count": (_c_int, []),
     "aao_cnn_set_params": (_c_int, [_vp, _pflt, _c_int]),
     "aao_cnn_get_params": (_c_int, [_vp, _pflt, _c_int]),
@@ -148,6 +150,11 @@ class Solver:
 
     def set_inner(self, inner: str = "dst", cycles: int = 1):
         self._check(self.lib.aao_set_inner(self._h, INNERS[inner], cycles))
+
+    def set_side(self, side: str = "right"):
+        """'right' (flexible GMRES, true-residual stopping) or 'left' (GMRES on
+        P^{-1} L u = P^{-1} rhs, preconditioned-residual stopping)."""
+        self._check(self.lib.aao_set_side(self._h, SIDES[side]))
 
     # ------------------------------------------------------------ learned correction
     def cnn_param_count(self) -> int:

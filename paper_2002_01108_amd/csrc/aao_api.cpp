@@ -72,6 +72,7 @@ struct aao_ctx {
 
   // inner solver of Step 2 (aao_set_inner)
   aao_inner inner = AAO_INNER_DST;
+  aao_side side = AAO_RIGHT;     // aao_set_side
   int inner_cycles = 1;
 
   // multigrid hierarchy (2D), built lazily for the current precision
@@ -1205,6 +1206,13 @@ aao_status aao_set_inner(aao_ctx* c, aao_inner inner, int cycles) {
   return AAO_OK;
 }
 
+aao_status aao_set_side(aao_ctx* c, aao_side side) {
+  if (!c) return AAO_EINVAL;
+  if (side != AAO_RIGHT && side != AAO_LEFT) return fail(c, AAO_EINVAL, "unknown side");
+  c->side = side;
+  return AAO_OK;
+}
+
 int aao_cnn_param_count(void) { return kCnnParams; }
 
 aao_status aao_cnn_set_params(aao_ctx* c, const float* params, int count) {
@@ -1543,6 +1551,21 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
     return AAO_OK;
   };
 
+  // Left preconditioning (Section 3, eq. (preconditionedsystem)): GMRES on
+  // P^{-1} L u = P^{-1} rhs, stopping on the preconditioned residual relative
+  // to that of the zero guess, ||P^{-1} rhs|| (Section 5).  The basis W then
+  // holds preconditioned residuals and u is updated from W, not from Z.
+  const bool left = c->side == AAO_LEFT;
+  double ref = bnorm;
+  if (left) {
+    TRY(apply_pinv(c, rhs, c->V));
+    TRY(sqnorm_dev(c, c->V, nullptr, o_nrm));
+    TRY(fetch_small(c, o_nrm, 1));
+    ref = sqrt(c->hsmall[o_nrm]);
+    if (!isfinite(ref)) return fail(c, AAO_ENAN, "preconditioned right-hand side is not finite");
+    if (ref == 0.0) ref = bnorm;   // P^{-1} is invertible: not reached for rhs != 0
+  }
+
   std::vector<double> H((size_t)(R + 1) * R), cs(R), sn(R), gv(R + 1), y(R), sc(R + 1);
   int total = 0, nhist = 0;
   bool converged = false;
@@ -1550,7 +1573,16 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
   while (true) {
     double beta, g0;
     const double* v0 = nullptr;  // W_0 when it is not stored in V
-    if (first && !use_guess) {
+    if (first && !use_guess && left) {
+      // W_0 = P^{-1} rhs, already in V
+      beta = ref;
+      g0 = beta;
+      sc[0] = beta;
+      if (!in_range(beta)) {
+        HIPCHK(c, launch_scale_host(c->V, c->V, nm, 1.0 / beta, c->stream));
+        sc[0] = 1.0;
+      }
+    } else if (first && !use_guess) {
       // r0 = rhs: the basis starts from the caller's array
       beta = bnorm;
       g0 = beta;
@@ -1559,6 +1591,32 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
       if (!in_range(beta)) {
         HIPCHK(c, launch_scale_host(rhs, c->V, nm, 1.0 / beta, c->stream));
         v0 = nullptr;
+        sc[0] = 1.0;
+      }
+    } else if (left) {
+      // W_0 = P^{-1} (L u - rhs) = -P^{-1} r0
+      TRY(apply_L(c, u, c->tmp));
+      c->hsmall[o_y] = 1.0;
+      HIPCHK(c, hipMemcpyAsync(c->dsmall + o_y, c->hsmall + o_y, sizeof(double),
+                               hipMemcpyHostToDevice, c->stream));
+      {
+        ProfScope ps(c, AAO_K_KRYLOV);
+        HIPCHK(c, launch_axpy_dot(rhs, 0, nullptr, 1, c->dsmall + o_y, c->tmp, nm, c->part, 0,
+                                  c->stream));
+      }
+      TRY(apply_pinv(c, c->tmp, c->V));
+      TRY(sqnorm_dev(c, c->V, nullptr, o_nrm));
+      TRY(fetch_small(c, o_nrm, 1));
+      beta = sqrt(c->hsmall[o_nrm]);
+      if (!isfinite(beta)) return fail(c, AAO_ENAN, "iterate is not finite");
+      if (beta / ref <= tol) {
+        converged = true;
+        break;
+      }
+      g0 = -beta;
+      sc[0] = beta;
+      if (!in_range(beta)) {
+        HIPCHK(c, launch_scale_host(c->V, c->V, nm, 1.0 / beta, c->stream));
         sc[0] = 1.0;
       }
     } else {
@@ -1600,18 +1658,24 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
       const double* wj = (j == 0 && v0) ? v0 : c->V + (int64_t)j * nm;
       double* zj = c->Z + (int64_t)j * nm;
       double* w = c->V + (int64_t)(j + 1) * nm;
-      TRY(apply_pinv(c, wj, zj));
       const int q = j + 1;
       const double* is2 = c->dsmall + o_is2;
       // CGS2 on the unnormalised basis: c1 = (W^T w) / s^2; w -= W c1;
-      // c2 = (W^T w) / s^2; w -= W c2; ||w||^2.  The first projection's dots
-      // come out of the stencil pass that forms w = L z (2D/3D, q <= 8).
-      const bool fuse = fused_stencil(c, q);
+      // c2 = (W^T w) / s^2; w -= W c2; ||w||^2.  With right preconditioning the
+      // first projection's dots come out of the stencil pass that forms
+      // w = L z (2D/3D, q <= 4); with left preconditioning w = P^{-1} L W_j.
+      const bool fuse = !left && fused_stencil(c, q);
+      if (left) {
+        TRY(apply_L(c, wj, c->tmp));
+        TRY(apply_pinv(c, c->tmp, w));
+      } else {
+        TRY(apply_pinv(c, wj, zj));
+      }
       if (fuse) {
         const double* basis[kStencilDotsMax];
         for (int i = 0; i < q; ++i) basis[i] = (i == 0 && v0) ? v0 : c->V + (int64_t)i * nm;
         TRY(stencil_fused(c, 2, zj, w, nullptr, basis, q, o_h1, is2));
-      } else {
+      } else if (!left) {
         TRY(apply_L(c, zj, w));
       }
       {
@@ -1672,7 +1736,7 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
       gv[j + 1] = -sn[j] * gv[j];
       gv[j] = cs[j] * gv[j];
       ++total;
-      const double est = fabs(gv[j + 1]) / bnorm;
+      const double est = fabs(gv[j + 1]) / ref;
       if (res_hist && nhist < hist_cap) res_hist[nhist] = est;
       ++nhist;
       const bool breakdown = (wn == 0.0);
@@ -1704,8 +1768,8 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
                              hipMemcpyHostToDevice, c->stream));
     {
       ProfScope ps(c, AAO_K_KRYLOV);
-      HIPCHK(c, launch_multi_axpy(c->Z, nm, k, c->dsmall + o_y, u, nm, u_zero ? 1 : 0,
-                                  c->stream));
+      HIPCHK(c, launch_multi_axpy(left ? c->V : c->Z, nm, k, c->dsmall + o_y, u, nm,
+                                  u_zero ? 1 : 0, c->stream));
     }
     u_zero = false;
     if (converged || total >= maxit) break;

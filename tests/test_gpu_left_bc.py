@@ -1,0 +1,132 @@
+"""Left preconditioning and the block-circulant (eps = 1) baseline on the GPU,
+through the C ABI.
+
+* Section 5, Example 1, Table 1: GMRES-BEC and GMRES-BC iteration counts and
+  RES for the heat equation with diffusion a = 1e-5 (printed values in
+  tests/golden/table1_bdf1.txt).  u_t = a Laplace(u) on (0, T] gives the same
+  backward-Euler system, (I + tau a K) u^k = u^{k-1}, as the unit-coefficient
+  equation on (0, aT] with the same number of steps, so the library runs it
+  with T = a; eps keeps the paper's min(0.5, 0.5 tau) with tau = 1/N.
+* At an equal step count the left-preconditioned iterate equals the oracle's
+  left GMRES iterate, for BEC and for BC.
+* Right preconditioning: both preconditioners reach the oracle's solution; BC
+  takes at least as many iterations.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import heat
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+HERE = os.path.dirname(__file__)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def solver(dim, m1, n, eps, T=1.0, side="right"):
+    from paper_2002_01108_amd import Solver
+    s = Solver(dim, m1, n, T=T, eps=eps, precision="fp64")
+    s.set_side(side)
+    return s
+
+
+def _golden_rows(name):
+    rows = []
+    with open(os.path.join(HERE, "golden", name)) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                rows.append([float(t) for t in line.split()])
+    return rows
+
+
+@pytest.mark.parametrize("row", range(2))
+@pytest.mark.parametrize("bec", [True, False], ids=["BEC", "BC"])
+def test_table1_iterations_gpu(row, bec):
+    """BEC counts exactly as printed.  BC within one iteration: its
+    preconditioned residual decays slowly and sits within a few per cent of
+    the 1e-7 threshold at the printed step (the oracle's estimate there is
+    1.04e-7 for N = 64), while with eps = 1 the k = 0 block is tau K alone, so
+    ||P^{-1}|| ~ 1 / (tau a mu_min) ~ 1e5 amplifies the rounding differences
+    between the FFT/DST inverse and the oracle's sparse LU to that level."""
+    n, J1, it_bec, res_bec, it_bc, res_bc = _golden_rows("table1_bdf1.txt")[row]
+    n, m1 = int(n), int(J1) - 1
+    a = 1e-5
+    eps = min(0.5, 0.5 / n) if bec else 1.0
+    x = W.node_coords(m1)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    u0 = (X * (X - 1) * Y * (Y - 1)).reshape(-1)
+    s = solver(2, m1, n, eps, T=a, side="left")
+    rhs = s.build_rhs(dev(np.zeros((n, m1 * m1))), dev(u0))
+    u, info = s.solve(rhs, tol=1e-7, maxit=200, restart=50)
+    want_it, want_res = (it_bec, res_bec) if bec else (it_bc, res_bc)
+    print(f"N={n} {'BEC' if bec else 'BC'}: iterations {info['iters']} (printed {int(want_it)}), "
+          f"RES {info['final_res']:.2e} (printed {want_res:.2e}), "
+          f"last estimates {[f'{h:.3e}' for h in info['hist'][-3:]]}", flush=True)
+    assert info["status"] == 0
+    if bec:
+        assert info["iters"] == int(want_it)
+    else:
+        assert abs(info["iters"] - int(want_it)) <= 1
+    assert want_res / 4 <= info["final_res"] <= want_res * 4
+
+
+def _c1(eps):
+    w = W.WORKLOADS["heat1d_63x64"]
+    p = heat.Problem(w.m1, w.dim, w.n, eps=eps)
+    f, u0, _ = W.make(w)
+    return w, p, p.rhs(f, u0)
+
+
+@pytest.mark.parametrize("eps", [0.125, 1.0])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_left_iterate_matches_oracle(eps, k):
+    w, p, rhs = _c1(eps)
+    x_or, it, _ = p.gmres_left(rhs, tol=0.0, maxit=k)
+    assert it == k
+    s = solver(w.dim, w.m1, w.n, eps, side="left")
+    u, info = s.solve(dev(rhs), tol=0.0, maxit=k)
+    assert info["iters"] == k
+    assert rel(host(u), x_or) <= 1e-10
+
+
+@pytest.mark.parametrize("dim,m1,n", [(1, 63, 64), (2, 37, 32), (3, 13, 16)])
+def test_bc_and_bec_reach_the_solution(dim, m1, n):
+    """Right and left preconditioning, BEC (eps = 0.1) and BC (eps = 1): the
+    solve at tol 1e-12 matches the oracle's sequential backward Euler, and BC
+    needs at least as many iterations as BEC."""
+    p = heat.Problem(m1, dim, n, eps=0.1)
+    rhs = np.random.default_rng(21).standard_normal((n, p.m))
+    exact = p.exact(rhs)
+    iters = {}
+    for side in ("right", "left"):
+        for eps in (0.1, 1.0):
+            s = solver(dim, m1, n, eps, side=side)
+            u, info = s.solve(dev(rhs), tol=1e-12, maxit=200, restart=50)
+            assert info["status"] == 0
+            assert rel(host(u), exact) <= 1e-10
+            iters[side, eps] = info["iters"]
+    print(iters, flush=True)
+    for side in ("right", "left"):
+        assert iters[side, 1.0] >= iters[side, 0.1]
+
+
+def test_side_rejects_unknown():
+    s = solver(1, 15, 8, 0.2)
+    assert s.lib.aao_set_side(s._h, 7) == -1      # AAO_EINVAL
