@@ -117,6 +117,20 @@ typedef enum {
 } aao_inner;
 aao_status aao_set_inner(aao_ctx *ctx, aao_inner inner, int cycles);
 
+/* Time discretisation of the all-at-once system (Section 4, eqs. (pstepscheme)
+ * and (pstepbecpreconditioner), M = I):
+ *  - order 1 (default): backward Euler, r = (1, -1);
+ *  - order 2: BDF2, r = (3/2, -2, 1/2) (Section 5, Table bdf2table), with a
+ *    backward-Euler first step (the paper does not say how the two-step
+ *    scheme starts; this start keeps the scheme second order).  Row 1 of L
+ *    is u^1 + tau K u^1, row 2 is (3/2) u^2 - 2 u^1 + tau K u^2, later rows
+ *    the full BDF2 row; aao_build_rhs then adds u^0 to row 1 and
+ *    -(1/2) u^0 to row 2.
+ * The preconditioner P_eps uses the Toeplitz R_eps of the scheme, i.e.
+ * lambda_k = sum_j r_j eps^{j/n} theta^{kj} in Step 2; Steps 1 and 3 are
+ * unchanged.  Returns AAO_EINVAL for another order. */
+aao_status aao_set_scheme(aao_ctx *ctx, int order);
+
 /* Side of the preconditioner in aao_solve.
  *  - AAO_RIGHT (default): flexible GMRES on L P^{-1} w = rhs, u = P^{-1} w; the
  *    stopping test is on the true residual ||rhs - L u|| / ||rhs||.

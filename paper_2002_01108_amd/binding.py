@@ -45,6 +45,7 @@ SIGNATURES = {
     "aao_set_coefficient": (_c_int, [_vp, _pdbl, _pdbl, _pdbl]),
     "aao_set_inner": (_c_int, [_vp, _c_int, _c_int]),
     "aao_set_side": (_c_int, [_vp, _c_int]),
+    "aao_set_scheme": (_c_int, [_vp, _c_int]),
     "aao_cnn_param_count": (_c_int, []),
     "aao_cnn_set_params": (_c_int, [_vp, _pflt, _c_int]),
     "aao_cnn_get_params": (_c_int, [_vp, _pflt, _c_int]),
@@ -150,6 +151,11 @@ class Solver:
 
     def set_inner(self, inner: str = "dst", cycles: int = 1):
         self._check(self.lib.aao_set_inner(self._h, INNERS[inner], cycles))
+
+    def set_scheme(self, order: int = 1):
+        """Time discretisation: 1 = backward Euler, 2 = BDF2 with a
+        backward-Euler first step (include/aao.h)."""
+        self._check(self.lib.aao_set_scheme(self._h, int(order)))
 
     def set_side(self, side: str = "right"):
         """'right' (flexible GMRES, true-residual stopping) or 'left' (GMRES on

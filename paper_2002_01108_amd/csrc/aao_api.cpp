@@ -938,6 +938,24 @@ aao_status ensure_krylov(aao_ctx* c, int restart) {
 }  // namespace
 
 // =====================================================================================
+// lambda_k = sum_j r_j eps^{j/n} theta^{kj} for k = 0..n/2 (eq. (repsdiagform));
+// backward Euler (1, -1) gives 1 - eps^{1/n} theta^k.  tw holds cos/sin of
+// 2 pi e / n for e = 0..n-1.
+std::vector<double> lambdas(const Geometry& g, double eps, const std::vector<double>& tw) {
+  const int n = g.n;
+  const double r[3] = {g.r0, g.r1, g.r2};
+  std::vector<double> lam(2 * g.nh, 0.0);
+  for (int k = 0; k < g.nh; ++k)
+    for (int j = 0; j < 3; ++j) {
+      if (r[j] == 0.0) continue;
+      const double ej = j == 0 ? 1.0 : pow(eps, (double)j / n);
+      const int e = (int)(((int64_t)k * j) % n);
+      lam[2 * k] += r[j] * ej * tw[2 * e];
+      lam[2 * k + 1] += r[j] * ej * tw[2 * e + 1];
+    }
+  return lam;
+}
+
 extern "C" {
 
 const char* aao_status_string(aao_status s) {
@@ -1018,13 +1036,7 @@ aao_status aao_setup(int dim, int m1, int m2, int m3, int n, double T, double ep
     gam32[e] = (float)gam[e];
     ginv32[e] = (float)ginv[e];
   }
-  // lambda_k = 1 - eps^{1/n} theta^k (eq. (repsdiagform) with r = (1, -1))
-  std::vector<double> lam(2 * g.nh);
-  const double e1n = pow(eps, 1.0 / n);
-  for (int k = 0; k < g.nh; ++k) {
-    lam[2 * k] = 1.0 - e1n * tw[2 * (k % n)];
-    lam[2 * k + 1] = -e1n * tw[2 * (k % n) + 1];
-  }
+  const std::vector<double> lam = lambdas(g, eps, tw);
   aao_status st;
   if ((st = upload(c, &c->tw64, tw)) != AAO_OK) return bail(st);
   if ((st = upload(c, &c->tw32, tw32)) != AAO_OK) return bail(st);
@@ -1203,6 +1215,26 @@ aao_status aao_set_inner(aao_ctx* c, aao_inner inner, int cycles) {
   }
   c->inner = inner;
   c->inner_cycles = cycles;
+  return AAO_OK;
+}
+
+aao_status aao_set_scheme(aao_ctx* c, int order) {
+  if (!c) return AAO_EINVAL;
+  Geometry g = c->g;
+  if (order == 1) { g.r0 = 1.0; g.r1 = -1.0; g.r2 = 0.0; }
+  else if (order == 2) { g.r0 = 1.5; g.r1 = -2.0; g.r2 = 0.5; }
+  else return fail(c, AAO_EINVAL, "time scheme order must be 1 or 2");
+  const int n = g.n;
+  std::vector<double> tw(2 * n);
+  for (int e = 0; e < n; ++e) {
+    tw[2 * e] = sin_pi_frac(2LL * e + n / 2, n);
+    tw[2 * e + 1] = sin_pi_frac(2LL * e, n);
+  }
+  const std::vector<double> lam = lambdas(g, c->eps, tw);
+  HIPCHK(c, hipMemcpyAsync(c->lam, lam.data(), lam.size() * sizeof(double),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->g = g;
   return AAO_OK;
 }
 
@@ -1459,7 +1491,7 @@ aao_status aao_sync(aao_ctx* ctx) {
 
 aao_status aao_build_rhs(aao_ctx* ctx, const double* f, const double* u0, double* rhs) {
   if (!ctx || !f || !u0 || !rhs) return AAO_EINVAL;
-  HIPCHK(ctx, launch_build_rhs(f, u0, rhs, nm_of(ctx), ctx->g.m, ctx->tau, ctx->stream));
+  HIPCHK(ctx, launch_build_rhs(f, u0, rhs, nm_of(ctx), ctx->g.m, ctx->tau, ctx->g.r2, ctx->stream));
   return AAO_OK;
 }
 

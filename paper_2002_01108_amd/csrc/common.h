@@ -80,6 +80,10 @@ struct Geometry {
   int64_t PS = 1;     // P1*P2*P3 (one real plane)
   int n = 2;          // time steps (power of two)
   int nh = 2;         // n/2 + 1 frequency blocks
+  // time discretisation of L (eq. (pstepscheme), M = I): row k >= 2 reads
+  // r0 u^k + r1 u^{k-1} + r2 u^{k-2} + tau K u^k; row 1 is a backward-Euler
+  // step, u^1 + tau K u^1.  Backward Euler: (1, -1, 0); BDF2: (3/2, -2, 1/2).
+  double r0 = 1.0, r1 = -1.0, r2 = 0.0;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -221,9 +225,10 @@ hipError_t launch_multi_axpy(const double* Z, int64_t ldz, int q, const double* 
 // partial squared norm of (a - b) (b may be null -> ||a||^2)
 hipError_t launch_diffnorm(const double* a, const double* b, int64_t len, double* part,
                            hipStream_t s);
-// y = tau*f, y[0:m] += u0
+// y = tau*f, y[0:m] += u0 (backward-Euler first step), y[m:2m] -= r2*u0 (the
+// u^0 term of the second row of a two-step scheme; r2 = 0 for backward Euler)
 hipError_t launch_build_rhs(const double* f, const double* u0, double* y, int64_t nm, int64_t m,
-                            double tau, hipStream_t s);
+                            double tau, double r2, hipStream_t s);
 
 // ---------------------------------------------------------------- multigrid (2D)
 // One level's complex grid for all blocks: element (k, plane, j, i) at

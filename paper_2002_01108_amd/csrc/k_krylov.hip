@@ -182,11 +182,13 @@ __global__ __launch_bounds__(KT) void k_diffnorm(const double* __restrict__ a,
 }
 
 __global__ void k_build_rhs(const double* __restrict__ f, const double* __restrict__ u0,
-                            double* __restrict__ y, int64_t nm, int64_t m, double tau) {
+                            double* __restrict__ y, int64_t nm, int64_t m, double tau,
+                            double r2) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nm;
        e += (int64_t)gridDim.x * blockDim.x) {
     double v = tau * f[e];
     if (e < m) v += u0[e];
+    else if (r2 != 0.0 && e < 2 * m) v -= r2 * u0[e - m];
     y[e] = v;
   }
 }
@@ -274,8 +276,9 @@ hipError_t launch_diffnorm(const double* a, const double* b, int64_t len, double
 }
 
 hipError_t launch_build_rhs(const double* f, const double* u0, double* y, int64_t nm, int64_t m,
-                            double tau, hipStream_t s) {
-  hipLaunchKernelGGL(k_build_rhs, dim3(simple_grid(nm)), dim3(256), 0, s, f, u0, y, nm, m, tau);
+                            double tau, double r2, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_rhs, dim3(simple_grid(nm)), dim3(256), 0, s, f, u0, y, nm, m, tau,
+                     r2);
   return hipGetLastError();
 }
 

@@ -1,11 +1,14 @@
-// All-at-once matrix-vector product y = L x (Section 2, eq. (allatoncesystem)):
-//   y^k = (I + tau K) x^k - x^{k-1},  x^0 := 0,
+// All-at-once matrix-vector product y = L x (Section 2, eq. (allatoncesystem);
+// p-step form of eq. (pstepscheme) with M = I):
+//   y^k = (r0 I + tau K) x^k + r1 x^{k-1} + r2 x^{k-2},  x^{<1} := 0,
+// with coefficient 1 in place of r0 on the first level (a backward-Euler first
+// step); backward Euler is (r0, r1, r2) = (1, -1, 0), BDF2 (3/2, -2, 1/2).
 // K the 3/5/7-point -Laplacian (constant coefficient) or the flux-form
 // discretisation of -div(a grad .) with coefficients on cell faces.
 //
 // One thread owns one spatial point and walks a chunk of time levels, keeping
-// x^{k-1} in a register, so x is read from HBM once per chunk (plus one
-// halo slab per chunk) and y written once: 16 B per unknown.  A block is a
+// x^{k-1} (and x^{k-2}) in registers, so x is read from HBM once per chunk
+// (plus one or two halo slabs per chunk) and y written once: 16 B per unknown.  A block is a
 // 64 x 4 patch of the x-y plane; spatial neighbours come through L1/L2.
 // Workgroups are renumbered so that patches adjacent in y land on the same
 // XCD (consecutive hardware workgroup ids rotate over the 8 XCDs).
@@ -18,11 +21,13 @@ constexpr int TX = 64;       // points along x per block
 constexpr int TY = 4;        // rows along y per block
 constexpr int TCHUNK = 8;    // time levels per block
 
-template <int DIM, bool VAR>
+// TWO: the scheme has an x^{k-2} term (r2 != 0); backward Euler compiles without it.
+template <int DIM, bool VAR, bool TWO>
 __global__ __launch_bounds__(TX * TY) void k_apply_L(
     const double* __restrict__ x, double* __restrict__ y, int n, int m1, int m2, int m3,
     int nbx, int nby, int nbt, double c1, double c2, double c3, const double* __restrict__ ax,
-    const double* __restrict__ ay, const double* __restrict__ az) {
+    const double* __restrict__ ay, const double* __restrict__ az, double r0, double r1,
+    double r2) {
   const int nblk = nbx * nby * m3 * nbt;
   const int b = xcd_remap(blockIdx.x, nblk);
   // logical tile order: x tiles fastest, then y tiles, then z, then time chunk
@@ -70,7 +75,9 @@ __global__ __launch_bounds__(TX * TY) void k_apply_L(
 
   const int k0 = bt * TCHUNK;
   const int k1 = min(n, k0 + TCHUNK);
+  const double dr = r0 - 1.0;   // diag carries 1 (first level); later levels add r0 - 1
   double prev = (k0 > 0) ? x[(int64_t)(k0 - 1) * m + s] : 0.0;
+  double prev2 = (TWO && k0 > 1) ? x[(int64_t)(k0 - 2) * m + s] : 0.0;
   for (int k = k0; k < k1; ++k) {
     const double* xk = x + (int64_t)k * m + s;
     const double xc = xk[0];
@@ -85,7 +92,10 @@ __global__ __launch_bounds__(TX * TY) void k_apply_L(
       if (hzm) nb += wzm * xk[-sz];
       if (hzp) nb += wzp * xk[sz];
     }
-    y[(int64_t)k * m + s] = diag * xc - nb - prev;
+    double v = (k == 0 ? diag : diag + dr) * xc - nb + r1 * prev;
+    if (TWO) v += r2 * prev2;
+    y[(int64_t)k * m + s] = v;
+    prev2 = prev;
     prev = xc;
   }
 }
@@ -110,11 +120,12 @@ struct StencilEpi {
   double* part;
 };
 
-template <int DIM, bool VAR, int TY, int TC, int EPI, int Q>
+template <int DIM, bool VAR, int TY, int TC, int EPI, int Q, bool TWO>
 __global__ __launch_bounds__(256) void k_apply_L25(
     const double* __restrict__ x, double* __restrict__ y, int n, int m1, int m2, int m3, int nxt,
     int nyt, int nct, double c1, double c2, double c3, const double* __restrict__ ax,
-    const double* __restrict__ ay, const double* __restrict__ az, StencilEpi ep) {
+    const double* __restrict__ ay, const double* __restrict__ az, StencilEpi ep, double r0,
+    double r1, double r2) {
   const int nblk = nxt * nyt * m3 * nct;
   int b = xcd_remap(blockIdx.x, nblk);
   const int bx = b % nxt; b /= nxt;
@@ -167,11 +178,15 @@ __global__ __launch_bounds__(256) void k_apply_L25(
 
   const int k0 = bc * TC;
   const int k1 = wave_on ? min(n, k0 + TC) : k0;
-  double prev[TY];
+  const double dr = r0 - 1.0;   // dg carries 1 (first level); later levels add r0 - 1
+  double prev[TY], prev2[TWO ? TY : 1];
 #pragma unroll
   for (int t = 0; t < TY; ++t) {
     const int j = j0 + t;
     prev[t] = (k0 > 0 && inx && j < m2) ? x[(int64_t)(k0 - 1) * m + base + (int64_t)j * m1] : 0.0;
+    if (TWO)
+      prev2[TWO ? t : 0] = (k0 > 1 && inx && j < m2)
+                               ? x[(int64_t)(k0 - 2) * m + base + (int64_t)j * m1] : 0.0;
   }
   for (int k = k0; k < k1; ++k) {
     const double* xk = x + (int64_t)k * m + base;
@@ -206,8 +221,9 @@ __global__ __launch_bounds__(256) void k_apply_L25(
       const double c = r[t + 1];
       const double left = __shfl_up(c, 1, 64);
       const double right = __shfl_down(c, 1, 64);
-      double acc = dg[t] * c - wxm[t] * left - wxp[t] * right - wym[t] * r[t] -
-                   wyp[t] * r[t + 2] - prev[t];
+      double acc = (k == 0 ? dg[t] : dg[t] + dr) * c - wxm[t] * left - wxp[t] * right -
+                   wym[t] * r[t] - wyp[t] * r[t + 2] + r1 * prev[t];
+      if (TWO) acc += r2 * prev2[TWO ? t : 0];
       if (DIM >= 3) acc -= wzm[t] * zl[t] + wzp[t] * zh[t];
       const bool out_ok = writer && j0 + t < m2;
       if (EPI != 1 && out_ok) yk[(int64_t)(j0 + t) * m1] = acc;
@@ -219,6 +235,7 @@ __global__ __launch_bounds__(256) void k_apply_L25(
 #pragma unroll
         for (int i = 0; i < NQ; ++i) red_acc[i] += eo[i][t] * acc;
       }
+      if (TWO) prev2[TWO ? t : 0] = prev[t];
       prev[t] = c;
     }
   }
@@ -252,13 +269,20 @@ template <int DIM, bool VAR, int EPI, int Q = 1>
 hipError_t launch25(const Geometry& g, const double* x, double* y, double c1, double c2,
                     double c3, const double* ax, const double* ay, const double* az,
                     const StencilEpi& ep, hipStream_t s) {
+  const bool two = g.r2 != 0.0;
   const int nxt = (g.m1 + XW - 1) / XW;
   const int nyt = (g.m2 + 4 * TY25 - 1) / (4 * TY25);
   const int nct = (g.n + TC25 - 1) / TC25;
   const int64_t nblk = blocks25(g);
   if (nblk <= 0 || nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_apply_L25<DIM, VAR, TY25, TC25, EPI, Q>), dim3((unsigned)nblk), dim3(256),
-                     0, s, x, y, g.n, g.m1, g.m2, g.m3, nxt, nyt, nct, c1, c2, c3, ax, ay, az, ep);
+  if (two)
+    hipLaunchKernelGGL((k_apply_L25<DIM, VAR, TY25, TC25, EPI, Q, true>), dim3((unsigned)nblk),
+                       dim3(256), 0, s, x, y, g.n, g.m1, g.m2, g.m3, nxt, nyt, nct, c1, c2, c3,
+                       ax, ay, az, ep, g.r0, g.r1, g.r2);
+  else
+    hipLaunchKernelGGL((k_apply_L25<DIM, VAR, TY25, TC25, EPI, Q, false>), dim3((unsigned)nblk),
+                       dim3(256), 0, s, x, y, g.n, g.m1, g.m2, g.m3, nxt, nyt, nct, c1, c2, c3,
+                       ax, ay, az, ep, g.r0, g.r1, g.r2);
   return hipGetLastError();
 }
 
@@ -271,8 +295,14 @@ hipError_t launch(const Geometry& g, const double* x, double* y, double c1, doub
   const int nbt = (g.n + TCHUNK - 1) / TCHUNK;
   const int64_t nblk = (int64_t)nbx * nby * g.m3 * nbt;
   if (nblk <= 0 || nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_apply_L<DIM, VAR>), dim3((unsigned)nblk), dim3(TX, TY), 0, s, x, y, g.n,
-                     g.m1, g.m2, g.m3, nbx, nby, nbt, c1, c2, c3, ax, ay, az);
+  if (g.r2 != 0.0)
+    hipLaunchKernelGGL((k_apply_L<DIM, VAR, true>), dim3((unsigned)nblk), dim3(TX, TY), 0, s, x,
+                       y, g.n, g.m1, g.m2, g.m3, nbx, nby, nbt, c1, c2, c3, ax, ay, az, g.r0,
+                       g.r1, g.r2);
+  else
+    hipLaunchKernelGGL((k_apply_L<DIM, VAR, false>), dim3((unsigned)nblk), dim3(TX, TY), 0, s, x,
+                       y, g.n, g.m1, g.m2, g.m3, nbx, nby, nbt, c1, c2, c3, ax, ay, az, g.r0,
+                       g.r1, g.r2);
   return hipGetLastError();
 }
 
