@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--variants", default="fp32,bf16x3",
                     help="comma list of extra preconditioner precisions to time")
+    ap.add_argument("--no-bdf2", action="store_true",
+                    help="skip the BDF2 solve on the same workload")
     ap.add_argument("--no-table1", action="store_true",
                     help="skip the BEC vs block-circulant comparison of Section 5, Table 1")
     ap.add_argument("--no-learned", action="store_true",
@@ -228,6 +230,27 @@ def cpu_baseline(w, f, u0, sample_steps):
                       f"source, u0), oracle GMRES-BEC (naive DFT + sparse LU per frequency, "
                       f"factorisations included) to rel.res 1e-8, {it} iterations, "
                       f"{dt:.1f} s"}
+
+
+def bdf2_leg(w, fd, u0d, f, u0, tol, restart, steps, oracle_check):
+    """The same workload with BDF2 in time (backward-Euler first step): FP64
+    solve to the same tolerance, with the error against the oracle's
+    sequential BDF2 solution."""
+    import torch
+    from paper_2002_01108_amd import Solver
+    s = Solver(w.dim, w.m1, w.n, T=w.T, eps=w.epsilon, precision="fp64")
+    s.set_scheme(2)
+    t, info, _, u, _ = time_solver(s, fd, u0d, tol, restart, steps, 1, [])
+    rec = {"value": w.dof / t, "ms_per_step": t * 1e3, "gmres_iters": info["iters"],
+           "rel_res": info["final_res"], "eps": w.epsilon}
+    if oracle_check:
+        from oracle import bdf
+        p = bdf.Problem(w.m1, w.dim, w.n, r=bdf.BDF2, T=w.T, eps=w.epsilon)
+        exact = p.exact(p.rhs(f, u0))
+        rec["rel_err_vs_oracle"] = float(np.linalg.norm(u.cpu().numpy() - exact)
+                                         / np.linalg.norm(exact))
+    torch.cuda.synchronize()
+    return rec
 
 
 def table1_leg(steps):
@@ -429,6 +452,9 @@ def main():
         variants[vp] = rec
     if variants:
         out["variants"] = variants
+    if not args.no_bdf2:
+        out["bdf2"] = bdf2_leg(w, fd, u0d, f, u0, args.tol, restart, max(1, args.steps // 2),
+                               not args.no_oracle_check)
     if not args.no_table1:
         out["table1"] = table1_leg(max(1, args.steps // 2))
     if not args.no_learned:

@@ -219,6 +219,24 @@ double sin_pi_frac(long long p, long long q) {
   return sg * sin(kPi * (double)r / (double)q);
 }
 
+// lambda_k = sum_j r_j eps^{j/n} theta^{kj} for k = 0..n/2 (eq. (repsdiagform));
+// backward Euler (1, -1) gives 1 - eps^{1/n} theta^k.  tw holds cos/sin of
+// 2 pi e / n for e = 0..n-1.
+std::vector<double> lambdas(const Geometry& g, double eps, const std::vector<double>& tw) {
+  const int n = g.n;
+  const double r[3] = {g.r0, g.r1, g.r2};
+  std::vector<double> lam(2 * g.nh, 0.0);
+  for (int k = 0; k < g.nh; ++k)
+    for (int j = 0; j < 3; ++j) {
+      if (r[j] == 0.0) continue;
+      const double ej = j == 0 ? 1.0 : pow(eps, (double)j / n);
+      const int e = (int)(((int64_t)k * j) % n);
+      lam[2 * k] += r[j] * ej * tw[2 * e];
+      lam[2 * k + 1] += r[j] * ej * tw[2 * e + 1];
+    }
+  return lam;
+}
+
 // round-to-nearest-even FP32 -> BF16 (bit pattern) and back
 uint16_t bf16_rne_host(float x) {
   uint32_t u;
@@ -756,10 +774,15 @@ aao_status cnn_tables(aao_ctx* c) {
   const Geometry& g = c->g;
   if (!n.phik) {
     std::vector<float> phi(4 * (size_t)g.nh);
-    const double e1n = pow(c->eps, 1.0 / g.n);
+    std::vector<double> tw(2 * g.n);
+    for (int e = 0; e < g.n; ++e) {
+      tw[2 * e] = sin_pi_frac(2LL * e + g.n / 2, g.n);
+      tw[2 * e + 1] = sin_pi_frac(2LL * e, g.n);
+    }
+    const std::vector<double> lam = lambdas(g, c->eps, tw);   // the scheme's lambda_k
     for (int k = 0; k < g.nh; ++k) {
-      const double re = 1.0 - e1n * sin_pi_frac(2LL * k + g.n / 2, g.n);
-      const double im = -e1n * sin_pi_frac(2LL * k, g.n);
+      const double re = lam[2 * k];
+      const double im = lam[2 * k + 1];
       phi[4 * k] = (float)re;
       phi[4 * k + 1] = (float)im;
       phi[4 * k + 2] = (float)log(hypot(re, im));
@@ -938,24 +961,6 @@ aao_status ensure_krylov(aao_ctx* c, int restart) {
 }  // namespace
 
 // =====================================================================================
-// lambda_k = sum_j r_j eps^{j/n} theta^{kj} for k = 0..n/2 (eq. (repsdiagform));
-// backward Euler (1, -1) gives 1 - eps^{1/n} theta^k.  tw holds cos/sin of
-// 2 pi e / n for e = 0..n-1.
-std::vector<double> lambdas(const Geometry& g, double eps, const std::vector<double>& tw) {
-  const int n = g.n;
-  const double r[3] = {g.r0, g.r1, g.r2};
-  std::vector<double> lam(2 * g.nh, 0.0);
-  for (int k = 0; k < g.nh; ++k)
-    for (int j = 0; j < 3; ++j) {
-      if (r[j] == 0.0) continue;
-      const double ej = j == 0 ? 1.0 : pow(eps, (double)j / n);
-      const int e = (int)(((int64_t)k * j) % n);
-      lam[2 * k] += r[j] * ej * tw[2 * e];
-      lam[2 * k + 1] += r[j] * ej * tw[2 * e + 1];
-    }
-  return lam;
-}
-
 extern "C" {
 
 const char* aao_status_string(aao_status s) {
@@ -1235,6 +1240,9 @@ aao_status aao_set_scheme(aao_ctx* c, int order) {
                            hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->g = g;
+  // the learned inner solve's frequency features follow lambda_k
+  dfree(c, c->cnn.phik);
+  c->cnn.phik = nullptr;
   return AAO_OK;
 }
 
