@@ -131,6 +131,23 @@ aao_status aao_set_inner(aao_ctx *ctx, aao_inner inner, int cycles);
  * unchanged.  Returns AAO_EINVAL for another order. */
 aao_status aao_set_scheme(aao_ctx *ctx, int order);
 
+/* Spatial discretisation.
+ *  - AAO_DISC_FD (default): finite differences, M = I, the 3/5/7-point K.
+ *  - AAO_DISC_Q1: bilinear (Q1) finite elements on the uniform square grid
+ *    (Section 5 uses them): L = R (x) M + tau I (x) K (eq. (pstepscheme)) with
+ *    M = M1 (x) M1, K = M1 (x) K1 + K1 (x) M1, M1 = h/6 tridiag(1, 4, 1),
+ *    K1 = 1/h tridiag(-1, 2, -1); both act as 9-point stencils in aao_apply_A
+ *    and the solve.  P_eps = R_eps (x) M + tau I (x) K: in the sine basis
+ *    B_k = lambda_k M + tau K is diagonal with entries m_i (lambda_k + tau k_i / m_i),
+ *    which Step 2 divides by.  aao_build_rhs returns M times the nodal right-
+ *    hand side (the load vectors of nodally sampled f and u0).
+ *    Needs dim = 2 with m1 = m2, a constant coefficient, the FP64 or FP32
+ *    preconditioner and the DST inner solve (AAO_ESTATE otherwise, and later
+ *    calls that would break these conditions return AAO_ESTATE).
+ * Returns AAO_EINVAL for an unknown value or a grid Q1 does not support. */
+typedef enum { AAO_DISC_FD = 0, AAO_DISC_Q1 = 1 } aao_discretisation;
+aao_status aao_set_discretisation(aao_ctx *ctx, aao_discretisation disc);
+
 /* Side of the preconditioner in aao_solve.
  *  - AAO_RIGHT (default): flexible GMRES on L P^{-1} w = rhs, u = P^{-1} w; the
  *    stopping test is on the true residual ||rhs - L u|| / ||rhs||.

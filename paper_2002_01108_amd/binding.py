@@ -46,6 +46,7 @@ SIGNATURES = {
     "aao_set_inner": (_c_int, [_vp, _c_int, _c_int]),
     "aao_set_side": (_c_int, [_vp, _c_int]),
     "aao_set_scheme": (_c_int, [_vp, _c_int]),
+    "aao_set_discretisation": (_c_int, [_vp, _c_int]),
     "aao_cnn_param_count": (_c_int, []),
     "aao_cnn_set_params": (_c_int, [_vp, _pflt, _c_int]),
     "aao_cnn_get_params": (_c_int, [_vp, _pflt, _c_int]),
@@ -156,6 +157,11 @@ class Solver:
         """Time discretisation: 1 = backward Euler, 2 = BDF2 with a
         backward-Euler first step (include/aao.h)."""
         self._check(self.lib.aao_set_scheme(self._h, int(order)))
+
+    def set_discretisation(self, disc: str = "fd"):
+        """'fd' (finite differences, M = I) or 'q1' (bilinear finite elements,
+        2D square grids; include/aao.h)."""
+        self._check(self.lib.aao_set_discretisation(self._h, {"fd": 0, "q1": 1}[disc]))
 
     def set_side(self, side: str = "right"):
         """'right' (flexible GMRES, true-residual stopping) or 'left' (GMRES on

@@ -33,6 +33,7 @@ struct aao_ctx {
   float* ginv32 = nullptr;
   double* lam = nullptr;         // lambda_k, k = 0..n/2, interleaved complex
   double* tmu[3] = {nullptr, nullptr, nullptr};  // tau * mu_i per axis (padded, 0 in pads)
+  double* ims[2] = {nullptr, nullptr};  // Q1: 1 / (mass eigenvalue) along x and y
   double* S64[3] = {nullptr, nullptr, nullptr};  // DST-I matrices per axis, P_d x P_d
   float* S32[3] = {nullptr, nullptr, nullptr};
   uint16_t* Shi[3] = {nullptr, nullptr, nullptr};  // BF16 hi/lo split of S32 (bit patterns)
@@ -334,6 +335,10 @@ FoldArgs fold_args(const aao_ctx* c, int d, bool real_ends) {
   f.P2 = g.P2;
   f.OS = 0;
   f.nout = 1;
+  if (g.q1) {
+    f.ims_c = c->ims[0];
+    f.ims_r = c->ims[1];
+  }
   if (d == 0) {  // rows (z, y) of length P1
     f.m = g.m1;
     f.Hp = g.P1 / 2;
@@ -1136,6 +1141,8 @@ aao_status aao_set_precision(aao_ctx* ctx, aao_precision p) {
   if (!ctx) return AAO_EINVAL;
   if (p != AAO_FP64 && p != AAO_FP32 && p != AAO_BF16X3)
     return fail(ctx, AAO_EINVAL, "unsupported precision");
+  if (ctx->g.q1 && p == AAO_BF16X3)
+    return fail(ctx, AAO_ESTATE, "Q1 elements need the FP64/FP32 DST preconditioner");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   ctx->prec = p;
   return ensure_spec(ctx);
@@ -1145,6 +1152,7 @@ aao_status aao_set_coefficient(aao_ctx* c, const double* ax, const double* ay,
                                const double* az) {
   if (!c) return AAO_EINVAL;
   const Geometry& g = c->g;
+  if (g.q1 && ax) return fail(c, AAO_ESTATE, "Q1 elements need a constant coefficient");
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (!ax) {  // back to a = 1
     c->var = false;
@@ -1218,6 +1226,8 @@ aao_status aao_set_inner(aao_ctx* c, aao_inner inner, int cycles) {
     default:
       return fail(c, AAO_EINVAL, "unknown inner solver");
   }
+  if (c->g.q1 && inner != AAO_INNER_DST)
+    return fail(c, AAO_ESTATE, "Q1 elements need the DST inner solve");
   c->inner = inner;
   c->inner_cycles = cycles;
   return AAO_OK;
@@ -1243,6 +1253,58 @@ aao_status aao_set_scheme(aao_ctx* c, int order) {
   // the learned inner solve's frequency features follow lambda_k
   dfree(c, c->cnn.phik);
   c->cnn.phik = nullptr;
+  return AAO_OK;
+}
+
+aao_status aao_set_discretisation(aao_ctx* c, aao_discretisation disc) {
+  if (!c) return AAO_EINVAL;
+  Geometry g = c->g;
+  if (disc != AAO_DISC_FD && disc != AAO_DISC_Q1) return fail(c, AAO_EINVAL, "unknown discretisation");
+  const bool q1 = disc == AAO_DISC_Q1;
+  if (q1) {
+    if (g.dim != 2 || g.m1 != g.m2)
+      return fail(c, AAO_EINVAL, "Q1 elements need a square 2D grid");
+    if (c->var) return fail(c, AAO_ESTATE, "Q1 elements need a constant coefficient");
+    if (c->prec == AAO_BF16X3 || c->inner != AAO_INNER_DST)
+      return fail(c, AAO_ESTATE, "Q1 elements need the FP64/FP32 DST preconditioner");
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double h = c->h[0];
+  // per axis: tau k_i / m_i (Q1) or tau mu_i (finite differences), and 1 / m_i,
+  // with s = sin((i+1) pi h / 2): k_i = 4 s^2 / h, m_i = h (1 - 2 s^2 / 3)
+  const int Ps[2] = {g.P1, g.P2};
+  const int ms[2] = {g.m1, g.m2};
+  for (int d = 0; d < 2 && d < g.dim; ++d) {
+    std::vector<double> tmu(Ps[d], 0.0), ims(Ps[d], 0.0);
+    const double hd = c->h[d];
+    for (int i = 0; i < ms[d]; ++i) {
+      const double sn = sin_pi_frac(i + 1, 2LL * (ms[d] + 1));
+      if (q1) {
+        const double mi = hd * (1.0 - 2.0 / 3.0 * sn * sn);
+        tmu[i] = c->tau * (4.0 * sn * sn / hd) / mi;
+        ims[i] = 1.0 / mi;
+      } else {
+        tmu[i] = c->tau * 4.0 / (hd * hd) * sn * sn;
+      }
+    }
+    HIPCHK(c, hipMemcpy(c->tmu[d], tmu.data(), tmu.size() * sizeof(double),
+                        hipMemcpyHostToDevice));
+    if (q1) {
+      aao_status st;
+      if (!c->ims[d] && (st = dalloc(c, &c->ims[d], ims.size())) != AAO_OK) return st;
+      HIPCHK(c, hipMemcpy(c->ims[d], ims.data(), ims.size() * sizeof(double),
+                          hipMemcpyHostToDevice));
+    }
+  }
+  g.q1 = q1 ? 1 : 0;
+  if (q1) {
+    g.qm[0] = 16.0 * h * h / 36.0;
+    g.qm[1] = 4.0 * h * h / 36.0;
+    g.qm[2] = h * h / 36.0;
+    g.qk[0] = 8.0 * c->tau / 3.0;
+    g.qk[1] = -c->tau / 3.0;
+  }
+  c->g = g;
   return AAO_OK;
 }
 
@@ -1499,7 +1561,23 @@ aao_status aao_sync(aao_ctx* ctx) {
 
 aao_status aao_build_rhs(aao_ctx* ctx, const double* f, const double* u0, double* rhs) {
   if (!ctx || !f || !u0 || !rhs) return AAO_EINVAL;
-  HIPCHK(ctx, launch_build_rhs(f, u0, rhs, nm_of(ctx), ctx->g.m, ctx->tau, ctx->g.r2, ctx->stream));
+  if (!ctx->g.q1) {
+    HIPCHK(ctx, launch_build_rhs(f, u0, rhs, nm_of(ctx), ctx->g.m, ctx->tau, ctx->g.r2,
+                                 ctx->stream));
+    return AAO_OK;
+  }
+  // Q1: the load vectors are M times the nodal values, level by level: the
+  // nodal right-hand side goes to the scratch vector, then the stencil with
+  // only its mass part (r = (1, 0, 0), no stiffness) applies M
+  if (!ctx->tmp) TRY(dalloc(ctx, &ctx->tmp, (size_t)nm_of(ctx)));
+  HIPCHK(ctx, launch_build_rhs(f, u0, ctx->tmp, nm_of(ctx), ctx->g.m, ctx->tau, ctx->g.r2,
+                               ctx->stream));
+  Geometry gm = ctx->g;
+  gm.r0 = 1.0;
+  gm.r1 = 0.0;
+  gm.r2 = 0.0;
+  gm.qk[0] = gm.qk[1] = 0.0;
+  HIPCHK(ctx, launch_apply_L(gm, ctx->tmp, rhs, 0.0, 0.0, 0.0, ctx->stream));
   return AAO_OK;
 }
 

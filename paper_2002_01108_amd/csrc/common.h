@@ -84,6 +84,11 @@ struct Geometry {
   // r0 u^k + r1 u^{k-1} + r2 u^{k-2} + tau K u^k; row 1 is a backward-Euler
   // step, u^1 + tau K u^1.  Backward Euler: (1, -1, 0); BDF2: (3/2, -2, 1/2).
   double r0 = 1.0, r1 = -1.0, r2 = 0.0;
+  // spatial discretisation: finite differences (q1 = 0, M = I) or Q1 finite
+  // elements on a uniform 2D grid (q1 = 1): 9-point M and tau K weights
+  // qm = h^2/36 (16, 4, 1), qk = tau/3 (8, -1)
+  int q1 = 0;
+  double qm[3] = {0.0, 0.0, 0.0}, qk[2] = {0.0, 0.0};
 };
 
 // ---------------------------------------------------------------- launchers
@@ -156,6 +161,10 @@ struct FoldArgs {
   int packed;     // 1: block 0 pairs the real planes of frequencies 0 and n/2
   int axis;       // 0 = x, 1 = y, 2 = z
   int m1, m2, m3, P1, P2;
+  // Q1 elements (2D, divide along y): the shifted divide also multiplies by
+  // 1 / (mass eigenvalue along x (column) * along y (row)); null otherwise
+  const double* ims_c = nullptr;
+  const double* ims_r = nullptr;
 };
 // out = S_d applied along `axis`; Soe = S[0:h, 0::2], Soo = S[0:h, 1::2] (Hp x Hp,
 // zero padded).  With lam != nullptr the result is divided by

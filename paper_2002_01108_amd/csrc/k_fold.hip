@@ -260,6 +260,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             vr = nr;
             vi = ni;
           }
+          if (LEFT && f.ims_r) {
+            // Q1 elements: B_k = M (lambda_k I + tau M^{-1} K) in the sine basis
+            const T ms = (T)(f.ims_c[dpos] * f.ims_r[a]);
+            vr *= ms;
+            vi *= ms;
+          }
         }
         int64_t off;
         if (LEFT) off = (int64_t)a * f.R + dpos;
@@ -545,6 +551,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
               vr = nr;
               vi = ni;
             }
+            if (LEFT && f.ims_r) {
+              // Q1 elements: B_k = M (lambda_k I + tau M^{-1} K) in the sine basis
+              const T ms = (T)(f.ims_c[dpos] * f.ims_r[a]);
+              vr *= ms;
+              vi *= ms;
+            }
           }
           int64_t off;
           if (LEFT) off = (int64_t)a * f.R + dpos;
@@ -743,7 +755,12 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
       vr = nr;
       vi = ni;
     }
-  };
+      if (f.ims_r) {   // Q1 elements: B_k = M (lambda_k I + tau M^{-1} K), sine basis
+        const double ms = f.ims_c[dl] * f.ims_r[a];
+        vr *= ms;
+        vi *= ms;
+      }
+    };
   // epilogue -> divide -> inverse inputs, held in registers until the tile is free
   double cmb[4][2][4];   // [v][plane][combo u+, u-, v+, v-]
 #pragma unroll

@@ -120,12 +120,24 @@ struct StencilEpi {
   double* part;
 };
 
-template <int DIM, bool VAR, int TY, int TC, int EPI, int Q, bool TWO>
+// Q1: 2D finite elements on a uniform grid (Section 5): L = R (x) M + tau I (x) K with
+// M = M1 (x) M1 and K = M1 (x) K1 + K1 (x) M1, both 9-point:
+//   M x = qm0 c + qm1 (edge neighbours) + qm2 (corner neighbours)
+//   tau K x = qk0 c + qk1 (all eight neighbours)
+// with (qm0, qm1, qm2) = h^2/36 (16, 4, 1) and (qk0, qk1) = tau/3 (8, -1).  The
+// time terms act on M x, so the wave keeps M x^{k-1} (and M x^{k-2}) and starts
+// its chunk one or two levels early to form them.
+struct Q1W {
+  double m0, m1, m2, k0, k1;
+};
+
+template <int DIM, bool VAR, int TY, int TC, int EPI, int Q, bool TWO, bool FE = false>
 __global__ __launch_bounds__(256) void k_apply_L25(
     const double* __restrict__ x, double* __restrict__ y, int n, int m1, int m2, int m3, int nxt,
     int nyt, int nct, double c1, double c2, double c3, const double* __restrict__ ax,
     const double* __restrict__ ay, const double* __restrict__ az, StencilEpi ep, double r0,
-    double r1, double r2) {
+    double r1, double r2, Q1W qw) {
+  static_assert(!FE || (DIM == 2 && !VAR), "Q1 elements: 2D, constant coefficient");
   const int nblk = nxt * nyt * m3 * nct;
   int b = xcd_remap(blockIdx.x, nblk);
   const int bx = b % nxt; b /= nxt;
@@ -179,16 +191,21 @@ __global__ __launch_bounds__(256) void k_apply_L25(
   const int k0 = bc * TC;
   const int k1 = wave_on ? min(n, k0 + TC) : k0;
   const double dr = r0 - 1.0;   // dg carries 1 (first level); later levels add r0 - 1
+  // prev / prev2: x^{k-1} / x^{k-2} (finite differences), M x^{k-1} / M x^{k-2} (Q1)
   double prev[TY], prev2[TWO ? TY : 1];
 #pragma unroll
   for (int t = 0; t < TY; ++t) {
     const int j = j0 + t;
-    prev[t] = (k0 > 0 && inx && j < m2) ? x[(int64_t)(k0 - 1) * m + base + (int64_t)j * m1] : 0.0;
+    prev[t] = (!FE && k0 > 0 && inx && j < m2)
+                  ? x[(int64_t)(k0 - 1) * m + base + (int64_t)j * m1] : 0.0;
     if (TWO)
-      prev2[TWO ? t : 0] = (k0 > 1 && inx && j < m2)
+      prev2[TWO ? t : 0] = (!FE && k0 > 1 && inx && j < m2)
                                ? x[(int64_t)(k0 - 2) * m + base + (int64_t)j * m1] : 0.0;
   }
-  for (int k = k0; k < k1; ++k) {
+  // Q1: run the levels before the chunk (at most 1 + TWO, not below level 0)
+  // without output, to form M x^{k0-1} and M x^{k0-2}
+  const int kstart = FE ? max(0, k0 - (TWO ? 2 : 1)) : k0;
+  for (int k = (wave_on ? kstart : k1); k < k1; ++k) {
     const double* xk = x + (int64_t)k * m + base;
     double r[TY + 2];
 #pragma unroll
@@ -209,7 +226,7 @@ __global__ __launch_bounds__(256) void k_apply_L25(
     if (EPI != 0) {
 #pragma unroll
       for (int t = 0; t < TY; ++t) {
-        const bool ok = writer && j0 + t < m2;
+        const bool ok = writer && j0 + t < m2 && (!FE || k >= k0);
         const int64_t off = (int64_t)k * m + base + (int64_t)(j0 + t) * m1;
 #pragma unroll
         for (int i = 0; i < NQ; ++i) eo[i][t] = ok ? (EPI == 1 ? ep.f : ep.w[i])[off] : 0.0;
@@ -221,10 +238,24 @@ __global__ __launch_bounds__(256) void k_apply_L25(
       const double c = r[t + 1];
       const double left = __shfl_up(c, 1, 64);
       const double right = __shfl_down(c, 1, 64);
-      double acc = (k == 0 ? dg[t] : dg[t] + dr) * c - wxm[t] * left - wxp[t] * right -
-                   wym[t] * r[t] - wyp[t] * r[t + 2] + r1 * prev[t];
+      double acc, mx = 0.0;
+      if (FE) {
+        const double se = left + right + r[t] + r[t + 2];
+        const double sc = __shfl_up(r[t], 1, 64) + __shfl_down(r[t], 1, 64) +
+                          __shfl_up(r[t + 2], 1, 64) + __shfl_down(r[t + 2], 1, 64);
+        mx = qw.m0 * c + qw.m1 * se + qw.m2 * sc;
+        acc = (k == 0 ? mx : r0 * mx) + (qw.k0 * c + qw.k1 * (se + sc)) + r1 * prev[t];
+      } else {
+        acc = (k == 0 ? dg[t] : dg[t] + dr) * c - wxm[t] * left - wxp[t] * right -
+              wym[t] * r[t] - wyp[t] * r[t + 2] + r1 * prev[t];
+      }
       if (TWO) acc += r2 * prev2[TWO ? t : 0];
       if (DIM >= 3) acc -= wzm[t] * zl[t] + wzp[t] * zh[t];
+      if (FE && k < k0) {   // a level before the chunk: history only
+        if (TWO) prev2[TWO ? t : 0] = prev[t];
+        prev[t] = mx;
+        continue;
+      }
       const bool out_ok = writer && j0 + t < m2;
       if (EPI != 1 && out_ok) yk[(int64_t)(j0 + t) * m1] = acc;
       if (EPI == 1 && out_ok) {
@@ -236,7 +267,7 @@ __global__ __launch_bounds__(256) void k_apply_L25(
         for (int i = 0; i < NQ; ++i) red_acc[i] += eo[i][t] * acc;
       }
       if (TWO) prev2[TWO ? t : 0] = prev[t];
-      prev[t] = c;
+      prev[t] = FE ? mx : c;
     }
   }
   if (EPI != 0) {
@@ -270,19 +301,29 @@ hipError_t launch25(const Geometry& g, const double* x, double* y, double c1, do
                     double c3, const double* ax, const double* ay, const double* az,
                     const StencilEpi& ep, hipStream_t s) {
   const bool two = g.r2 != 0.0;
+  const Q1W qw{g.qm[0], g.qm[1], g.qm[2], g.qk[0], g.qk[1]};
   const int nxt = (g.m1 + XW - 1) / XW;
   const int nyt = (g.m2 + 4 * TY25 - 1) / (4 * TY25);
   const int nct = (g.n + TC25 - 1) / TC25;
   const int64_t nblk = blocks25(g);
   if (nblk <= 0 || nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
-  if (two)
-    hipLaunchKernelGGL((k_apply_L25<DIM, VAR, TY25, TC25, EPI, Q, true>), dim3((unsigned)nblk),
-                       dim3(256), 0, s, x, y, g.n, g.m1, g.m2, g.m3, nxt, nyt, nct, c1, c2, c3,
-                       ax, ay, az, ep, g.r0, g.r1, g.r2);
-  else
-    hipLaunchKernelGGL((k_apply_L25<DIM, VAR, TY25, TC25, EPI, Q, false>), dim3((unsigned)nblk),
-                       dim3(256), 0, s, x, y, g.n, g.m1, g.m2, g.m3, nxt, nyt, nct, c1, c2, c3,
-                       ax, ay, az, ep, g.r0, g.r1, g.r2);
+#define L25_LAUNCH(TW, F)                                                                   \
+  hipLaunchKernelGGL((k_apply_L25<DIM, VAR, TY25, TC25, EPI, Q, TW, F>), dim3((unsigned)nblk), \
+                     dim3(256), 0, s, x, y, g.n, g.m1, g.m2, g.m3, nxt, nyt, nct, c1, c2, c3,  \
+                     ax, ay, az, ep, g.r0, g.r1, g.r2, qw)
+  if (g.q1) {
+    if constexpr (DIM == 2 && !VAR) {
+      if (two) L25_LAUNCH(true, true);
+      else L25_LAUNCH(false, true);
+    } else {
+      return hipErrorInvalidValue;   // Q1 elements: 2D constant coefficient only
+    }
+  } else if (two) {
+    L25_LAUNCH(true, false);
+  } else {
+    L25_LAUNCH(false, false);
+  }
+#undef L25_LAUNCH
   return hipGetLastError();
 }
 
