@@ -253,39 +253,61 @@ def bdf2_leg(w, fd, u0d, f, u0, tol, restart, steps, oracle_check):
     return rec
 
 
+# Section 5, Table 1 (backward Euler, Q1 elements): (N, J+1) -> BEC (iterations,
+# CPU s, RES), BC (iterations, CPU s, RES) as printed; MATLAB on 2 x 14-core
+# Xeon E5-2690 v4, FP64.  Context for the GPU times, not a target.
+TABLE1_PRINTED = {
+    (64, 64): ((2, 0.55, 9.11e-11), (13, 1.21, 2.09e-5)),
+    (128, 64): ((2, 0.31, 2.27e-11), (13, 1.18, 2.09e-5)),
+    (256, 256): ((2, 12.54, 1.60e-11), (13, 53.46, 3.08e-5)),
+    (512, 512): ((1, 74.01, 6.05e-8), (13, 406.46, 3.16e-5)),
+}
+
+
 def table1_leg(steps):
-    """Section 5, Example 1 (Table 1): heat equation with a = 1e-5, u0 =
-    x(x-1)y(y-1), f = 0, 63^2 interior points, N = 64 and 128, left-
-    preconditioned GMRES(50) from zero to a 1e-7 drop of the preconditioned
-    residual, BEC (eps = min(0.5, 0.5 tau)) against block circulant (eps = 1).
-    u_t = a Laplace(u) on (0, 1] is run as the unit-coefficient system on
-    (0, a] (the same backward-Euler equations).  Iterations, time per solve and
-    the true residual; the paper prints 2 / 13 iterations for both N."""
+    """Section 5, Example 1 (Table 1) as the paper runs it: Q1 finite elements,
+    heat equation with a = 1e-5, u0 = x(x-1)y(y-1), f = 0, left-preconditioned
+    GMRES(50) from zero to a 1e-7 drop of the preconditioned residual, BEC
+    (eps = min(0.5, 0.5 tau)) against block circulant (eps = 1), on the rows of
+    TABLE1_PRINTED.  u_t = a Laplace(u) on (0, 1] is run as the unit-coefficient
+    system on (0, a] (the same backward-Euler equations).  Iterations, time per
+    solve (right-hand side already assembled) and the true residual, beside the
+    printed values."""
     import torch
     import workloads as W
     from paper_2002_01108_amd import Solver
-    m1, a = 63, 1e-5
-    x = W.node_coords(m1)
-    X, Y = np.meshgrid(x, x, indexing="xy")
-    u0 = torch.from_numpy((X * (X - 1) * Y * (Y - 1)).reshape(-1)).cuda()
+    a = 1e-5
     out = {}
-    for n in (64, 128):
+    for (n, J1), printed in TABLE1_PRINTED.items():
+        m1 = J1 - 1
+        x = W.node_coords(m1)
+        X, Y = np.meshgrid(x, x, indexing="xy")
+        u0 = torch.from_numpy((X * (X - 1) * Y * (Y - 1)).reshape(-1)).cuda()
         f = torch.zeros((n, m1 * m1), dtype=torch.float64, device="cuda")
-        for name, eps in (("bec", min(0.5, 0.5 / n)), ("bc", 1.0)):
+        reps = steps if n * m1 * m1 < 10 ** 7 else 1
+        for (name, eps), (p_it, p_cpu, p_res) in zip((("bec", min(0.5, 0.5 / n)), ("bc", 1.0)),
+                                                     printed):
             s = Solver(2, m1, n, T=a, eps=eps, precision="fp64")
+            s.set_discretisation("q1")
             s.set_side("left")
             rhs = s.build_rhs(f, u0)
             u = s.new()
             info = s.solve(rhs, tol=1e-7, maxit=200, restart=50, u=u)[1]
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            for _ in range(steps):
+            for _ in range(reps):
                 info = s.solve(rhs, tol=1e-7, maxit=200, restart=50, u=u)[1]
             torch.cuda.synchronize()
-            dt = (time.perf_counter() - t0) / steps
-            out[f"N{n}_{name}"] = {"gmres_iters": info["iters"], "ms_per_solve": dt * 1e3,
-                                   "rel_res": info["final_res"],
-                                   "unknowns_per_s": n * m1 * m1 / dt}
+            dt = (time.perf_counter() - t0) / reps
+            out[f"N{n}_J{J1}_{name}"] = {
+                "dof": n * m1 * m1, "gmres_iters": info["iters"], "ms_per_solve": dt * 1e3,
+                "rel_res": info["final_res"], "unknowns_per_s": n * m1 * m1 / dt,
+                "paper": {"iters": p_it, "cpu_s": p_cpu, "rel_res": p_res}}
+            print(f"[table1] N={n} J+1={J1} {name}: {info['iters']} iterations, "
+                  f"{dt * 1e3:.2f} ms, RES {info['final_res']:.3e}", file=sys.stderr, flush=True)
+            del s, rhs, u
+            torch.cuda.empty_cache()
+        del f, u0
     return out
 
 
