@@ -63,31 +63,46 @@ def levels(ax, ay, tau: float):
     return out
 
 
-def _neighbour_sum(e, wx, wy):
-    """sum over faces of w_f * e_nbr (zero outside) and the diagonal sum of w_f."""
-    m = e.shape[0]
+def planes(*c):
+    """The four coupling planes (W, E, S, N), each [m][m], of one level: node
+    (j, i) couples to its west, east, south and north neighbours with weights
+    -W, -E, -S, -N and has diagonal W + E + S + N (a neighbour across the
+    boundary is zero).  `c` is either the face weights (wx, wy) of the flux form
+    (symmetric: W[j, i] = wx[j, i], E[j, i] = wx[j, i+1], S[j, i] = wy[j, i],
+    N[j, i] = wy[j+1, i]) or the four planes themselves (a nonsymmetric operator
+    such as upwinded convection-diffusion)."""
+    if len(c) == 4:
+        return c
+    wx, wy = c
+    m = wx.shape[0]
+    return wx[:, :m], wx[:, 1:], wy[:m, :], wy[1:, :]
+
+
+def _neighbour_sum(e, *c):
+    """sum over neighbours of coupling * e_nbr (zero outside) and the diagonal."""
+    W, E, S, N = planes(*c)
     s = np.zeros_like(e)
-    s[:, 1:] += wx[:, 1:m] * e[:, :-1]          # left neighbour through face i
-    s[:, :-1] += wx[:, 1:m] * e[:, 1:]          # right neighbour through face i+1
-    s[1:, :] += wy[1:m, :] * e[:-1, :]          # lower neighbour
-    s[:-1, :] += wy[1:m, :] * e[1:, :]          # upper neighbour
-    d = wx[:, :m] + wx[:, 1:] + wy[:m, :] + wy[1:, :]
+    s[:, 1:] += W[:, 1:] * e[:, :-1]            # west neighbour
+    s[:, :-1] += E[:, :-1] * e[:, 1:]           # east neighbour
+    s[1:, :] += S[1:, :] * e[:-1, :]            # south (lower) neighbour
+    s[:-1, :] += N[:-1, :] * e[1:, :]           # north (upper) neighbour
+    d = W + E + S + N
     return s, d
 
 
-def apply_B(e, lam, wx, wy):
-    """(lambda I + tau K_a) e on one level."""
-    s, d = _neighbour_sum(e, wx, wy)
+def apply_B(e, lam, *c):
+    """(lambda I + tau K) e on one level; `c` as for `planes`."""
+    s, d = _neighbour_sum(e, *c)
     return (lam + d) * e - s
 
 
-def rbgs(e, r, lam, wx, wy):
+def rbgs(e, r, lam, *c):
     """One red-black Gauss-Seidel sweep: red points, then black points."""
     m = e.shape[0]
     jj, ii = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
     e = e.copy()
     for color in (0, 1):
-        s, d = _neighbour_sum(e, wx, wy)
+        s, d = _neighbour_sum(e, *c)
         upd = (r + s) / (lam + d)
         mask = (ii + jj) % 2 == color
         e[mask] = upd[mask]
@@ -119,20 +134,20 @@ def prolong(ec, mf):
 
 def vcycle(lvls, level: int, r: np.ndarray, lam: complex, pre: int = 1, post: int = 1):
     """One V-cycle for B e = r from a zero initial guess on `level`."""
-    m, wx, wy = lvls[level]
+    m, *c = lvls[level]
     e = np.zeros_like(r, dtype=np.complex128)
     if level == len(lvls) - 1:
         for _ in range(COARSE_SWEEPS):
-            e = rbgs(e, r, lam, wx, wy)
+            e = rbgs(e, r, lam, *c)
         return e
     for _ in range(pre):
-        e = rbgs(e, r, lam, wx, wy)
-    res = r - apply_B(e, lam, wx, wy)
+        e = rbgs(e, r, lam, *c)
+    res = r - apply_B(e, lam, *c)
     mc = lvls[level + 1][0]
     ec = vcycle(lvls, level + 1, restrict(res, mc), lam, pre, post)
     e = e + prolong(ec, m)
     for _ in range(post):
-        e = rbgs(e, r, lam, wx, wy)
+        e = rbgs(e, r, lam, *c)
     return e
 
 
@@ -140,13 +155,18 @@ def step2_mg(ax, ay, tau: float, lam: np.ndarray, yt: np.ndarray, cycles: int = 
     """Step 2 with `cycles` V-cycles per block (each cycle a correction of the
     previous iterate); yt: [nk][m*m] complex; returns the same shape."""
     lv = levels(np.asarray(ax, float), np.asarray(ay, float), tau)
+    return step2_levels(lv, lam, yt, cycles)
+
+
+def step2_levels(lv, lam: np.ndarray, yt: np.ndarray, cycles: int = 1):
+    """Step 2 on a ready level list (entries (m, *couplings) as `planes` takes)."""
     m = lv[0][0]
     out = np.empty_like(yt, dtype=np.complex128)
     for k in range(yt.shape[0]):
         r = yt[k].reshape(m, m)
         e = np.zeros((m, m), dtype=np.complex128)
         for _ in range(cycles):
-            e = e + vcycle(lv, 0, r - apply_B(e, lam[k], lv[0][1], lv[0][2]), lam[k])
+            e = e + vcycle(lv, 0, r - apply_B(e, lam[k], *lv[0][1:]), lam[k])
         out[k] = e.reshape(-1)
     return out
 
