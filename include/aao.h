@@ -91,6 +91,25 @@ aao_status aao_set_precision(aao_ctx *ctx, aao_precision p);
 aao_status aao_set_coefficient(aao_ctx *ctx, const double *ax, const double *ay,
                                const double *az);
 
+/* Convection-diffusion K u = -nu Laplace(u) + w . grad(u) on the unit square
+ * (the setting of Section 5, Example 3, with a circulating wind; the paper's
+ * SUPG-stabilised Q1 elements are replaced by five-point finite differences
+ * with first-order upwinding).  wx, wy: HOST arrays [m2][m1] of the wind
+ * components at the interior nodes (copied; the caller keeps ownership); nu > 0.
+ * Node (j, i) couples to its west, east, south and north neighbours with
+ *   W = nu/h1^2 + max(wx, 0)/h1,  E = nu/h1^2 + max(-wx, 0)/h1,
+ *   S = nu/h2^2 + max(wy, 0)/h2,  N = nu/h2^2 + max(-wy, 0)/h2,
+ * (K u)_p = (W + E + S + N) u_p - W u_west - E u_east - S u_south - N u_north,
+ * a nonsymmetric M-matrix (Assumption 1 does not hold; Section 5 tests it
+ * anyway).  A problem posed on (-1, 1)^2 maps to this one with nu/4 and w/2.
+ * The blocks of Step 2 then need AAO_INNER_MG: its coarse levels use the same
+ * discretisation with the wind taken at the coarse nodes and h doubled.
+ * Needs dim = 2 and finite differences (AAO_EINVAL / AAO_ESTATE otherwise);
+ * replaces any face coefficient; wx = null restores K = -Laplace.  Values must
+ * be finite (AAO_EINVAL).  Afterwards AAO_INNER_DST_MEAN, AAO_INNER_CNN and Q1
+ * elements return AAO_ESTATE. */
+aao_status aao_set_convection(aao_ctx *ctx, double nu, const double *wx, const double *wy);
+
 /* Inner solver of Step 2 (eq. (blockdiaginv)) for each block
  * B_k = lambda_k I + tau K:
  *   AAO_INNER_DST       exact sine-transform diagonalisation (constant a only;
@@ -223,6 +242,17 @@ aao_status aao_cnn_train(aao_ctx *ctx, int steps, int batch, float lr, const int
 /* rhs = (tau f^1 + u0; tau f^2; ...; tau f^n) (Section 2, eq. (allatoncesystem)).
  * f: device [n][m], u0: device [m], rhs: device [n][m] (may alias f). */
 aao_status aao_build_rhs(aao_ctx *ctx, const double *f, const double *u0, double *rhs);
+
+/* Inhomogeneous Dirichlet data (Section 2, the boundary condition of eq.
+ * (heateq); Section 5, Example 3's hot wall): f^k += (the couplings of K to
+ * the boundary nodes) x (their values at t_k = k tau), the terms that move to
+ * the right-hand side when the boundary values are known; aao_build_rhs then
+ * scales f by tau.  2D finite differences only (any coefficient form).
+ * gb: device [n][2 m2 + 2 m1], per time level the values next to the west
+ * wall (x = 0, one per row, m2), the east wall (x = 1, m2), the south wall
+ * (y = 0, one per column, m1) and the north wall (y = 1, m1); f: device [n][m],
+ * updated in place.  AAO_EINVAL for another dimension, AAO_ESTATE for Q1. */
+aao_status aao_boundary_source(aao_ctx *ctx, const double *gb, double *f);
 
 /* y = L x, the all-at-once matrix (Section 2, eq. (allatoncesystem)).
  * x, y: device [n][m], must not alias. */

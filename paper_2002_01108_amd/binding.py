@@ -47,6 +47,8 @@ SIGNATURES = {
     "aao_set_side": (_c_int, [_vp, _c_int]),
     "aao_set_scheme": (_c_int, [_vp, _c_int]),
     "aao_set_discretisation": (_c_int, [_vp, _c_int]),
+    "aao_set_convection": (_c_int, [_vp, _c_double, _pdbl, _pdbl]),
+    "aao_boundary_source": (_c_int, [_vp, _vp, _vp]),
     "aao_cnn_param_count": (_c_int, []),
     "aao_cnn_set_params": (_c_int, [_vp, _pflt, _c_int]),
     "aao_cnn_get_params": (_c_int, [_vp, _pflt, _c_int]),
@@ -150,6 +152,17 @@ class Solver:
         ptrs = [a.ctypes.data_as(_pdbl) for a in arrs] + [None] * (3 - len(arrs))
         self._check(self.lib.aao_set_coefficient(self._h, *ptrs))
 
+    def set_convection(self, nu=None, wind=None):
+        """-nu Laplace + w . grad with upwinding on the unit square; wind =
+        (wx, wy) host arrays [m2][m1] at the interior nodes (include/aao.h).
+        No arguments: back to K = -Laplace."""
+        if wind is None:
+            self._check(self.lib.aao_set_convection(self._h, 0.0, None, None))
+            return
+        wx, wy = (np.ascontiguousarray(a, dtype=np.float64) for a in wind)
+        self._check(self.lib.aao_set_convection(self._h, float(nu), wx.ctypes.data_as(_pdbl),
+                                                wy.ctypes.data_as(_pdbl)))
+
     def set_inner(self, inner: str = "dst", cycles: int = 1):
         self._check(self.lib.aao_set_inner(self._h, INNERS[inner], cycles))
 
@@ -250,6 +263,12 @@ class Solver:
         out = self.new() if out is None else out
         self._check(self.lib.aao_build_rhs(self._h, _ptr(f), _ptr(u0), _ptr(out)))
         return out
+
+    def boundary_source(self, gb, f):
+        """f += boundary couplings x Dirichlet values gb (device [n][2 m2 + 2 m1]:
+        west, east, south, north walls per time level); f updated in place."""
+        self._check(self.lib.aao_boundary_source(self._h, _ptr(gb), _ptr(f)))
+        return f
 
     def apply_A(self, x, out=None):
         out = self.new() if out is None else out

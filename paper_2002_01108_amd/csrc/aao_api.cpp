@@ -71,6 +71,14 @@ struct aao_ctx {
   double amean = 1.0;
   double* tmu_mean[3] = {nullptr, nullptr, nullptr};  // amean * tau * mu_i
 
+  // convection-diffusion (aao_set_convection): var is also set, wface[0] holds
+  // tau (W, E, S, N) as four planes and wface[1] = wface[2] = null
+  bool conv = false;
+  double nu = 0.0;
+  std::vector<double> host_wind[2];      // wind at the interior nodes [m2][m1]
+  std::vector<double> host_planes;       // unscaled couplings [W, E, S, N][m2][m1]
+  double* cb = nullptr;                  // boundary couplings (aao_boundary_source)
+
   // inner solver of Step 2 (aao_set_inner)
   aao_inner inner = AAO_INNER_DST;
   aao_side side = AAO_RIGHT;     // aao_set_side
@@ -79,8 +87,9 @@ struct aao_ctx {
   // multigrid hierarchy (2D), built lazily for the current precision
   struct MgLevel {
     int m = 0;
-    void* wx = nullptr;   // [m][m+1] face weights, spectrum precision
-    void* wy = nullptr;   // [m+1][m]
+    void* wx = nullptr;   // [m][m+1] face weights, spectrum precision, or the four
+                          // coupling planes [W, E, S, N][m][m] (convection)
+    void* wy = nullptr;   // [m+1][m]; null with coupling planes
     void* E = nullptr;    // levels >= 1: correction, compact [nh][2][m][m]
     void* R = nullptr;    // levels >= 1: right-hand side
     void* Res = nullptr;  // residual on this level (compact)
@@ -537,10 +546,27 @@ MgGrid compact_view(void* p, int m) {
   return v;
 }
 
+// Upwinded convection-diffusion couplings [W, E, S, N][m2][m1] for the wind at
+// the nodes: nu/h^2 plus the upwind part |w|/h on the side the wind comes from.
+std::vector<double> upwind_planes(double nu, double h1, double h2, const std::vector<double>& w1,
+                                  const std::vector<double>& w2, int m1, int m2) {
+  const size_t pl = (size_t)m1 * m2;
+  std::vector<double> P(4 * pl);
+  const double dx = nu / (h1 * h1), dy = nu / (h2 * h2);
+  for (size_t p = 0; p < pl; ++p) {
+    P[p] = dx + std::max(w1[p], 0.0) / h1;
+    P[pl + p] = dx + std::max(-w1[p], 0.0) / h1;
+    P[2 * pl + p] = dy + std::max(w2[p], 0.0) / h2;
+    P[3 * pl + p] = dy + std::max(-w2[p], 0.0) / h2;
+  }
+  return P;
+}
+
 void mg_release(aao_ctx* c);
 
 // Level hierarchy for the current coefficient and precision: m -> (m-1)/2 while m
-// is odd and >= 3; coarse faces are harmonic means of the two fine faces they span.
+// is odd and >= 3; coarse faces are harmonic means of the two fine faces they span,
+// or (convection) coarse coupling planes from the wind at the coarse nodes.
 aao_status mg_build(aao_ctx* c) {
   const int want = (c->prec == AAO_FP64) ? 0 : 1;
   if (!c->mg.empty() && c->mg_prec == want) return AAO_OK;
@@ -555,24 +581,36 @@ aao_status mg_build(aao_ctx* c) {
     ay = c->host_face[1];
   }
   double h = c->h[0];
+  std::vector<double> w1, w2;            // convection: wind at this level's nodes
+  if (c->conv) {
+    w1 = c->host_wind[0];
+    w2 = c->host_wind[1];
+  }
   for (int lev = 0;; ++lev) {
     aao_ctx::MgLevel L;
     L.m = m;
     const double sc = c->tau / (h * h);
-    std::vector<double> wx(ax.size()), wy(ay.size());
-    for (size_t e = 0; e < ax.size(); ++e) wx[e] = sc * ax[e];
-    for (size_t e = 0; e < ay.size(); ++e) wy[e] = sc * ay[e];
+    std::vector<double> wx, wy;
+    if (c->conv) {
+      wx = upwind_planes(c->nu, h, h, w1, w2, m, m);
+      for (double& v : wx) v *= c->tau;
+    } else {
+      wx.resize(ax.size());
+      wy.resize(ay.size());
+      for (size_t e = 0; e < ax.size(); ++e) wx[e] = sc * ax[e];
+      for (size_t e = 0; e < ay.size(); ++e) wy[e] = sc * ay[e];
+    }
     if (want == 0) {
-      double *px, *py;
+      double *px, *py = nullptr;
       TRY(upload(c, &px, wx));
-      TRY(upload(c, &py, wy));
+      if (!c->conv) TRY(upload(c, &py, wy));
       L.wx = px;
       L.wy = py;
     } else {
       std::vector<float> fx(wx.begin(), wx.end()), fy(wy.begin(), wy.end());
-      float *px, *py;
+      float *px, *py = nullptr;
       TRY(upload(c, &px, fx));
-      TRY(upload(c, &py, fy));
+      if (!c->conv) TRY(upload(c, &py, fy));
       L.wx = px;
       L.wy = py;
     }
@@ -592,6 +630,19 @@ aao_status mg_build(aao_ctx* c) {
     c->mg.push_back(L);
     if (last) break;
     const int mc = (m - 1) / 2;
+    if (c->conv) {   // coarse node (J, I) is fine node (2J+1, 2I+1)
+      std::vector<double> c1((size_t)mc * mc), c2((size_t)mc * mc);
+      for (int J = 0; J < mc; ++J)
+        for (int I = 0; I < mc; ++I) {
+          c1[(size_t)J * mc + I] = w1[(size_t)(2 * J + 1) * m + 2 * I + 1];
+          c2[(size_t)J * mc + I] = w2[(size_t)(2 * J + 1) * m + 2 * I + 1];
+        }
+      w1.swap(c1);
+      w2.swap(c2);
+      m = mc;
+      h *= 2.0;
+      continue;
+    }
     std::vector<double> axc((size_t)mc * (mc + 1)), ayc((size_t)(mc + 1) * mc);
     for (int J = 0; J < mc; ++J)
       for (int I = 0; I <= mc; ++I) {
@@ -777,6 +828,8 @@ aao_status cnn_backward_run(aao_ctx* c, int B, int H, int W, float* dx) {
 aao_status cnn_tables(aao_ctx* c) {
   auto& n = c->cnn;
   const Geometry& g = c->g;
+  if (c->conv)
+    return fail(c, AAO_ESTATE, "the learned correction needs a diffusion coefficient on faces");
   if (!n.phik) {
     std::vector<float> phi(4 * (size_t)g.nh);
     std::vector<double> tw(2 * g.n);
@@ -882,6 +935,8 @@ aao_status spatial_solve(aao_ctx* c, void** cur, void** other, bool real_ends) {
         return fail(c, AAO_ESTATE, "the exact sine-transform solve needs a constant coefficient");
       return dst_solve(c, cur, other, false, real_ends);
     case AAO_INNER_DST_MEAN:
+      if (c->conv)
+        return fail(c, AAO_ESTATE, "convection-diffusion needs the multigrid inner solve");
       return dst_solve(c, cur, other, true, real_ends);
     case AAO_INNER_MG:
       return mg_solve(c, cur, other);
@@ -1154,6 +1209,10 @@ aao_status aao_set_coefficient(aao_ctx* c, const double* ax, const double* ay,
   const Geometry& g = c->g;
   if (g.q1 && ax) return fail(c, AAO_ESTATE, "Q1 elements need a constant coefficient");
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->conv = false;
+  c->host_planes.clear();
+  c->host_wind[0].clear();
+  c->host_wind[1].clear();
   if (!ax) {  // back to a = 1
     c->var = false;
     for (int d = 0; d < 3; ++d) {
@@ -1210,6 +1269,32 @@ aao_status aao_set_coefficient(aao_ctx* c, const double* ax, const double* ay,
   return AAO_OK;
 }
 
+aao_status aao_set_convection(aao_ctx* c, double nu, const double* wx, const double* wy) {
+  if (!c) return AAO_EINVAL;
+  if (!wx) return aao_set_coefficient(c, nullptr, nullptr, nullptr);
+  const Geometry& g = c->g;
+  if (g.dim != 2) return fail(c, AAO_EINVAL, "convection-diffusion needs a 2D grid");
+  if (!wy) return fail(c, AAO_EINVAL, "missing wind component");
+  if (g.q1) return fail(c, AAO_ESTATE, "Q1 elements need a constant coefficient");
+  if (!(nu > 0.0) || !isfinite(nu)) return fail(c, AAO_EINVAL, "nu must be positive and finite");
+  const size_t pl = (size_t)g.m1 * g.m2;
+  for (size_t p = 0; p < pl; ++p)
+    if (!isfinite(wx[p]) || !isfinite(wy[p])) return fail(c, AAO_EINVAL, "wind must be finite");
+  // drop any face coefficient (also releases the multigrid levels and CNN tables)
+  TRY(aao_set_coefficient(c, nullptr, nullptr, nullptr));
+  c->host_wind[0].assign(wx, wx + pl);
+  c->host_wind[1].assign(wy, wy + pl);
+  c->host_planes = upwind_planes(nu, c->h[0], c->h[1], c->host_wind[0], c->host_wind[1], g.m1,
+                                 g.m2);
+  std::vector<double> w(c->host_planes);
+  for (double& v : w) v *= c->tau;
+  TRY(upload(c, &c->wface[0], w));
+  c->nu = nu;
+  c->conv = true;
+  c->var = true;
+  return AAO_OK;
+}
+
 aao_status aao_set_inner(aao_ctx* c, aao_inner inner, int cycles) {
   if (!c || cycles < 1 || cycles > 1000) return AAO_EINVAL;
   switch (inner) {
@@ -1228,6 +1313,8 @@ aao_status aao_set_inner(aao_ctx* c, aao_inner inner, int cycles) {
   }
   if (c->g.q1 && inner != AAO_INNER_DST)
     return fail(c, AAO_ESTATE, "Q1 elements need the DST inner solve");
+  if (c->conv && (inner == AAO_INNER_DST_MEAN || inner == AAO_INNER_CNN))
+    return fail(c, AAO_ESTATE, "convection-diffusion needs the multigrid inner solve");
   c->inner = inner;
   c->inner_cycles = cycles;
   return AAO_OK;
@@ -1578,6 +1665,50 @@ aao_status aao_build_rhs(aao_ctx* ctx, const double* f, const double* u0, double
   gm.r2 = 0.0;
   gm.qk[0] = gm.qk[1] = 0.0;
   HIPCHK(ctx, launch_apply_L(gm, ctx->tmp, rhs, 0.0, 0.0, 0.0, ctx->stream));
+  return AAO_OK;
+}
+
+aao_status aao_boundary_source(aao_ctx* ctx, const double* gb, double* f) {
+  if (!ctx || !gb || !f) return AAO_EINVAL;
+  const Geometry& g = ctx->g;
+  if (g.dim != 2) return fail(ctx, AAO_EINVAL, "boundary data: 2D grids only");
+  if (g.q1) return fail(ctx, AAO_ESTATE, "boundary data: finite differences only");
+  const int m1 = g.m1, m2 = g.m2;
+  const size_t pl = (size_t)m1 * m2;
+  const double ix = 1.0 / (ctx->h[0] * ctx->h[0]), iy = 1.0 / (ctx->h[1] * ctx->h[1]);
+  // couplings of K to the nodes across each wall: west, east per row, south, north per column
+  std::vector<double> cb(2 * (size_t)(m1 + m2));
+  const auto& P = ctx->host_planes;
+  const auto& F = ctx->host_face;
+  for (int j = 0; j < m2; ++j) {
+    const size_t r = (size_t)j * m1;
+    if (ctx->conv) {
+      cb[j] = P[r];
+      cb[m2 + j] = P[pl + r + m1 - 1];
+    } else if (ctx->var) {
+      cb[j] = F[0][(size_t)j * (m1 + 1)] * ix;
+      cb[m2 + j] = F[0][(size_t)j * (m1 + 1) + m1] * ix;
+    } else {
+      cb[j] = cb[m2 + j] = ix;
+    }
+  }
+  for (int i = 0; i < m1; ++i) {
+    double* cs = &cb[2 * (size_t)m2];
+    if (ctx->conv) {
+      cs[i] = P[2 * pl + i];
+      cs[m1 + i] = P[3 * pl + (size_t)(m2 - 1) * m1 + i];
+    } else if (ctx->var) {
+      cs[i] = F[1][i] * iy;
+      cs[m1 + i] = F[1][(size_t)m2 * m1 + i] * iy;
+    } else {
+      cs[i] = cs[m1 + i] = iy;
+    }
+  }
+  // an earlier call may still read the table on the stream
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (!ctx->cb) TRY(dalloc(ctx, &ctx->cb, cb.size()));
+  HIPCHK(ctx, hipMemcpy(ctx->cb, cb.data(), cb.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(ctx, launch_boundary_source(gb, ctx->cb, f, g.n, m1, m2, ctx->stream));
   return AAO_OK;
 }
 

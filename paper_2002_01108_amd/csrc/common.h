@@ -98,6 +98,9 @@ struct Geometry {
 hipError_t launch_apply_L(const Geometry& g, const double* x, double* y, double c1, double c2,
                           double c3, hipStream_t s);
 // y = L x with the flux-form variable-coefficient operator; faces pre-scaled by tau/h^2.
+// 2D with ay == nullptr: ax holds the four coupling planes [W, E, S, N][m2][m1]
+// of a nonsymmetric five-point operator (node couples to its west, east, south,
+// north neighbour with -W, -E, -S, -N, diagonal W + E + S + N), pre-scaled by tau.
 hipError_t launch_apply_L_var(const Geometry& g, const double* x, double* y, const double* ax,
                               const double* ay, const double* az, hipStream_t s);
 
@@ -238,6 +241,11 @@ hipError_t launch_diffnorm(const double* a, const double* b, int64_t len, double
 // u^0 term of the second row of a two-step scheme; r2 = 0 for backward Euler)
 hipError_t launch_build_rhs(const double* f, const double* u0, double* y, int64_t nm, int64_t m,
                             double tau, double r2, hipStream_t s);
+// f[k] += the boundary couplings cb times the Dirichlet values gb[k] (2D):
+// gb [n][2 m2 + 2 m1] = west (m2), east (m2), south (m1), north (m1) walls;
+// cb the same layout without the time index.
+hipError_t launch_boundary_source(const double* gb, const double* cb, double* f, int n, int m1,
+                                  int m2, hipStream_t s);
 
 // ---------------------------------------------------------------- multigrid (2D)
 // One level's complex grid for all blocks: element (k, plane, j, i) at
@@ -247,6 +255,8 @@ struct MgGrid {
   int pitch = 0;
   int64_t pstride = 0, bstride = 0;
 };
+// Level couplings: face weights wx [m][m+1], wy [m+1][m], or, with wy == nullptr,
+// the four coupling planes [W, E, S, N][m][m] in wx (all pre-scaled by tau).
 template <typename T>
 hipError_t mg_rbgs(const MgGrid& e, const MgGrid& r, const void* wx, const void* wy,
                    const double* lam, int m, int nh, int color, int zero_init, hipStream_t s);

@@ -193,6 +193,27 @@ __global__ void k_build_rhs(const double* __restrict__ f, const double* __restri
   }
 }
 
+// One thread per (time level, row): the west and east boundary terms of the
+// row, and for the first / last row also the south / north terms of each
+// column, so no two threads touch the same entry.
+__global__ void k_boundary_source(const double* __restrict__ gb, const double* __restrict__ cb,
+                                  double* __restrict__ f, int n, int m1, int m2) {
+  const int64_t nb = 2LL * m1 + 2LL * m2;
+  const int64_t total = (int64_t)n * m2;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(e / m2), j = (int)(e - (int64_t)k * m2);
+    const double* g = gb + k * nb;
+    double* row = f + ((int64_t)k * m2 + j) * m1;
+    row[0] += cb[j] * g[j];
+    row[m1 - 1] += cb[m2 + j] * g[m2 + j];
+    if (j == 0)
+      for (int i = 0; i < m1; ++i) row[i] += cb[2 * m2 + i] * g[2 * m2 + i];
+    if (j == m2 - 1)
+      for (int i = 0; i < m1; ++i) row[i] += cb[2 * m2 + m1 + i] * g[2 * m2 + m1 + i];
+  }
+}
+
 unsigned simple_grid(int64_t len) {
   int64_t b = (len + 255) / 256;
   if (b > 16384) b = 16384;
@@ -279,6 +300,14 @@ hipError_t launch_build_rhs(const double* f, const double* u0, double* y, int64_
                             double tau, double r2, hipStream_t s) {
   hipLaunchKernelGGL(k_build_rhs, dim3(simple_grid(nm)), dim3(256), 0, s, f, u0, y, nm, m, tau,
                      r2);
+  return hipGetLastError();
+}
+
+hipError_t launch_boundary_source(const double* gb, const double* cb, double* f, int n, int m1,
+                                  int m2, hipStream_t s) {
+  if (n < 1 || m1 < 1 || m2 < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_boundary_source, dim3(simple_grid((int64_t)n * m2)), dim3(256), 0, s, gb,
+                     cb, f, n, m1, m2);
   return hipGetLastError();
 }
 

@@ -7,8 +7,11 @@
 // All n/2+1 blocks are processed by every launch (one thread per grid point
 // and block).  Smoother: red-black Gauss-Seidel (red: i1 + i2 even).
 // Restriction: full weighting (transpose of bilinear interpolation / 4).
-// Prolongation: bilinear.  Coarse operators are rediscretised with harmonic
-// face averages, prepared on the host as face weights w = tau/h_l^2 * a.
+// Prolongation: bilinear.  Coarse operators are rediscretised on the host:
+// face weights w = tau/h_l^2 * a with harmonic face averages (flux form), or
+// the four coupling planes tau (W, E, S, N) of a nonsymmetric five-point
+// operator (wy == nullptr; upwinded convection-diffusion with the wind taken
+// at the coarse nodes).
 //
 // A grid view addresses element (k, plane, j, i) at
 //   p + k*bstride + plane*pstride + j*pitch + i
@@ -27,13 +30,31 @@ template <typename T> struct GView {
   }
 };
 
-// sum_f w_f e_nbr (complex) and the diagonal sum of w_f at (j, i)
+// couplings of node (j, i) to its west, east, south and north neighbours
+template <typename T>
+__device__ __forceinline__ void couplings(const T* __restrict__ wx, const T* __restrict__ wy,
+                                          int j, int i, int m, T& wl, T& wr, T& wd, T& wu) {
+  if (wy) {
+    wl = wx[(int64_t)j * (m + 1) + i];
+    wr = wx[(int64_t)j * (m + 1) + i + 1];
+    wd = wy[(int64_t)j * m + i];
+    wu = wy[(int64_t)(j + 1) * m + i];
+  } else {
+    const int64_t p = (int64_t)j * m + i, mm = (int64_t)m * m;
+    wl = wx[p];
+    wr = wx[p + mm];
+    wd = wx[p + 2 * mm];
+    wu = wx[p + 3 * mm];
+  }
+}
+
+// sum of coupling * e_nbr (complex) and the diagonal (sum of couplings) at (j, i)
 template <typename T>
 __device__ __forceinline__ void nbr_sum(const GView<T>& e, int k, int j, int i, int m,
                                         const T* __restrict__ wx, const T* __restrict__ wy,
                                         T& sr, T& si, T& d) {
-  const T wl = wx[(int64_t)j * (m + 1) + i], wr = wx[(int64_t)j * (m + 1) + i + 1];
-  const T wd = wy[(int64_t)j * m + i], wu = wy[(int64_t)(j + 1) * m + i];
+  T wl, wr, wd, wu;
+  couplings(wx, wy, j, i, m, wl, wr, wd, wu);
   d = wl + wr + wd + wu;
   sr = T(0);
   si = T(0);
@@ -64,8 +85,8 @@ __global__ void k_rbgs(GView<T> e, GView<T> r, const T* __restrict__ wx,
     }
     T sr, si, d;
     if (zero_init) {
-      const T wl = wx[(int64_t)j * (m + 1) + i], wr = wx[(int64_t)j * (m + 1) + i + 1];
-      const T wd = wy[(int64_t)j * m + i], wu = wy[(int64_t)(j + 1) * m + i];
+      T wl, wr, wd, wu;
+      couplings(wx, wy, j, i, m, wl, wr, wd, wu);
       d = wl + wr + wd + wu;
       sr = si = T(0);
     } else {

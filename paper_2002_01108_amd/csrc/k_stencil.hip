@@ -3,8 +3,10 @@
 //   y^k = (r0 I + tau K) x^k + r1 x^{k-1} + r2 x^{k-2},  x^{<1} := 0,
 // with coefficient 1 in place of r0 on the first level (a backward-Euler first
 // step); backward Euler is (r0, r1, r2) = (1, -1, 0), BDF2 (3/2, -2, 1/2).
-// K the 3/5/7-point -Laplacian (constant coefficient) or the flux-form
-// discretisation of -div(a grad .) with coefficients on cell faces.
+// K the 3/5/7-point -Laplacian (constant coefficient), the flux-form
+// discretisation of -div(a grad .) with coefficients on cell faces, or (2D, no
+// y-face array) a nonsymmetric five-point operator given by four coupling
+// planes W, E, S, N per node (upwinded convection-diffusion).
 //
 // One thread owns one spatial point and walks a chunk of time levels, keeping
 // x^{k-1} (and x^{k-2}) in registers, so x is read from HBM once per chunk
@@ -165,7 +167,14 @@ __global__ __launch_bounds__(256) void k_apply_L25(
   for (int t = 0; t < TY; ++t) {
     const int j = j0 + t;
     const bool ok = inx && j < m2;
-    if (VAR) {
+    if (VAR && DIM == 2 && ay == nullptr) {   // coupling planes [W, E, S, N][m2][m1]
+      const int64_t p = (int64_t)j * m1 + i1;
+      wxm[t] = ok ? ax[p] : 0.0;
+      wxp[t] = ok ? ax[p + pl] : 0.0;
+      wym[t] = ok ? ax[p + 2 * pl] : 0.0;
+      wyp[t] = ok ? ax[p + 3 * pl] : 0.0;
+      wzm[t] = wzp[t] = 0.0;
+    } else if (VAR) {
       const int64_t fx = ((int64_t)i3 * m2 + j) * (m1 + 1) + i1;
       const int64_t fy = ((int64_t)i3 * (m2 + 1) + j) * m1 + i1;
       wxm[t] = ok ? ax[fx] : 0.0;

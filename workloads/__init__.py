@@ -2,8 +2,9 @@
 
 This module is shared by the CPU oracle and the GPU path.  It draws and samples
 inputs only: the source f, the initial value u0, the diffusion coefficient a on
-cell faces, and the manufactured solution of the paper's variable-coefficient
-example (Section 5, Example 2).  It holds none of the method's arithmetic (no
+cell faces, the manufactured solution of the paper's variable-coefficient
+example (Section 5, Example 2), and the wind and hot-wall boundary data of its
+convection-diffusion example (Section 5, Example 3).  It holds none of the method's arithmetic (no
 operator, transform, preconditioner or Krylov step).
 
 Conventions
@@ -37,7 +38,7 @@ class Workload:
     T: float = 1.0
     eps: float | None = None          # None -> sqrt(tau) capped at 0.5
     u0_kind: str = "modes"            # "sine" | "modes" | "zero"
-    coefficient: str = "const"        # "const" | "grf"
+    coefficient: str = "const"        # "const" | "grf" | "wind"
     precision: str = "fp64"           # preconditioner arithmetic
     inner: str = "dst"
     extra: dict = field(default_factory=dict)
@@ -75,7 +76,36 @@ WORKLOADS = {
                                precision="fp32"),
     "varheat2d_255x256": Workload("varheat2d_255x256", 2, 255, 256, u0_kind="modes",
                                   coefficient="grf", inner="cnn"),
+    # Section 5, Example 3 on (-1, 1)^2: J+1 = 256, N = 256, eps = 0.5 tau
+    "cd2d_255x256": Workload("cd2d_255x256", 2, 255, 256, eps=0.5 / 256, u0_kind="zero",
+                             coefficient="wind", inner="mg"),
 }
+
+# Section 5, Example 3: diffusion 1/200 on (-1, 1)^2, circulating wind, a hot
+# wall x = 1 whose temperature rises as 1 - exp(-10 t), zero elsewhere and at t = 0.
+CD_NU = 1.0 / 200.0
+
+
+def cd_nodes(m1: int) -> np.ndarray:
+    """Interior node coordinates on (-1, 1): -1 + (i+1) h, h = 2/(m1+1)."""
+    return -1.0 + (2.0 / (m1 + 1)) * np.arange(1, m1 + 1)
+
+
+def cd_wind(m1: int):
+    """(w1, w2) = (2y(1-x^2), -2x(1-y^2)) at the interior nodes, [m1][m1] (y, x)."""
+    x = cd_nodes(m1)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    return 2.0 * Y * (1.0 - X * X), -2.0 * X * (1.0 - Y * Y)
+
+
+def cd_hot_wall(m1: int, n: int, T: float = 1.0) -> np.ndarray:
+    """Boundary values [n][4 m1] at t_k = (k+1) T/n next to the west, east,
+    south and north walls (m1 each): 1 - exp(-10 t) on the east wall x = 1,
+    zero on the others."""
+    g = np.zeros((n, 4 * m1))
+    t = (np.arange(n) + 1) * (T / n)
+    g[:, m1:2 * m1] = (1.0 - np.exp(-10.0 * t))[:, None]
+    return g
 
 
 def node_coords(m1: int) -> np.ndarray:
@@ -215,7 +245,7 @@ def manufactured_faces(m1: int):
 def make(workload: Workload | str, seed: int = 0):
     """(f [n][m], u0 [m], faces or None) for a named or given workload."""
     w = WORKLOADS[workload] if isinstance(workload, str) else workload
-    f = source(w.n, w.m1, w.dim, seed)
+    f = np.zeros((w.n, w.m)) if w.coefficient == "wind" else source(w.n, w.m1, w.dim, seed)
     u0 = initial_value(w.m1, w.dim, w.u0_kind, seed + 1)
     faces = grf_faces(w.m1, w.dim, seed + 2) if w.coefficient == "grf" else None
     return f, u0, faces
