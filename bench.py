@@ -49,6 +49,8 @@ def parse():
                     help="skip the BEC vs block-circulant comparison of Section 5, Table 1")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the variable-coefficient learned/multigrid leg")
+    ap.add_argument("--no-cd", action="store_true",
+                    help="skip the convection-diffusion leg (Section 5, Example 3 stand-in)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=64)
@@ -212,11 +214,48 @@ def copy_calibration():
                       "copies": 5}), flush=True)
 
 
-def cpu_baseline(w, f, u0, sample_steps):
-    """The oracle's GMRES-BEC on the first `sample_steps` time levels of the
-    same workload (same grid, tau, eps, source and u0), single BLAS thread."""
+def cpu_baseline_leg(w, f, u0, sample_steps, checks, timed=True):
+    """The one place this benchmark runs the CPU oracle.
+
+    (a) timed = True: the oracle's GMRES-BEC on the first `sample_steps` time
+        levels of the main workload (same grid, tau, eps, source and u0), one
+        BLAS thread: the `cpu_baseline` record.
+    (b) `checks`: (record, spec, u) triples left by the GPU legs; for each spec
+        the oracle's FP64 solution of the same system (sequential time
+        stepping, exact up to rounding) is computed once and the GPU solution's
+        relative error against it is written into the record as
+        `rel_err_vs_oracle`.  Specs: ("heat", name), ("heat_bdf2", name),
+        ("heat_faces", name), ("cd", name)."""
+    import workloads as W
+    from oracle import bdf, cd, heat
+    refs = {}
+
+    def reference(spec):
+        kind, name = spec
+        v = W.WORKLOADS[name]
+        fv, u0v, faces = W.make(v)
+        if kind == "heat":
+            p = heat.Problem(v.m1, v.dim, v.n, T=v.T, eps=v.epsilon)
+            return p.exact(p.rhs(fv, u0v))
+        if kind == "heat_bdf2":
+            p = bdf.Problem(v.m1, v.dim, v.n, r=bdf.BDF2, T=v.T, eps=v.epsilon)
+            return p.exact(p.rhs(fv, u0v))
+        if kind == "heat_faces":
+            p = heat.Problem(v.m1, v.dim, v.n, T=v.T, eps=v.epsilon, faces=faces)
+            return p.exact(p.rhs(fv, u0v))
+        if kind == "cd":
+            p = cd.Problem(v.m1, v.n, T=v.T, eps=v.epsilon)
+            return p.exact(p.rhs())
+        raise ValueError(kind)
+
+    for rec, spec, u in checks:
+        if spec not in refs:
+            refs[spec] = reference(spec)
+        ex = refs[spec]
+        rec["rel_err_vs_oracle"] = float(np.linalg.norm(u - ex) / np.linalg.norm(ex))
+    if not timed:
+        return None
     from threadpoolctl import threadpool_limits
-    from oracle import heat
     ns = min(sample_steps, w.n)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
@@ -232,10 +271,10 @@ def cpu_baseline(w, f, u0, sample_steps):
                       f"{dt:.1f} s"}
 
 
-def bdf2_leg(w, fd, u0d, f, u0, tol, restart, steps, oracle_check):
+def bdf2_leg(w, fd, u0d, tol, restart, steps, checks):
     """The same workload with BDF2 in time (backward-Euler first step): FP64
-    solve to the same tolerance, with the error against the oracle's
-    sequential BDF2 solution."""
+    solve to the same tolerance; its solution goes to `checks` for the error
+    against the oracle's sequential BDF2 solution."""
     import torch
     from paper_2002_01108_amd import Solver
     s = Solver(w.dim, w.m1, w.n, T=w.T, eps=w.epsilon, precision="fp64")
@@ -243,12 +282,7 @@ def bdf2_leg(w, fd, u0d, f, u0, tol, restart, steps, oracle_check):
     t, info, _, u, _ = time_solver(s, fd, u0d, tol, restart, steps, 1, [])
     rec = {"value": w.dof / t, "ms_per_step": t * 1e3, "gmres_iters": info["iters"],
            "rel_res": info["final_res"], "eps": w.epsilon}
-    if oracle_check:
-        from oracle import bdf
-        p = bdf.Problem(w.m1, w.dim, w.n, r=bdf.BDF2, T=w.T, eps=w.epsilon)
-        exact = p.exact(p.rhs(f, u0))
-        rec["rel_err_vs_oracle"] = float(np.linalg.norm(u.cpu().numpy() - exact)
-                                         / np.linalg.norm(exact))
+    checks.append((rec, ("heat_bdf2", w.name), u.cpu().numpy()))
     torch.cuda.synchronize()
     return rec
 
@@ -311,13 +345,74 @@ def table1_leg(steps):
     return out
 
 
-def learned_leg(tol, steps, oracle_check, train_fields=4, train_steps=1500, batch=8):
+# Section 5, Table 3 (Example 3, Q1 + SUPG, one ILU-smoothed V-cycle per
+# block), row N = 2^8, J+1 = 2^8 as printed: BEC / BC (iterations, CPU s, RES);
+# MATLAB on 2 x 14-core Xeon E5-2690 v4.  Context for the stand-in, not a target.
+TABLE3_PRINTED = {"bec": (5, 45.13, 1.09e-8), "bc": (22, 160.84, 7.56e-8)}
+
+
+def cd_leg(steps, checks):
+    """Convection-diffusion stand-in for Section 5, Example 3 (cd2d_255x256:
+    J+1 = 256, N = 256, circulating wind, hot wall, upwind differences, V-cycle
+    inner solves).  One step = boundary load + right-hand side + solve.
+    Table 3's solver set-up (left GMRES(50) from zero to a 1e-7 drop of the
+    preconditioned residual) with BEC (eps = 0.5 tau) and BC (eps = 1) and
+    three V-cycles per block, BEC with one V-cycle, and right FGMRES with BEC
+    to RES 1e-8 (whose solution is checked against the oracle)."""
+    import torch
+    import workloads as W
+    from paper_2002_01108_amd import Solver
+    w = W.WORKLOADS["cd2d_255x256"]
+    w1, w2 = W.cd_wind(w.m1)
+    gb = torch.from_numpy(W.cd_hot_wall(w.m1, w.n, w.T)).cuda()
+    u0 = torch.zeros(w.m, dtype=torch.float64, device="cuda")
+    out = {"workload": w.name, "dof": w.dof, "nu": W.CD_NU,
+           "discretisation": "five-point upwind differences on (-1, 1)^2 (Q1 + SUPG in the paper)"}
+    runs = (("bec_left", w.epsilon, "left", 1e-7, 3), ("bc_left", 1.0, "left", 1e-7, 3),
+            ("bec_left_1vcycle", w.epsilon, "left", 1e-7, 1),
+            ("bec_fgmres", w.epsilon, "right", 1e-8, 3))
+    for name, eps, side, tol, cycles in runs:
+        s = Solver(2, w.m1, w.n, T=w.T, eps=eps, precision="fp64")
+        s.set_convection(W.CD_NU / 4.0, (w1 / 2.0, w2 / 2.0))   # (-1, 1)^2 -> unit square
+        s.set_inner("mg", cycles)
+        s.set_side(side)
+        f, rhs, u = s.new(), s.new(), s.new()
+
+        def step():
+            f.zero_()
+            s.boundary_source(gb, f)
+            s.build_rhs(f, u0, out=rhs)
+            return s.solve(rhs, tol=tol, maxit=300, restart=50, u=u)[1]
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        rec = {"eps": eps, "side": side, "tol": tol, "vcycles": cycles,
+               "gmres_iters": info["iters"], "ms_per_step": dt * 1e3,
+               "rel_res": info["final_res"], "value": w.dof / dt}
+        if name in ("bec_left", "bc_left"):
+            it, cpu_s, res = TABLE3_PRINTED[name[:-5]]
+            rec["paper"] = {"iters": it, "cpu_s": cpu_s, "rel_res": res}
+        if name == "bec_fgmres":
+            checks.append((rec, ("cd", w.name), u.cpu().numpy()))
+        print(f"[cd] {name}: {info['iters']} iterations, {dt * 1e3:.2f} ms, "
+              f"RES {info['final_res']:.3e}", file=sys.stderr, flush=True)
+        out[name] = rec
+        del s, f, rhs, u
+        torch.cuda.empty_cache()
+    return out
+
+
+def learned_leg(tol, steps, checks, train_fields=4, train_steps=1500, batch=8):
     """Variable-coefficient workload: train the learned inner solve on the GPU,
     then time FGMRES with it against the multigrid fallback and the
     mean-coefficient sine-transform solve.  Returns a dict for the JSON line."""
     import torch
     import workloads as W
-    from oracle import cnn
     from paper_2002_01108_amd import Solver
 
     w = W.WORKLOADS["varheat2d_255x256"]
@@ -327,7 +422,7 @@ def learned_leg(tol, steps, oracle_check, train_fields=4, train_steps=1500, batc
     fd = torch.from_numpy(f).cuda()
     u0d = torch.from_numpy(u0).cuda()
     t0 = time.perf_counter()
-    s.cnn_set_params(cnn.init_params(0).astype(np.float32))
+    s.cnn_set_params(W.cnn_init_params(0).astype(np.float32))
     ys = np.random.default_rng(1000).standard_normal((train_fields, w.n, w.m))
     npairs = s.cnn_make_pairs(torch.from_numpy(ys).cuda(), target_cycles=20)
     idx = np.random.default_rng(1001).integers(0, npairs, size=(train_steps, batch))
@@ -338,11 +433,6 @@ def learned_leg(tol, steps, oracle_check, train_fields=4, train_steps=1500, batc
            "train": {"fields": train_fields, "pairs": npairs, "steps": train_steps, "batch": batch,
                      "seconds": t_train, "loss_first": float(np.mean(loss[:20])),
                      "loss_last": float(np.mean(loss[-100:]))}}
-    exact = None
-    if oracle_check:
-        from oracle import heat
-        p = heat.Problem(w.m1, w.dim, w.n, eps=w.epsilon, faces=faces)
-        exact = p.exact(p.rhs(f, u0))
     trained = s.cnn_get_params()
     # "mg_sweep": the learned inner solve with a zero network, i.e. the V-cycle
     # plus the red-black sweep that wraps the network (the control that isolates
@@ -359,9 +449,7 @@ def learned_leg(tol, steps, oracle_check, train_fields=4, train_steps=1500, batc
         t, info, _, u, _ = time_solver(s, fd, u0d, tol, 50, steps, 1, [])
         rec = {"value": w.dof / t, "ms_per_step": t * 1e3, "gmres_iters": info["iters"],
                "rel_res": info["final_res"]}
-        if exact is not None:
-            rec["rel_err_vs_oracle"] = float(np.linalg.norm(u.cpu().numpy() - exact)
-                                             / np.linalg.norm(exact))
+        checks.append((rec, ("heat_faces", w.name), u.cpu().numpy()))
         out[inner] = rec
     return out
 
@@ -450,12 +538,8 @@ def main():
     out["kernels"]["apply_L"]["note"] = "standalone aao_apply_A, 20 calls on the workload's rhs"
     s.profile(None)
 
-    if not args.no_oracle_check:
-        from oracle import heat
-        p = heat.Problem(w.m1, w.dim, w.n, eps=w.epsilon)
-        exact = p.exact(p.rhs(f, u0))
-        got = u.cpu().numpy()
-        out["rel_err_vs_oracle"] = float(np.linalg.norm(got - exact) / np.linalg.norm(exact))
+    checks = []      # (record, oracle spec, GPU solution) for the cpu_baseline leg
+    checks.append((out, ("heat", w.name), u.cpu().numpy()))
 
     variants = {}
     for vp in [v for v in args.variants.split(",") if v and v != prec]:
@@ -468,25 +552,26 @@ def main():
                                        1, [])
         rec = {"value": dof / tv, "ms_per_step": tv * 1e3, "gmres_iters": iv["iters"],
                "rel_res": iv["final_res"]}
-        if "rel_err_vs_oracle" in out:
-            rec["rel_err_vs_oracle"] = float(np.linalg.norm(uv.cpu().numpy() - exact)
-                                             / np.linalg.norm(exact))
+        checks.append((rec, ("heat", w.name), uv.cpu().numpy()))
         variants[vp] = rec
     if variants:
         out["variants"] = variants
     if not args.no_bdf2:
-        out["bdf2"] = bdf2_leg(w, fd, u0d, f, u0, args.tol, restart, max(1, args.steps // 2),
-                               not args.no_oracle_check)
+        out["bdf2"] = bdf2_leg(w, fd, u0d, args.tol, restart, max(1, args.steps // 2), checks)
     if not args.no_table1:
         out["table1"] = table1_leg(max(1, args.steps // 2))
     if not args.no_learned:
         # the variable-coefficient system is worse conditioned: RES 1e-9 keeps the
         # error against the oracle at the 1e-8 level the comparison is made at
-        out["learned"] = learned_leg(args.tol / 10, max(1, args.steps // 2),
-                                     not args.no_oracle_check)
+        out["learned"] = learned_leg(args.tol / 10, max(1, args.steps // 2), checks)
+    if not args.no_cd:
+        out["cd"] = cd_leg(max(1, args.steps // 2), checks)
 
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, f, u0, args.cpu_sample_steps)
+    cpu = cpu_baseline_leg(w, f, u0, args.cpu_sample_steps,
+                           [] if args.no_oracle_check else checks,
+                           timed=not args.no_cpu_baseline)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

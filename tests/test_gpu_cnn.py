@@ -34,7 +34,7 @@ def rel(a, b):
 
 
 def params_for(seed):
-    p = cnn.init_params(seed)
+    p = W.cnn_init_params(seed)
     return p + 0.05 * np.random.default_rng(seed + 100).standard_normal(p.size)
 
 
@@ -76,14 +76,14 @@ def test_set_params_validation():
     s = solver()
     with pytest.raises(AaoError):
         s.cnn_set_params(np.zeros(10, np.float32))
-    bad = cnn.init_params(0).astype(np.float32)
+    bad = W.cnn_init_params(0).astype(np.float32)
     bad[3] = np.nan
     with pytest.raises(AaoError):
         s.cnn_set_params(bad)
     with pytest.raises(AaoError):
         s.set_inner("cnn")          # no parameters yet
-    s.cnn_set_params(cnn.init_params(0).astype(np.float32))
-    assert np.array_equal(s.cnn_get_params(), cnn.init_params(0).astype(np.float32))
+    s.cnn_set_params(W.cnn_init_params(0).astype(np.float32))
+    assert np.array_equal(s.cnn_get_params(), W.cnn_init_params(0).astype(np.float32))
 
 
 def test_learned_inner_solve_matches_oracle():
@@ -180,7 +180,7 @@ def test_trained_network_gains_over_multigrid():
     faces = W.grf_faces(m1, 2, seed=2)
     p = heat.Problem(m1, 2, n, faces=faces)
     s = solver(m1, n, faces)
-    s.cnn_set_params(cnn.init_params(11).astype(np.float32))
+    s.cnn_set_params(W.cnn_init_params(11).astype(np.float32))
     rng = np.random.default_rng(12)
     ys = rng.standard_normal((6, n, p.m))
     npairs = s.cnn_make_pairs(dev(ys), target_cycles=20)

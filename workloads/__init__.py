@@ -249,3 +249,16 @@ def make(workload: Workload | str, seed: int = 0):
     u0 = initial_value(w.m1, w.dim, w.u0_kind, seed + 1)
     faces = grf_faces(w.m1, w.dim, seed + 2) if w.coefficient == "grf" else None
     return f, u0, faces
+
+
+def cnn_init_params(seed: int = 0, C: int = 8) -> np.ndarray:
+    """Initial parameters of the learned inner solve, drawn seeded on the host in
+    the library's flat layout W1[C][3][3][3] G1[C][4] H1[C][4] W2[C][C][3][3]
+    G2[C][4] H2[C][4] W3[2][C][3][3] b3[2]: He-normal convolution weights, zero
+    FiLM maps and bias (FP64; the library stores FP32)."""
+    rng = np.random.default_rng(seed)
+    w1 = rng.standard_normal(C * 27) * np.sqrt(2.0 / 27)
+    w2 = rng.standard_normal(C * C * 9) * np.sqrt(2.0 / (9 * C))
+    w3 = rng.standard_normal(2 * C * 9) * np.sqrt(1.0 / (9 * C))
+    film = np.zeros(2 * C * 4)
+    return np.concatenate([w1, film, w2, film, w3, np.zeros(2)])
