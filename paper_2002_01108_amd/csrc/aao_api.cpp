@@ -524,7 +524,7 @@ aao_status dst_solve(aao_ctx* c, void** cur, void** other, bool mean, bool real_
 }
 
 // ---------------------------------------------------------------- multigrid inner solve
-const int kCoarseSweeps = 16;  // red-black sweeps from zero on the coarsest grid
+constexpr int kCoarseSweeps = 16;  // red-black sweeps from zero on the coarsest grid
 
 double harmonic(double a, double b) { return 2.0 * a * b / (a + b); }
 
@@ -623,7 +623,9 @@ aao_status mg_build(aao_ctx* c) {
       L.R = p;
     }
     const bool last = (m < 3) || (m % 2 == 0);
-    if (!last) {
+    // residual, and the second iterate buffer of the out-of-place sweeps
+    // (prolonged iterate before post-smoothing; ping-pong on the coarsest level)
+    if (!last || m > 1) {
       TRY(dalloc(c, &p, cells * esz));
       L.Res = p;
     }
@@ -679,25 +681,33 @@ aao_status vcycle(aao_ctx* c, size_t lev, const MgGrid& R, const MgGrid& E) {
   const auto& L = c->mg[lev];
   const int nh = c->g.nh, m = L.m;
   hipStream_t s = c->stream;
-  auto sweep = [&](int zero_init) -> aao_status {
-    HIPCHK(c, mg_rbgs<T>(E, R, L.wx, L.wy, c->lam, m, nh, 0, zero_init, s));
-    HIPCHK(c, mg_rbgs<T>(E, R, L.wx, L.wy, c->lam, m, nh, 1, 0, s));
-    return AAO_OK;
-  };
+  // one red-black smoothing step per launch (with the residual after the
+  // pre-smoothing step fused into it)
   if (lev + 1 == c->mg.size()) {
-    const int sweeps = (m == 1) ? 1 : kCoarseSweeps;  // one point: the first sweep is exact
-    for (int i = 0; i < sweeps; ++i) TRY(sweep(i == 0));
+    if (m == 1) {   // one point: the first sweep is exact
+      HIPCHK(c, mg_sweep<T>(E, E, R, nullptr, L.wx, L.wy, c->lam, m, nh, 1, s));
+      return AAO_OK;
+    }
+    // sweeps alternate between the two buffers; an even count ends in E
+    static_assert(kCoarseSweeps % 2 == 0, "the last coarse sweep must write E");
+    const MgGrid X = compact_view(L.Res, m);
+    for (int i = 0; i < kCoarseSweeps; ++i) {
+      const MgGrid& from = (i % 2 == 0) ? E : X;
+      const MgGrid& to = (i % 2 == 0) ? X : E;
+      HIPCHK(c, mg_sweep<T>(from, to, R, nullptr, L.wx, L.wy, c->lam, m, nh, i == 0, s));
+    }
     return AAO_OK;
   }
-  TRY(sweep(1));
   const MgGrid res = compact_view(L.Res, m);
-  HIPCHK(c, mg_residual<T>(E, R, res, L.wx, L.wy, c->lam, m, nh, s));
+  HIPCHK(c, mg_sweep<T>(E, E, R, &res, L.wx, L.wy, c->lam, m, nh, 1, s));
   const auto& C = c->mg[lev + 1];
   const MgGrid Rc = compact_view(C.R, C.m), Ec = compact_view(C.E, C.m);
   HIPCHK(c, mg_restrict<T>(res, Rc, m, C.m, nh, s));
   TRY(vcycle<T>(c, lev + 1, Rc, Ec));
-  HIPCHK(c, mg_prolong_add<T>(Ec, E, C.m, m, nh, s));
-  TRY(sweep(0));
+  // the residual is no longer needed: its buffer takes E + P e_c, and the
+  // post-smoothing step writes back to E
+  HIPCHK(c, mg_prolong_add<T>(Ec, E, res, C.m, m, nh, s));
+  HIPCHK(c, mg_sweep<T>(res, E, R, nullptr, L.wx, L.wy, c->lam, m, nh, 0, s));
   return AAO_OK;
 }
 

@@ -4,8 +4,10 @@
 // V-cycle with one pre- and one post-smoothing step, linear interpolation and
 // its transpose (Section 4, closing paragraphs; Section 5, Example 2).
 //
-// All n/2+1 blocks are processed by every launch (one thread per grid point
-// and block).  Smoother: red-black Gauss-Seidel (red: i1 + i2 even).
+// All n/2+1 blocks are processed by every launch.  Smoother: red-black
+// Gauss-Seidel (red: i1 + i2 even), one red and one black half sweep per
+// launch (tiled, see k_rbgs_fused); the other kernels take one thread per
+// grid point and block.
 // Restriction: full weighting (transpose of bilinear interpolation / 4).
 // Prolongation: bilinear.  Coarse operators are rediscretised on the host:
 // face weights w = tau/h_l^2 * a with harmonic face averages (flux form), or
@@ -124,6 +126,112 @@ __global__ void k_residual(GView<T> e, GView<T> r, GView<T> res, const T* __rest
   }
 }
 
+// One smoothing step (a red then a black half sweep) in one pass over the
+// data, optionally followed by the residual r - B e on the same points.  A
+// block owns a TX x TY tile of one frequency block: e (old values, halo 3) and
+// r (halo 2) are staged in LDS, the red points are updated on the tile plus a
+// ring of two, the black points on the tile plus one (their red neighbours are
+// then all new), and the residual on the tile (whose neighbours are then all
+// new).  The halo rings repeat the neighbouring tiles' updates with the same
+// inputs, so every point gets the value the two separate half sweeps give.
+// Outside the grid e and r are zero (Dirichlet).  The old iterate is read from
+// e and the new one written to eo: blocks read their neighbours' old values,
+// so eo may equal e only when the old iterate is zero (zero_init, e unread).
+constexpr int FTX = 64, FTY = 16;
+
+template <typename T, bool RES>
+__global__ __launch_bounds__(256) void k_rbgs_fused(GView<T> e, GView<T> eo, GView<T> r,
+                                                    GView<T> res,
+                                                    const T* __restrict__ wx,
+                                                    const T* __restrict__ wy,
+                                                    const double* __restrict__ lam, int m,
+                                                    int zero_init) {
+  constexpr int EH = 3, EX = FTX + 2 * EH, EY = FTY + 2 * EH;   // e tile with its halo
+  constexpr int RH = 2, RX = FTX + 2 * RH, RY = FTY + 2 * RH;   // r tile with its halo
+  __shared__ T se[2][EY][EX];
+  __shared__ T sr[2][RY][RX];
+  const int k = blockIdx.z;
+  const int x0 = blockIdx.x * FTX, y0 = blockIdx.y * FTY;
+  const T lr = (T)lam[2 * k], li = (T)lam[2 * k + 1];
+  for (int q = threadIdx.x; q < EY * EX; q += 256) {
+    const int ly = q / EX, lx = q % EX;
+    const int j = y0 - EH + ly, i = x0 - EH + lx;
+    T vr = T(0), vi = T(0);
+    if (!zero_init && j >= 0 && j < m && i >= 0 && i < m) {
+      const T* p = e.at(k, j, i);
+      vr = p[0];
+      vi = p[e.pstride];
+    }
+    se[0][ly][lx] = vr;
+    se[1][ly][lx] = vi;
+  }
+  for (int q = threadIdx.x; q < RY * RX; q += 256) {
+    const int ly = q / RX, lx = q % RX;
+    const int j = y0 - RH + ly, i = x0 - RH + lx;
+    T vr = T(0), vi = T(0);
+    if (j >= 0 && j < m && i >= 0 && i < m) {
+      const T* p = r.at(k, j, i);
+      vr = p[0];
+      vi = p[r.pstride];
+    }
+    sr[0][ly][lx] = vr;
+    sr[1][ly][lx] = vi;
+  }
+  __syncthreads();
+  // Gauss-Seidel update of the points of one colour in the tile plus a ring
+  // of `ring`: e = (r + sum of couplings x neighbours) / (lambda + diagonal)
+  auto half_sweep = [&](int color, int ring) {
+    const int W = FTX + 2 * ring, H = FTY + 2 * ring;
+    for (int q = threadIdx.x; q < W * H; q += 256) {
+      const int qy = q / W, qx = q - qy * W;
+      const int j = y0 - ring + qy, i = x0 - ring + qx;
+      if (j < 0 || j >= m || i < 0 || i >= m || ((i + j) & 1) != color) continue;
+      const int ey = qy - ring + EH, ex = qx - ring + EH;
+      T wl, wr, wd, wu;
+      couplings(wx, wy, j, i, m, wl, wr, wd, wu);
+      const T d = wl + wr + wd + wu;
+      const T snr = wl * se[0][ey][ex - 1] + wr * se[0][ey][ex + 1] + wd * se[0][ey - 1][ex] +
+                    wu * se[0][ey + 1][ex];
+      const T sni = wl * se[1][ey][ex - 1] + wr * se[1][ey][ex + 1] + wd * se[1][ey - 1][ex] +
+                    wu * se[1][ey + 1][ex];
+      const int ry = qy - ring + RH, rx = qx - ring + RH;
+      const T ar = sr[0][ry][rx] + snr, ai = sr[1][ry][rx] + sni;
+      const T c = lr + d, dd = li;
+      const T inv = T(1) / (c * c + dd * dd);
+      se[0][ey][ex] = (ar * c + ai * dd) * inv;
+      se[1][ey][ex] = (ai * c - ar * dd) * inv;
+    }
+  };
+  half_sweep(0, 2);
+  __syncthreads();
+  half_sweep(1, 1);
+  __syncthreads();
+  for (int q = threadIdx.x; q < FTX * FTY; q += 256) {
+    const int qy = q / FTX, qx = q % FTX;
+    const int j = y0 + qy, i = x0 + qx;
+    if (j >= m || i >= m) continue;
+    const int ey = qy + EH, ex = qx + EH;
+    const T er = se[0][ey][ex], ei = se[1][ey][ex];
+    T* ep = eo.at(k, j, i);
+    ep[0] = er;
+    ep[eo.pstride] = ei;
+    if (RES) {
+      T wl, wr, wd, wu;
+      couplings(wx, wy, j, i, m, wl, wr, wd, wu);
+      const T d = wl + wr + wd + wu;
+      const T snr = wl * se[0][ey][ex - 1] + wr * se[0][ey][ex + 1] + wd * se[0][ey - 1][ex] +
+                    wu * se[0][ey + 1][ex];
+      const T sni = wl * se[1][ey][ex - 1] + wr * se[1][ey][ex + 1] + wd * se[1][ey - 1][ex] +
+                    wu * se[1][ey + 1][ex];
+      const T c = lr + d, dd = li;
+      const int ry = qy + RH, rx = qx + RH;
+      T* op = res.at(k, j, i);
+      op[0] = sr[0][ry][rx] - (c * er - dd * ei) + snr;
+      op[res.pstride] = sr[1][ry][rx] - (c * ei + dd * er) + sni;
+    }
+  }
+}
+
 // coarse (J, I) = (1/16) [4 f(j,i) + 2 (edge neighbours) + corners], j = 2J+1, i = 2I+1
 template <typename T>
 __global__ void k_restrict(GView<T> f, GView<T> c, int mf, int mc, int nh) {
@@ -144,9 +252,9 @@ __global__ void k_restrict(GView<T> f, GView<T> c, int mf, int mc, int nh) {
   }
 }
 
-// fine += bilinear interpolation of coarse (zero beyond the coarse grid)
+// fo = f + bilinear interpolation of coarse (zero beyond the coarse grid); fo may be f
 template <typename T>
-__global__ void k_prolong_add(GView<T> c, GView<T> f, int mc, int mf, int nh) {
+__global__ void k_prolong_add(GView<T> c, GView<T> f, GView<T> fo, int mc, int mf, int nh) {
   const int64_t total = (int64_t)nh * mf * mf;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -171,9 +279,10 @@ __global__ void k_prolong_add(GView<T> c, GView<T> f, int mc, int mf, int nh) {
         ai += w * cp[c.pstride];
       }
     }
-    T* fp = f.at(k, j, i);
-    fp[0] += ar;
-    fp[f.pstride] += ai;
+    const T* fp = f.at(k, j, i);
+    T* op = fo.at(k, j, i);
+    op[0] = fp[0] + ar;
+    op[fo.pstride] = fp[f.pstride] + ai;
   }
 }
 
@@ -215,6 +324,24 @@ hipError_t mg_rbgs(const MgGrid& e, const MgGrid& r, const void* wx, const void*
 }
 
 template <typename T>
+hipError_t mg_sweep(const MgGrid& e, const MgGrid& eo, const MgGrid& r, const MgGrid* res,
+                    const void* wx, const void* wy, const double* lam, int m, int nh,
+                    int zero_init, hipStream_t s) {
+  if (m < 1 || nh < 1 || nh > 65535) return hipErrorInvalidValue;
+  if (!zero_init && e.p == eo.p) return hipErrorInvalidValue;   // blocks read old values
+  const dim3 grid((m + FTX - 1) / FTX, (m + FTY - 1) / FTY, nh);
+  if (res)
+    hipLaunchKernelGGL((k_rbgs_fused<T, true>), grid, dim3(256), 0, s, view<T>(e), view<T>(eo),
+                       view<T>(r), view<T>(*res), (const T*)wx, (const T*)wy, lam, m,
+                       zero_init);
+  else
+    hipLaunchKernelGGL((k_rbgs_fused<T, false>), grid, dim3(256), 0, s, view<T>(e),
+                       view<T>(eo), view<T>(r), view<T>(eo), (const T*)wx, (const T*)wy, lam,
+                       m, zero_init);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t mg_residual(const MgGrid& e, const MgGrid& r, const MgGrid& res, const void* wx,
                        const void* wy, const double* lam, int m, int nh, hipStream_t s) {
   hipLaunchKernelGGL((k_residual<T>), dim3(mg_grid((int64_t)nh * m * m)), dim3(256), 0, s,
@@ -230,10 +357,10 @@ hipError_t mg_restrict(const MgGrid& f, const MgGrid& c, int mf, int mc, int nh,
 }
 
 template <typename T>
-hipError_t mg_prolong_add(const MgGrid& c, const MgGrid& f, int mc, int mf, int nh,
-                          hipStream_t s) {
+hipError_t mg_prolong_add(const MgGrid& c, const MgGrid& f, const MgGrid& fo, int mc, int mf,
+                          int nh, hipStream_t s) {
   hipLaunchKernelGGL((k_prolong_add<T>), dim3(mg_grid((int64_t)nh * mf * mf)), dim3(256), 0, s,
-                     view<T>(c), view<T>(f), mc, mf, nh);
+                     view<T>(c), view<T>(f), view<T>(fo), mc, mf, nh);
   return hipGetLastError();
 }
 
@@ -247,11 +374,14 @@ hipError_t mg_add(const MgGrid& x, const MgGrid& y, int m, int nh, hipStream_t s
 #define INST(T)                                                                                 \
   template hipError_t mg_rbgs<T>(const MgGrid&, const MgGrid&, const void*, const void*,       \
                                  const double*, int, int, int, int, hipStream_t);              \
+  template hipError_t mg_sweep<T>(const MgGrid&, const MgGrid&, const MgGrid&, const MgGrid*, \
+                                  const void*, const void*, const double*, int, int, int,      \
+                                  hipStream_t);                                                \
   template hipError_t mg_residual<T>(const MgGrid&, const MgGrid&, const MgGrid&, const void*, \
                                      const void*, const double*, int, int, hipStream_t);       \
   template hipError_t mg_restrict<T>(const MgGrid&, const MgGrid&, int, int, int, hipStream_t); \
-  template hipError_t mg_prolong_add<T>(const MgGrid&, const MgGrid&, int, int, int,           \
-                                        hipStream_t);                                          \
+  template hipError_t mg_prolong_add<T>(const MgGrid&, const MgGrid&, const MgGrid&, int, int, \
+                                        int, hipStream_t);                                     \
   template hipError_t mg_add<T>(const MgGrid&, const MgGrid&, int, int, hipStream_t);
 INST(double)
 INST(float)
