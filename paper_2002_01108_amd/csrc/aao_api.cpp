@@ -93,6 +93,8 @@ struct aao_ctx {
     void* E = nullptr;    // levels >= 1: correction, compact [nh][2][m][m]
     void* R = nullptr;    // levels >= 1: right-hand side
     void* Res = nullptr;  // residual on this level (compact)
+    void* X = nullptr;    // iterate after pre-smoothing (compact); the out-of-place
+                          // sweeps alternate between it and E
   };
   std::vector<MgLevel> mg;
   int mg_prec = -1;
@@ -623,12 +625,12 @@ aao_status mg_build(aao_ctx* c) {
       L.R = p;
     }
     const bool last = (m < 3) || (m % 2 == 0);
-    // residual, and the second iterate buffer of the out-of-place sweeps
-    // (prolonged iterate before post-smoothing; ping-pong on the coarsest level)
-    if (!last || m > 1) {
+    if (!last) {
       TRY(dalloc(c, &p, cells * esz));
       L.Res = p;
     }
+    TRY(dalloc(c, &p, cells * esz));
+    L.X = p;
     c->mg.push_back(L);
     if (last) break;
     const int mc = (m - 1) / 2;
@@ -671,69 +673,55 @@ void mg_release(aao_ctx* c) {
     dfree(c, L.E);
     dfree(c, L.R);
     dfree(c, L.Res);
+    dfree(c, L.X);
   }
   c->mg.clear();
   c->mg_prec = -1;
 }
 
+// One V-cycle for B e = R on level `lev` (Section 4's multigrid inner solve).
+// guess: E holds an initial iterate (else the cycle starts from zero).  The
+// pre-smoothing step goes from E into X with the residual fused in; the
+// post-smoothing step reads X plus the prolonged coarse correction and writes
+// E.  The coarsest level alternates its sweeps between E and X.
 template <typename T>
-aao_status vcycle(aao_ctx* c, size_t lev, const MgGrid& R, const MgGrid& E) {
+aao_status vcycle(aao_ctx* c, size_t lev, const MgGrid& R, const MgGrid& E, bool guess = false) {
   const auto& L = c->mg[lev];
   const int nh = c->g.nh, m = L.m;
   hipStream_t s = c->stream;
-  // one red-black smoothing step per launch (with the residual after the
-  // pre-smoothing step fused into it)
+  const MgGrid X = compact_view(L.X, m);
   if (lev + 1 == c->mg.size()) {
-    if (m == 1) {   // one point: the first sweep is exact
-      HIPCHK(c, mg_sweep<T>(E, E, R, nullptr, L.wx, L.wy, c->lam, m, nh, 1, s));
+    if (m == 1 && !guess) {   // one point: the first sweep is exact
+      HIPCHK(c, mg_sweep<T>(E, E, R, nullptr, nullptr, 0, L.wx, L.wy, c->lam, m, nh, 1, s));
       return AAO_OK;
     }
-    // sweeps alternate between the two buffers; an even count ends in E
     static_assert(kCoarseSweeps % 2 == 0, "the last coarse sweep must write E");
-    const MgGrid X = compact_view(L.Res, m);
     for (int i = 0; i < kCoarseSweeps; ++i) {
       const MgGrid& from = (i % 2 == 0) ? E : X;
       const MgGrid& to = (i % 2 == 0) ? X : E;
-      HIPCHK(c, mg_sweep<T>(from, to, R, nullptr, L.wx, L.wy, c->lam, m, nh, i == 0, s));
+      HIPCHK(c, mg_sweep<T>(from, to, R, nullptr, nullptr, 0, L.wx, L.wy, c->lam, m, nh,
+                            i == 0 && !guess, s));
     }
     return AAO_OK;
   }
   const MgGrid res = compact_view(L.Res, m);
-  HIPCHK(c, mg_sweep<T>(E, E, R, &res, L.wx, L.wy, c->lam, m, nh, 1, s));
+  HIPCHK(c, mg_sweep<T>(E, X, R, &res, nullptr, 0, L.wx, L.wy, c->lam, m, nh, !guess, s));
   const auto& C = c->mg[lev + 1];
   const MgGrid Rc = compact_view(C.R, C.m), Ec = compact_view(C.E, C.m);
   HIPCHK(c, mg_restrict<T>(res, Rc, m, C.m, nh, s));
   TRY(vcycle<T>(c, lev + 1, Rc, Ec));
-  // the residual is no longer needed: its buffer takes E + P e_c, and the
-  // post-smoothing step writes back to E
-  HIPCHK(c, mg_prolong_add<T>(Ec, E, res, C.m, m, nh, s));
-  HIPCHK(c, mg_sweep<T>(res, E, R, nullptr, L.wx, L.wy, c->lam, m, nh, 0, s));
+  HIPCHK(c, mg_sweep<T>(X, E, R, nullptr, &Ec, C.m, L.wx, L.wy, c->lam, m, nh, 0, s));
   return AAO_OK;
 }
 
-// e = MG(r) with c->inner_cycles V-cycles in correction form: e += V(r - B e).
+// e = MG(r) with c->inner_cycles V-cycles, each after the first starting from
+// the previous iterate (the same iterates as the correction form
+// e += V(r - B e) from zero: a smoothing step is affine in its start).
 template <typename T>
 aao_status mg_solve_t(aao_ctx* c, void* r, void* e) {
   const MgGrid R = spec_view(c, r), E = spec_view(c, e);
   TRY(vcycle<T>(c, 0, R, E));
-  if (c->inner_cycles > 1) {
-    if (!c->specC) {
-      char* p;
-      TRY(dalloc(c, &p, c->spec_bytes));
-      HIPCHK(c, hipMemset(p, 0, c->spec_bytes));
-      c->specC = p;
-      TRY(dalloc(c, &p, c->spec_bytes));
-      HIPCHK(c, hipMemset(p, 0, c->spec_bytes));
-      c->specD = p;
-    }
-    const MgGrid Rs = spec_view(c, c->specC), D = spec_view(c, c->specD);
-    const auto& L0 = c->mg[0];
-    for (int cyc = 1; cyc < c->inner_cycles; ++cyc) {
-      HIPCHK(c, mg_residual<T>(E, R, Rs, L0.wx, L0.wy, c->lam, L0.m, c->g.nh, c->stream));
-      TRY(vcycle<T>(c, 0, Rs, D));
-      HIPCHK(c, mg_add<T>(E, D, L0.m, c->g.nh, c->stream));
-    }
-  }
+  for (int cyc = 1; cyc < c->inner_cycles; ++cyc) TRY(vcycle<T>(c, 0, R, E, true));
   return AAO_OK;
 }
 

@@ -6,8 +6,9 @@
 //
 // All n/2+1 blocks are processed by every launch.  Smoother: red-black
 // Gauss-Seidel (red: i1 + i2 even), one red and one black half sweep per
-// launch (tiled, see k_rbgs_fused); the other kernels take one thread per
-// grid point and block.
+// launch (tiled, see k_rbgs_fused), which also adds the prolonged coarse
+// correction before post-smoothing; restriction and the stand-alone residual
+// and half sweep take one thread per grid point and block.
 // Restriction: full weighting (transpose of bilinear interpolation / 4).
 // Prolongation: bilinear.  Coarse operators are rediscretised on the host:
 // face weights w = tau/h_l^2 * a with harmonic face averages (flux form), or
@@ -31,6 +32,32 @@ template <typename T> struct GView {
     return p + k * bstride + (int64_t)j * pitch + i;
   }
 };
+
+// bilinear interpolation of the coarse grid c at fine node (j, i): coarse node
+// I sits on fine node 2I+1; zero beyond the coarse grid
+template <typename T>
+__device__ __forceinline__ void interp(const GView<T>& c, int k, int j, int i, int mc, T& ar,
+                                       T& ai) {
+  int Ix[2], Jy[2];
+  T wxv[2], wyv[2];
+  int nx, ny;
+  if (i & 1) { Ix[0] = (i - 1) >> 1; wxv[0] = T(1); nx = 1; }
+  else { Ix[0] = (i >> 1) - 1; Ix[1] = i >> 1; wxv[0] = wxv[1] = T(0.5); nx = 2; }
+  if (j & 1) { Jy[0] = (j - 1) >> 1; wyv[0] = T(1); ny = 1; }
+  else { Jy[0] = (j >> 1) - 1; Jy[1] = j >> 1; wyv[0] = wyv[1] = T(0.5); ny = 2; }
+  ar = T(0);
+  ai = T(0);
+  for (int b = 0; b < ny; ++b) {
+    if (Jy[b] < 0 || Jy[b] >= mc) continue;
+    for (int a = 0; a < nx; ++a) {
+      if (Ix[a] < 0 || Ix[a] >= mc) continue;
+      const T w = wxv[a] * wyv[b];
+      const T* cp = c.at(k, Jy[b], Ix[a]);
+      ar += w * cp[0];
+      ai += w * cp[c.pstride];
+    }
+  }
+}
 
 // couplings of node (j, i) to its west, east, south and north neighbours
 template <typename T>
@@ -137,11 +164,14 @@ __global__ void k_residual(GView<T> e, GView<T> r, GView<T> res, const T* __rest
 // Outside the grid e and r are zero (Dirichlet).  The old iterate is read from
 // e and the new one written to eo: blocks read their neighbours' old values,
 // so eo may equal e only when the old iterate is zero (zero_init, e unread).
+// With mc > 0 the old iterate is e plus the bilinear interpolation of the
+// coarse-grid correction ec (the prolongation of the V-cycle, added while the
+// tile is staged).
 constexpr int FTX = 64, FTY = 16;
 
 template <typename T, bool RES>
 __global__ __launch_bounds__(256) void k_rbgs_fused(GView<T> e, GView<T> eo, GView<T> r,
-                                                    GView<T> res,
+                                                    GView<T> res, GView<T> ec, int mc,
                                                     const T* __restrict__ wx,
                                                     const T* __restrict__ wy,
                                                     const double* __restrict__ lam, int m,
@@ -161,6 +191,12 @@ __global__ __launch_bounds__(256) void k_rbgs_fused(GView<T> e, GView<T> eo, GVi
       const T* p = e.at(k, j, i);
       vr = p[0];
       vi = p[e.pstride];
+      if (mc > 0) {
+        T pr, pi;
+        interp(ec, k, j, i, mc, pr, pi);
+        vr = vr + pr;
+        vi = vi + pi;
+      }
     }
     se[0][ly][lx] = vr;
     se[1][ly][lx] = vi;
@@ -252,56 +288,6 @@ __global__ void k_restrict(GView<T> f, GView<T> c, int mf, int mc, int nh) {
   }
 }
 
-// fo = f + bilinear interpolation of coarse (zero beyond the coarse grid); fo may be f
-template <typename T>
-__global__ void k_prolong_add(GView<T> c, GView<T> f, GView<T> fo, int mc, int mf, int nh) {
-  const int64_t total = (int64_t)nh * mf * mf;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int k = (int)(idx / ((int64_t)mf * mf));
-    const int rem = (int)(idx - (int64_t)k * mf * mf);
-    const int j = rem / mf, i = rem - j * mf;
-    int Ix[2], Jy[2];
-    T wxv[2], wyv[2];
-    int nx, ny;
-    if (i & 1) { Ix[0] = (i - 1) >> 1; wxv[0] = T(1); nx = 1; }
-    else { Ix[0] = (i >> 1) - 1; Ix[1] = i >> 1; wxv[0] = wxv[1] = T(0.5); nx = 2; }
-    if (j & 1) { Jy[0] = (j - 1) >> 1; wyv[0] = T(1); ny = 1; }
-    else { Jy[0] = (j >> 1) - 1; Jy[1] = j >> 1; wyv[0] = wyv[1] = T(0.5); ny = 2; }
-    T ar = T(0), ai = T(0);
-    for (int b = 0; b < ny; ++b) {
-      if (Jy[b] < 0 || Jy[b] >= mc) continue;
-      for (int a = 0; a < nx; ++a) {
-        if (Ix[a] < 0 || Ix[a] >= mc) continue;
-        const T w = wxv[a] * wyv[b];
-        const T* cp = c.at(k, Jy[b], Ix[a]);
-        ar += w * cp[0];
-        ai += w * cp[c.pstride];
-      }
-    }
-    const T* fp = f.at(k, j, i);
-    T* op = fo.at(k, j, i);
-    op[0] = fp[0] + ar;
-    op[fo.pstride] = fp[f.pstride] + ai;
-  }
-}
-
-// x += y on the valid region
-template <typename T>
-__global__ void k_add(GView<T> x, GView<T> y, int m, int nh) {
-  const int64_t total = (int64_t)nh * m * m;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int k = (int)(idx / ((int64_t)m * m));
-    const int rem = (int)(idx - (int64_t)k * m * m);
-    const int j = rem / m, i = rem - j * m;
-    T* xp = x.at(k, j, i);
-    const T* yp = y.at(k, j, i);
-    xp[0] += yp[0];
-    xp[x.pstride] += yp[y.pstride];
-  }
-}
-
 unsigned mg_grid(int64_t total) {
   int64_t b = (total + 255) / 256;
   if (b > 65536) b = 65536;
@@ -325,19 +311,21 @@ hipError_t mg_rbgs(const MgGrid& e, const MgGrid& r, const void* wx, const void*
 
 template <typename T>
 hipError_t mg_sweep(const MgGrid& e, const MgGrid& eo, const MgGrid& r, const MgGrid* res,
-                    const void* wx, const void* wy, const double* lam, int m, int nh,
-                    int zero_init, hipStream_t s) {
+                    const MgGrid* ec, int mc, const void* wx, const void* wy, const double* lam,
+                    int m, int nh, int zero_init, hipStream_t s) {
   if (m < 1 || nh < 1 || nh > 65535) return hipErrorInvalidValue;
   if (!zero_init && e.p == eo.p) return hipErrorInvalidValue;   // blocks read old values
+  if ((ec != nullptr) != (mc > 0) || (ec && 2 * mc + 1 > m)) return hipErrorInvalidValue;
   const dim3 grid((m + FTX - 1) / FTX, (m + FTY - 1) / FTY, nh);
+  const GView<T> vc = ec ? view<T>(*ec) : view<T>(e);
   if (res)
     hipLaunchKernelGGL((k_rbgs_fused<T, true>), grid, dim3(256), 0, s, view<T>(e), view<T>(eo),
-                       view<T>(r), view<T>(*res), (const T*)wx, (const T*)wy, lam, m,
-                       zero_init);
+                       view<T>(r), view<T>(*res), vc, ec ? mc : 0, (const T*)wx, (const T*)wy,
+                       lam, m, zero_init);
   else
     hipLaunchKernelGGL((k_rbgs_fused<T, false>), grid, dim3(256), 0, s, view<T>(e),
-                       view<T>(eo), view<T>(r), view<T>(eo), (const T*)wx, (const T*)wy, lam,
-                       m, zero_init);
+                       view<T>(eo), view<T>(r), view<T>(eo), vc, ec ? mc : 0, (const T*)wx,
+                       (const T*)wy, lam, m, zero_init);
   return hipGetLastError();
 }
 
@@ -356,33 +344,16 @@ hipError_t mg_restrict(const MgGrid& f, const MgGrid& c, int mf, int mc, int nh,
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t mg_prolong_add(const MgGrid& c, const MgGrid& f, const MgGrid& fo, int mc, int mf,
-                          int nh, hipStream_t s) {
-  hipLaunchKernelGGL((k_prolong_add<T>), dim3(mg_grid((int64_t)nh * mf * mf)), dim3(256), 0, s,
-                     view<T>(c), view<T>(f), view<T>(fo), mc, mf, nh);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t mg_add(const MgGrid& x, const MgGrid& y, int m, int nh, hipStream_t s) {
-  hipLaunchKernelGGL((k_add<T>), dim3(mg_grid((int64_t)nh * m * m)), dim3(256), 0, s, view<T>(x),
-                     view<T>(y), m, nh);
-  return hipGetLastError();
-}
-
 #define INST(T)                                                                                 \
   template hipError_t mg_rbgs<T>(const MgGrid&, const MgGrid&, const void*, const void*,       \
                                  const double*, int, int, int, int, hipStream_t);              \
   template hipError_t mg_sweep<T>(const MgGrid&, const MgGrid&, const MgGrid&, const MgGrid*, \
-                                  const void*, const void*, const double*, int, int, int,      \
-                                  hipStream_t);                                                \
+                                  const MgGrid*, int, const void*, const void*, const double*, \
+                                  int, int, int, hipStream_t);                                 \
   template hipError_t mg_residual<T>(const MgGrid&, const MgGrid&, const MgGrid&, const void*, \
                                      const void*, const double*, int, int, hipStream_t);       \
-  template hipError_t mg_restrict<T>(const MgGrid&, const MgGrid&, int, int, int, hipStream_t); \
-  template hipError_t mg_prolong_add<T>(const MgGrid&, const MgGrid&, const MgGrid&, int, int, \
-                                        int, hipStream_t);                                     \
-  template hipError_t mg_add<T>(const MgGrid&, const MgGrid&, int, int, hipStream_t);
+  template hipError_t mg_restrict<T>(const MgGrid&, const MgGrid&, int, int, int, hipStream_t);
+
 INST(double)
 INST(float)
 #undef INST
