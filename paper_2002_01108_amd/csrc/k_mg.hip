@@ -167,7 +167,7 @@ __global__ void k_residual(GView<T> e, GView<T> r, GView<T> res, const T* __rest
 // With mc > 0 the old iterate is e plus the bilinear interpolation of the
 // coarse-grid correction ec (the prolongation of the V-cycle, added while the
 // tile is staged).
-constexpr int FTX = 64, FTY = 16;
+constexpr int FTX = 32, FTY = 16;   // tile shape measured fastest of 16..128 x 8..32
 
 template <typename T, bool RES>
 __global__ __launch_bounds__(256) void k_rbgs_fused(GView<T> e, GView<T> eo, GView<T> r,
