@@ -214,6 +214,13 @@ def copy_calibration():
                       "copies": 5}), flush=True)
 
 
+def record(checks, rec, spec, u):
+    """Keep a host copy of a GPU solution for the cpu_baseline leg's oracle
+    check (nothing when the checks are off: no device-to-host copy)."""
+    if checks is not None:
+        checks.append((rec, spec, u.cpu().numpy()))
+
+
 def cpu_baseline_leg(w, f, u0, sample_steps, checks, timed=True):
     """The one place this benchmark runs the CPU oracle.
 
@@ -282,7 +289,7 @@ def bdf2_leg(w, fd, u0d, tol, restart, steps, checks):
     t, info, _, u, _ = time_solver(s, fd, u0d, tol, restart, steps, 1, [])
     rec = {"value": w.dof / t, "ms_per_step": t * 1e3, "gmres_iters": info["iters"],
            "rel_res": info["final_res"], "eps": w.epsilon}
-    checks.append((rec, ("heat_bdf2", w.name), u.cpu().numpy()))
+    record(checks, rec, ("heat_bdf2", w.name), u)
     torch.cuda.synchronize()
     return rec
 
@@ -398,7 +405,7 @@ def cd_leg(steps, checks):
             it, cpu_s, res = TABLE3_PRINTED[name[:-5]]
             rec["paper"] = {"iters": it, "cpu_s": cpu_s, "rel_res": res}
         if name == "bec_fgmres":
-            checks.append((rec, ("cd", w.name), u.cpu().numpy()))
+            record(checks, rec, ("cd", w.name), u)
         print(f"[cd] {name}: {info['iters']} iterations, {dt * 1e3:.2f} ms, "
               f"RES {info['final_res']:.3e}", file=sys.stderr, flush=True)
         out[name] = rec
@@ -449,7 +456,7 @@ def learned_leg(tol, steps, checks, train_fields=4, train_steps=1500, batch=8):
         t, info, _, u, _ = time_solver(s, fd, u0d, tol, 50, steps, 1, [])
         rec = {"value": w.dof / t, "ms_per_step": t * 1e3, "gmres_iters": info["iters"],
                "rel_res": info["final_res"]}
-        checks.append((rec, ("heat_faces", w.name), u.cpu().numpy()))
+        record(checks, rec, ("heat_faces", w.name), u)
         out[inner] = rec
     return out
 
@@ -538,8 +545,9 @@ def main():
     out["kernels"]["apply_L"]["note"] = "standalone aao_apply_A, 20 calls on the workload's rhs"
     s.profile(None)
 
-    checks = []      # (record, oracle spec, GPU solution) for the cpu_baseline leg
-    checks.append((out, ("heat", w.name), u.cpu().numpy()))
+    # (record, oracle spec, GPU solution) for the cpu_baseline leg
+    checks = None if args.no_oracle_check else []
+    record(checks, out, ("heat", w.name), u)
 
     variants = {}
     for vp in [v for v in args.variants.split(",") if v and v != prec]:
@@ -552,7 +560,7 @@ def main():
                                        1, [])
         rec = {"value": dof / tv, "ms_per_step": tv * 1e3, "gmres_iters": iv["iters"],
                "rel_res": iv["final_res"]}
-        checks.append((rec, ("heat", w.name), uv.cpu().numpy()))
+        record(checks, rec, ("heat", w.name), uv)
         variants[vp] = rec
     if variants:
         out["variants"] = variants
@@ -567,8 +575,7 @@ def main():
     if not args.no_cd:
         out["cd"] = cd_leg(max(1, args.steps // 2), checks)
 
-    cpu = cpu_baseline_leg(w, f, u0, args.cpu_sample_steps,
-                           [] if args.no_oracle_check else checks,
+    cpu = cpu_baseline_leg(w, f, u0, args.cpu_sample_steps, checks or [],
                            timed=not args.no_cpu_baseline)
     if cpu is not None:
         out["cpu_baseline"] = cpu

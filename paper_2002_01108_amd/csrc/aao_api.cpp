@@ -373,6 +373,12 @@ FoldArgs fold_args(const aao_ctx* c, int d, bool real_ends) {
 
 // The fused forward-divide-inverse kernel applies along the last axis when it
 // has the two-level fold tables and a padded length of 128 or 256 (FP64).
+// x-axis products without a divide by whole rows (k_dst_fold2_rows)
+bool use_rows(const aao_ctx* c) {
+  const Geometry& g = c->g;
+  return g.dim >= 2 && c->prec == AAO_FP64 && c->FqT64[0] && (g.P1 == 128 || g.P1 == 256);
+}
+
 bool use_fused_last(const aao_ctx* c) {
   const int d = c->g.dim - 1;
   const int Ps[3] = {c->g.P1, c->g.P2, c->g.P3};
@@ -404,8 +410,7 @@ hipError_t fold_product(aao_ctx* c, int d, const void* in, void* out, double* co
   // matrix-core rate) the extra loads and barrier of its K loop cost more
   // than it saves, so FP32 keeps the one-level fold
   // along x without a divide (P1 = 128 or 256): whole rows per block
-  if (d == 0 && !divtm && g.dim >= 2 && c->prec == AAO_FP64 && c->FqT64[0] &&
-      (g.P1 == 128 || g.P1 == 256)) {
+  if (d == 0 && !divtm && use_rows(c)) {
     FoldArgs fr = f;
     fr.ndt = g.P2 * g.P3 / 16;
     return launch_dst_fold2_rows((const double*)in, (double*)out, c->FqT64[0], fr, c->stream);
@@ -499,6 +504,16 @@ aao_status dst_solve(aao_ctx* c, void** cur, void** other, bool mean, bool real_
   if (use_fold(c)) {
     double* const* tm = mean ? c->tmu_mean : c->tmu;
     const bool fuse = use_fused_last(c);
+    if (fuse && dim == 2 && use_rows(c)) {
+      // rows along x, the fused forward-divide-inverse along y, rows along x:
+      // each block reads whole rows (or whole columns) of its tile before it
+      // writes them and no two blocks share one, so the three launches work in
+      // place and the DST passes touch one spectrum buffer
+      HIPCHK(c, fold_product(c, 0, *cur, *cur, nullptr, real_ends));
+      HIPCHK(c, fused_last(c, *cur, *cur, tm, real_ends));
+      HIPCHK(c, fold_product(c, 0, *cur, *cur, nullptr, real_ends));
+      return AAO_OK;
+    }
     for (int d = 0; d < dim; ++d) {
       if (fuse && d == dim - 1) break;
       HIPCHK(c, fold_product(c, d, *cur, *other, d == dim - 1 ? tm : nullptr, real_ends));

@@ -623,7 +623,7 @@ constexpr int FCF = 16;
 
 template <int HQ>
 __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(2))) void k_dst_fold2_fused(
-    const double* __restrict__ in, double* __restrict__ out, const double* __restrict__ tt,
+    const double* in, double* out, const double* __restrict__ tt,
     FoldArgs f, const double* __restrict__ lam, const double* __restrict__ tmu1,
     const double* __restrict__ tmu2, const double* __restrict__ tmu3) {
   using V = d4;
@@ -843,7 +843,7 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
 // of a half-wave fall on distinct banks; output rows P + 1 apart likewise.
 template <int HQ>
 __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(2))) void k_dst_fold2_rows(
-    const double* __restrict__ in, double* __restrict__ out, const double* __restrict__ tt,
+    const double* in, double* out, const double* __restrict__ tt,
     FoldArgs f, int ntiles) {
   using V = d4;
   constexpr int P = 4 * HQ, NT = 64 * (HQ / 16), NV = 16;
