@@ -7,8 +7,8 @@ For a variable coefficient the blocks B_k = lambda_k I + tau K_a of Step 2
 paper solves each one approximately with one V-cycle of geometric multigrid
 with one pre- and one post-smoothing step, linear interpolation and its
 transpose (Section 4, closing paragraphs; Section 5, Example 2).  This module
-writes that V-cycle out plainly for 2D grids, in the readings listed in
-DESIGN.md:
+writes that V-cycle out plainly for 2D grids, with these readings of what
+the paper leaves open:
 
 * smoother: red-black Gauss-Seidel (red = (i1 + i2) even), one red and one
   black half sweep per smoothing step (the paper's ILU smoother is sequential);

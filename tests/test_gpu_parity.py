@@ -1,6 +1,6 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle.
 
-Tolerances (relative 2-norm unless stated), derived in the design doc:
+Tolerances (relative 2-norm unless stated), derived from the arithmetic:
   FP64 steps 1/3 and L v      1e-12   (u = 1.1e-16, log2 n passes, eps^{-1} <= 32)
   FP64 step 2 / P^{-1}        1e-11   (dense orthogonal transforms, K <= 1024 terms)
   FP64 solve                  1e-10   (iterate at equal k, and vs sequential BE)
