@@ -92,7 +92,6 @@ struct aao_ctx {
     void* wy = nullptr;   // [m+1][m]; null with coupling planes
     void* E = nullptr;    // levels >= 1: correction, compact [nh][2][m][m]
     void* R = nullptr;    // levels >= 1: right-hand side
-    void* Res = nullptr;  // residual on this level (compact)
     void* X = nullptr;    // iterate after pre-smoothing (compact); the out-of-place
                           // sweeps alternate between it and E
   };
@@ -640,10 +639,6 @@ aao_status mg_build(aao_ctx* c) {
       L.R = p;
     }
     const bool last = (m < 3) || (m % 2 == 0);
-    if (!last) {
-      TRY(dalloc(c, &p, cells * esz));
-      L.Res = p;
-    }
     TRY(dalloc(c, &p, cells * esz));
     L.X = p;
     c->mg.push_back(L);
@@ -687,7 +682,6 @@ void mg_release(aao_ctx* c) {
     dfree(c, L.wy);
     dfree(c, L.E);
     dfree(c, L.R);
-    dfree(c, L.Res);
     dfree(c, L.X);
   }
   c->mg.clear();
@@ -696,9 +690,10 @@ void mg_release(aao_ctx* c) {
 
 // One V-cycle for B e = R on level `lev` (Section 4's multigrid inner solve).
 // guess: E holds an initial iterate (else the cycle starts from zero).  The
-// pre-smoothing step goes from E into X with the residual fused in; the
-// post-smoothing step reads X plus the prolonged coarse correction and writes
-// E.  The coarsest level alternates its sweeps between E and X.
+// pre-smoothing step goes from E into X and writes the restricted residual as
+// the next level's right-hand side; the post-smoothing step reads X plus the
+// prolonged coarse correction and writes E.  The coarsest level alternates its
+// sweeps between E and X.
 template <typename T>
 aao_status vcycle(aao_ctx* c, size_t lev, const MgGrid& R, const MgGrid& E, bool guess = false) {
   const auto& L = c->mg[lev];
@@ -707,25 +702,23 @@ aao_status vcycle(aao_ctx* c, size_t lev, const MgGrid& R, const MgGrid& E, bool
   const MgGrid X = compact_view(L.X, m);
   if (lev + 1 == c->mg.size()) {
     if (m == 1 && !guess) {   // one point: the first sweep is exact
-      HIPCHK(c, mg_sweep<T>(E, E, R, nullptr, nullptr, 0, L.wx, L.wy, c->lam, m, nh, 1, s));
+      HIPCHK(c, mg_sweep<T>(E, E, R, nullptr, 0, nullptr, 0, L.wx, L.wy, c->lam, m, nh, 1, s));
       return AAO_OK;
     }
     static_assert(kCoarseSweeps % 2 == 0, "the last coarse sweep must write E");
     for (int i = 0; i < kCoarseSweeps; ++i) {
       const MgGrid& from = (i % 2 == 0) ? E : X;
       const MgGrid& to = (i % 2 == 0) ? X : E;
-      HIPCHK(c, mg_sweep<T>(from, to, R, nullptr, nullptr, 0, L.wx, L.wy, c->lam, m, nh,
+      HIPCHK(c, mg_sweep<T>(from, to, R, nullptr, 0, nullptr, 0, L.wx, L.wy, c->lam, m, nh,
                             i == 0 && !guess, s));
     }
     return AAO_OK;
   }
-  const MgGrid res = compact_view(L.Res, m);
-  HIPCHK(c, mg_sweep<T>(E, X, R, &res, nullptr, 0, L.wx, L.wy, c->lam, m, nh, !guess, s));
   const auto& C = c->mg[lev + 1];
   const MgGrid Rc = compact_view(C.R, C.m), Ec = compact_view(C.E, C.m);
-  HIPCHK(c, mg_restrict<T>(res, Rc, m, C.m, nh, s));
+  HIPCHK(c, mg_sweep<T>(E, X, R, &Rc, C.m, nullptr, 0, L.wx, L.wy, c->lam, m, nh, !guess, s));
   TRY(vcycle<T>(c, lev + 1, Rc, Ec));
-  HIPCHK(c, mg_sweep<T>(X, E, R, nullptr, &Ec, C.m, L.wx, L.wy, c->lam, m, nh, 0, s));
+  HIPCHK(c, mg_sweep<T>(X, E, R, nullptr, 0, &Ec, C.m, L.wx, L.wy, c->lam, m, nh, 0, s));
   return AAO_OK;
 }
 

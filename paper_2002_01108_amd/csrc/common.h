@@ -263,17 +263,16 @@ hipError_t mg_rbgs(const MgGrid& e, const MgGrid& r, const void* wx, const void*
 // One smoothing step (red then black half sweep) in one launch from the old
 // iterate e into eo (eo may be e only with zero_init: the old iterate is then
 // zero and not read); with ec (coarse grid of mc points, 2 mc + 1 <= m) the
-// old iterate is e + the bilinear interpolation of ec; with res, also
-// res = r - B eo (res aliases none of them).
+// old iterate is e + the bilinear interpolation of ec; with rc (coarse grid of
+// mcr points, 2 mcr + 1 <= m), also rc = full-weighting restriction of
+// r - B eo (rc aliases none of them).
 template <typename T>
-hipError_t mg_sweep(const MgGrid& e, const MgGrid& eo, const MgGrid& r, const MgGrid* res,
-                    const MgGrid* ec, int mc, const void* wx, const void* wy, const double* lam,
-                    int m, int nh, int zero_init, hipStream_t s);
+hipError_t mg_sweep(const MgGrid& e, const MgGrid& eo, const MgGrid& r, const MgGrid* rc,
+                    int mcr, const MgGrid* ec, int mc, const void* wx, const void* wy,
+                    const double* lam, int m, int nh, int zero_init, hipStream_t s);
 template <typename T>
 hipError_t mg_residual(const MgGrid& e, const MgGrid& r, const MgGrid& res, const void* wx,
                        const void* wy, const double* lam, int m, int nh, hipStream_t s);
-template <typename T>
-hipError_t mg_restrict(const MgGrid& f, const MgGrid& c, int mf, int mc, int nh, hipStream_t s);
 
 // ---------------------------------------------------------------- learned correction
 // Parameter vector: W1[C][3][3][3] G1[C][4] H1[C][4] W2[C][C][3][3] G2[C][4] H2[C][4]

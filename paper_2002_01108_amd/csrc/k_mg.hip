@@ -6,9 +6,10 @@
 //
 // All n/2+1 blocks are processed by every launch.  Smoother: red-black
 // Gauss-Seidel (red: i1 + i2 even), one red and one black half sweep per
-// launch (tiled, see k_rbgs_fused), which also adds the prolonged coarse
-// correction before post-smoothing; restriction and the stand-alone residual
-// and half sweep take one thread per grid point and block.
+// launch (tiled, see k_rbgs_fused), which also restricts the residual after
+// pre-smoothing and adds the prolonged coarse correction before
+// post-smoothing; the stand-alone residual and half sweep (learned correction)
+// take one thread per grid point and block.
 // Restriction: full weighting (transpose of bilinear interpolation / 4).
 // Prolongation: bilinear.  Coarse operators are rediscretised on the host:
 // face weights w = tau/h_l^2 * a with harmonic face averages (flux form), or
@@ -154,32 +155,37 @@ __global__ void k_residual(GView<T> e, GView<T> r, GView<T> res, const T* __rest
 }
 
 // One smoothing step (a red then a black half sweep) in one pass over the
-// data, optionally followed by the residual r - B e on the same points.  A
-// block owns a TX x TY tile of one frequency block: e (old values, halo 3) and
-// r (halo 2) are staged in LDS, the red points are updated on the tile plus a
-// ring of two, the black points on the tile plus one (their red neighbours are
-// then all new), and the residual on the tile (whose neighbours are then all
-// new).  The halo rings repeat the neighbouring tiles' updates with the same
-// inputs, so every point gets the value the two separate half sweeps give.
-// Outside the grid e and r are zero (Dirichlet).  The old iterate is read from
-// e and the new one written to eo: blocks read their neighbours' old values,
-// so eo may equal e only when the old iterate is zero (zero_init, e unread).
-// With mc > 0 the old iterate is e plus the bilinear interpolation of the
-// coarse-grid correction ec (the prolongation of the V-cycle, added while the
-// tile is staged).
+// data.  A block owns a FTX x FTY tile of one frequency block: e (old values)
+// and r are staged in LDS with halos, the red points are updated on the tile
+// plus a ring of EH - 1, the black points on the tile plus EH - 2 (their red
+// neighbours are then all new).  The halo rings repeat the neighbouring tiles'
+// updates with the same inputs, so every point gets the value the two separate
+// half sweeps give.  Outside the grid e and r are zero (Dirichlet).  The old
+// iterate is read from e and the new one written to eo: blocks read their
+// neighbours' old values, so eo may equal e only when the old iterate is zero
+// (zero_init, e unread).  With mc > 0 the old iterate is e plus the bilinear
+// interpolation of the coarse-grid correction ec (the prolongation of the
+// V-cycle, added while the tile is staged).
+// RST (pre-smoothing): the halos grow by one, the residual r - B e is formed on
+// the tile plus one ring in LDS, and its full-weighting restriction is written
+// for the coarse points centred in the tile (fine node 2J+1, 2I+1; the tile
+// origin is even, so each coarse point has exactly one owner).
 constexpr int FTX = 32, FTY = 16;   // tile shape measured fastest of 16..128 x 8..32
+static_assert(FTX % 2 == 0 && FTY % 2 == 0, "even tile origins");
 
-template <typename T, bool RES>
+template <typename T, bool RST>
 __global__ __launch_bounds__(256) void k_rbgs_fused(GView<T> e, GView<T> eo, GView<T> r,
-                                                    GView<T> res, GView<T> ec, int mc,
+                                                    GView<T> rc, int mcr, GView<T> ec, int mc,
                                                     const T* __restrict__ wx,
                                                     const T* __restrict__ wy,
                                                     const double* __restrict__ lam, int m,
                                                     int zero_init) {
-  constexpr int EH = 3, EX = FTX + 2 * EH, EY = FTY + 2 * EH;   // e tile with its halo
-  constexpr int RH = 2, RX = FTX + 2 * RH, RY = FTY + 2 * RH;   // r tile with its halo
+  constexpr int EH = RST ? 4 : 3, EX = FTX + 2 * EH, EY = FTY + 2 * EH;   // e tile + halo
+  constexpr int RH = EH - 1, RX = FTX + 2 * RH, RY = FTY + 2 * RH;        // r tile + halo
+  constexpr int QX = RST ? FTX + 2 : 1, QY = RST ? FTY + 2 : 1;           // residual, ring 1
   __shared__ T se[2][EY][EX];
   __shared__ T sr[2][RY][RX];
+  __shared__ T sq[2][QY][QX];
   const int k = blockIdx.z;
   const int x0 = blockIdx.x * FTX, y0 = blockIdx.y * FTY;
   const T lr = (T)lam[2 * k], li = (T)lam[2 * k + 1];
@@ -214,6 +220,16 @@ __global__ __launch_bounds__(256) void k_rbgs_fused(GView<T> e, GView<T> eo, GVi
     sr[1][ly][lx] = vi;
   }
   __syncthreads();
+  // sum of couplings x neighbours and the diagonal at e-tile position (ey, ex)
+  auto nsum = [&](int j, int i, int ey, int ex, T& snr, T& sni, T& d) {
+    T wl, wr, wd, wu;
+    couplings(wx, wy, j, i, m, wl, wr, wd, wu);
+    d = wl + wr + wd + wu;
+    snr = wl * se[0][ey][ex - 1] + wr * se[0][ey][ex + 1] + wd * se[0][ey - 1][ex] +
+          wu * se[0][ey + 1][ex];
+    sni = wl * se[1][ey][ex - 1] + wr * se[1][ey][ex + 1] + wd * se[1][ey - 1][ex] +
+          wu * se[1][ey + 1][ex];
+  };
   // Gauss-Seidel update of the points of one colour in the tile plus a ring
   // of `ring`: e = (r + sum of couplings x neighbours) / (lambda + diagonal)
   auto half_sweep = [&](int color, int ring) {
@@ -223,13 +239,8 @@ __global__ __launch_bounds__(256) void k_rbgs_fused(GView<T> e, GView<T> eo, GVi
       const int j = y0 - ring + qy, i = x0 - ring + qx;
       if (j < 0 || j >= m || i < 0 || i >= m || ((i + j) & 1) != color) continue;
       const int ey = qy - ring + EH, ex = qx - ring + EH;
-      T wl, wr, wd, wu;
-      couplings(wx, wy, j, i, m, wl, wr, wd, wu);
-      const T d = wl + wr + wd + wu;
-      const T snr = wl * se[0][ey][ex - 1] + wr * se[0][ey][ex + 1] + wd * se[0][ey - 1][ex] +
-                    wu * se[0][ey + 1][ex];
-      const T sni = wl * se[1][ey][ex - 1] + wr * se[1][ey][ex + 1] + wd * se[1][ey - 1][ex] +
-                    wu * se[1][ey + 1][ex];
+      T snr, sni, d;
+      nsum(j, i, ey, ex, snr, sni, d);
       const int ry = qy - ring + RH, rx = qx - ring + RH;
       const T ar = sr[0][ry][rx] + snr, ai = sr[1][ry][rx] + sni;
       const T c = lr + d, dd = li;
@@ -238,52 +249,53 @@ __global__ __launch_bounds__(256) void k_rbgs_fused(GView<T> e, GView<T> eo, GVi
       se[1][ey][ex] = (ai * c - ar * dd) * inv;
     }
   };
-  half_sweep(0, 2);
+  half_sweep(0, EH - 1);
   __syncthreads();
-  half_sweep(1, 1);
+  half_sweep(1, EH - 2);
   __syncthreads();
+  if (RST) {   // residual r - B e on the tile plus one ring (zero outside the grid)
+    for (int q = threadIdx.x; q < QX * QY; q += 256) {
+      const int qy = q / QX, qx = q % QX;
+      const int j = y0 - 1 + qy, i = x0 - 1 + qx;
+      T vr = T(0), vi = T(0);
+      if (j >= 0 && j < m && i >= 0 && i < m) {
+        const int ey = qy - 1 + EH, ex = qx - 1 + EH;
+        T snr, sni, d;
+        nsum(j, i, ey, ex, snr, sni, d);
+        const T er = se[0][ey][ex], ei = se[1][ey][ex];
+        const T c = lr + d, dd = li;
+        vr = sr[0][qy - 1 + RH][qx - 1 + RH] - (c * er - dd * ei) + snr;
+        vi = sr[1][qy - 1 + RH][qx - 1 + RH] - (c * ei + dd * er) + sni;
+      }
+      sq[0][qy][qx] = vr;
+      sq[1][qy][qx] = vi;
+    }
+  }
   for (int q = threadIdx.x; q < FTX * FTY; q += 256) {
     const int qy = q / FTX, qx = q % FTX;
     const int j = y0 + qy, i = x0 + qx;
     if (j >= m || i >= m) continue;
-    const int ey = qy + EH, ex = qx + EH;
-    const T er = se[0][ey][ex], ei = se[1][ey][ex];
     T* ep = eo.at(k, j, i);
-    ep[0] = er;
-    ep[eo.pstride] = ei;
-    if (RES) {
-      T wl, wr, wd, wu;
-      couplings(wx, wy, j, i, m, wl, wr, wd, wu);
-      const T d = wl + wr + wd + wu;
-      const T snr = wl * se[0][ey][ex - 1] + wr * se[0][ey][ex + 1] + wd * se[0][ey - 1][ex] +
-                    wu * se[0][ey + 1][ex];
-      const T sni = wl * se[1][ey][ex - 1] + wr * se[1][ey][ex + 1] + wd * se[1][ey - 1][ex] +
-                    wu * se[1][ey + 1][ex];
-      const T c = lr + d, dd = li;
-      const int ry = qy + RH, rx = qx + RH;
-      T* op = res.at(k, j, i);
-      op[0] = sr[0][ry][rx] - (c * er - dd * ei) + snr;
-      op[res.pstride] = sr[1][ry][rx] - (c * ei + dd * er) + sni;
-    }
+    ep[0] = se[0][qy + EH][qx + EH];
+    ep[eo.pstride] = se[1][qy + EH][qx + EH];
   }
-}
-
-// coarse (J, I) = (1/16) [4 f(j,i) + 2 (edge neighbours) + corners], j = 2J+1, i = 2I+1
-template <typename T>
-__global__ void k_restrict(GView<T> f, GView<T> c, int mf, int mc, int nh) {
-  const int64_t total = (int64_t)nh * mc * mc;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int k = (int)(idx / ((int64_t)mc * mc));
-    const int rem = (int)(idx - (int64_t)k * mc * mc);
-    const int J = rem / mc, I = rem - J * mc;
-    const int j = 2 * J + 1, i = 2 * I + 1;   // interior of the fine grid: all 9 exist
-    for (int pl = 0; pl < 2; ++pl) {
-      const T* p = f.at(k, j, i) + pl * f.pstride;
-      const int P = f.pitch;
-      const T v = T(4) * p[0] + T(2) * (p[-1] + p[1] + p[-P] + p[P]) +
-                  (p[-P - 1] + p[-P + 1] + p[P - 1] + p[P + 1]);
-      c.at(k, J, I)[pl * c.pstride] = v * T(0.0625);
+  if (RST) {
+    __syncthreads();
+    // coarse (J, I) = (1/16) [4 centre + 2 (edge neighbours) + corners] of the
+    // residual around fine node (2J+1, 2I+1)
+    constexpr int CX = FTX / 2, CY = FTY / 2;
+    for (int q = threadIdx.x; q < CX * CY; q += 256) {
+      const int J = y0 / 2 + q / CX, I = x0 / 2 + q % CX;
+      if (J >= mcr || I >= mcr) continue;
+      const int ly = 2 * J + 1 - y0 + 1, lx = 2 * I + 1 - x0 + 1;
+      for (int pl = 0; pl < 2; ++pl) {
+        const T v = T(4) * sq[pl][ly][lx] +
+                    T(2) * (sq[pl][ly][lx - 1] + sq[pl][ly][lx + 1] + sq[pl][ly - 1][lx] +
+                            sq[pl][ly + 1][lx]) +
+                    (sq[pl][ly - 1][lx - 1] + sq[pl][ly - 1][lx + 1] + sq[pl][ly + 1][lx - 1] +
+                     sq[pl][ly + 1][lx + 1]);
+        rc.at(k, J, I)[pl * rc.pstride] = v * T(0.0625);
+      }
     }
   }
 }
@@ -310,21 +322,22 @@ hipError_t mg_rbgs(const MgGrid& e, const MgGrid& r, const void* wx, const void*
 }
 
 template <typename T>
-hipError_t mg_sweep(const MgGrid& e, const MgGrid& eo, const MgGrid& r, const MgGrid* res,
-                    const MgGrid* ec, int mc, const void* wx, const void* wy, const double* lam,
-                    int m, int nh, int zero_init, hipStream_t s) {
+hipError_t mg_sweep(const MgGrid& e, const MgGrid& eo, const MgGrid& r, const MgGrid* rc,
+                    int mcr, const MgGrid* ec, int mc, const void* wx, const void* wy,
+                    const double* lam, int m, int nh, int zero_init, hipStream_t s) {
   if (m < 1 || nh < 1 || nh > 65535) return hipErrorInvalidValue;
   if (!zero_init && e.p == eo.p) return hipErrorInvalidValue;   // blocks read old values
   if ((ec != nullptr) != (mc > 0) || (ec && 2 * mc + 1 > m)) return hipErrorInvalidValue;
+  if ((rc != nullptr) != (mcr > 0) || (rc && 2 * mcr + 1 > m)) return hipErrorInvalidValue;
   const dim3 grid((m + FTX - 1) / FTX, (m + FTY - 1) / FTY, nh);
   const GView<T> vc = ec ? view<T>(*ec) : view<T>(e);
-  if (res)
+  if (rc)
     hipLaunchKernelGGL((k_rbgs_fused<T, true>), grid, dim3(256), 0, s, view<T>(e), view<T>(eo),
-                       view<T>(r), view<T>(*res), vc, ec ? mc : 0, (const T*)wx, (const T*)wy,
-                       lam, m, zero_init);
+                       view<T>(r), view<T>(*rc), mcr, vc, ec ? mc : 0, (const T*)wx,
+                       (const T*)wy, lam, m, zero_init);
   else
     hipLaunchKernelGGL((k_rbgs_fused<T, false>), grid, dim3(256), 0, s, view<T>(e),
-                       view<T>(eo), view<T>(r), view<T>(eo), vc, ec ? mc : 0, (const T*)wx,
+                       view<T>(eo), view<T>(r), view<T>(eo), 0, vc, ec ? mc : 0, (const T*)wx,
                        (const T*)wy, lam, m, zero_init);
   return hipGetLastError();
 }
@@ -337,22 +350,14 @@ hipError_t mg_residual(const MgGrid& e, const MgGrid& r, const MgGrid& res, cons
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t mg_restrict(const MgGrid& f, const MgGrid& c, int mf, int mc, int nh, hipStream_t s) {
-  hipLaunchKernelGGL((k_restrict<T>), dim3(mg_grid((int64_t)nh * mc * mc)), dim3(256), 0, s,
-                     view<T>(f), view<T>(c), mf, mc, nh);
-  return hipGetLastError();
-}
-
 #define INST(T)                                                                                 \
   template hipError_t mg_rbgs<T>(const MgGrid&, const MgGrid&, const void*, const void*,       \
                                  const double*, int, int, int, int, hipStream_t);              \
   template hipError_t mg_sweep<T>(const MgGrid&, const MgGrid&, const MgGrid&, const MgGrid*, \
-                                  const MgGrid*, int, const void*, const void*, const double*, \
-                                  int, int, int, hipStream_t);                                 \
+                                  int, const MgGrid*, int, const void*, const void*,           \
+                                  const double*, int, int, int, hipStream_t);                  \
   template hipError_t mg_residual<T>(const MgGrid&, const MgGrid&, const MgGrid&, const void*, \
-                                     const void*, const double*, int, int, hipStream_t);       \
-  template hipError_t mg_restrict<T>(const MgGrid&, const MgGrid&, int, int, int, hipStream_t);
+                                     const void*, const double*, int, int, hipStream_t);
 
 INST(double)
 INST(float)
