@@ -1,0 +1,60 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU guard, the algorithmic
+byte and flop counts behind the roofline record (checked against independent
+counts), and that solutions are copied for the oracle check only when it runs.
+"""
+import os
+import subprocess
+import sys
+
+import bench
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_dst_bytes_per_launch():
+    """One DST pass reads and writes the spectrum of real time data once: n/2 - 1
+    complex blocks and the two real ones, i.e. n m values, FP64."""
+    w = W.WORKLOADS["heat2d_255x256"]
+    assert bench.class_bytes(w, "fp64")["dst"] == 2 * 256 * 255 * 255 * 8 == 266342400
+
+
+def test_dst_launch_mix_and_flops():
+    """255^2 x 256 FP64: x forward, fused last axis (forward, divide, inverse),
+    x inverse = 3 launches for 4 products.  The two-level fold runs a quarter
+    of the dense DST-I multiply-adds, the one-level fold half."""
+    w = W.WORKLOADS["heat2d_255x256"]
+    assert bench.dst_path(w, "fp64") == "fold2"
+    assert bench.dst_launch_mix(w, "fp64") == (3, 4)
+    md = w.m1
+    dense_flops = 2.0 * md * md * w.n * (w.m // md)
+    assert abs(bench.dst_product_flops(w, "fp64") / dense_flops - 0.25) < 0.005
+    w32 = W.WORKLOADS["heat2d_511x512"]
+    assert bench.dst_path(w32, "fp32") == "fold"
+    dense32 = 2.0 * w32.m1 ** 2 * w32.n * (w32.m // w32.m1)
+    assert abs(bench.dst_product_flops(w32, "fp32") / dense32 - 0.5) < 0.002
+    assert abs(bench.dst_flops_per_launch(w, "fp64") - 2.841e9) < 0.001e9
+
+
+def test_record_only_when_checking():
+    class Fake:
+        def cpu(self):
+            raise AssertionError("copied although the checks are off")
+    bench.record(None, {}, ("heat", "heat2d_255x256"), Fake())
+    checks = []
+
+    class Dev:
+        def cpu(self):
+            return self
+
+        def numpy(self):
+            return "u"
+    bench.record(checks, {"x": 1}, ("cd", "cd2d_255x256"), Dev())
+    assert checks == [({"x": 1}, ("cd", "cd2d_255x256"), "u")]
