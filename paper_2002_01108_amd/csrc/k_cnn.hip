@@ -40,33 +40,65 @@ __global__ __launch_bounds__(PT) void k_conv_fwd(const float* __restrict__ x,
                                                  const float* __restrict__ bias,
                                                  float* __restrict__ z, float* __restrict__ out,
                                                  int H, int W, int nchunk) {
-  __shared__ float ws[CO * CI * 9];
-  for (int i = threadIdx.x; i < CO * CI * 9; i += PT) ws[i] = w[i];
+  // weights staged tap-major, [c][di][dj][o], so that the CO weights of one
+  // tap are contiguous (vector LDS reads, broadcast to the wave)
+  __shared__ __align__(16) float ws[CI * 9 * CO];
+  for (int t = threadIdx.x; t < CO * CI * 9; t += PT) {
+    const int o = t / (CI * 9), tap = t - o * (CI * 9);
+    ws[tap * CO + o] = w[t];
+  }
   __syncthreads();
   const int HW = H * W;
   const int b = blockIdx.x / nchunk, chunk = blockIdx.x - b * nchunk;
   const int p = chunk * PT + threadIdx.x;
   if (p >= HW) return;
   const int i = p / W, j = p - i * W;
-  float acc[CO];
+  // the 9 inputs of the next channel are loaded (from clamped in-range
+  // addresses) while the current channel's taps are accumulated, and the taps
+  // outside the image are zeroed afterwards, so loads overlap the arithmetic
+  // instead of waiting one tap at a time behind a bounds test
+  const int jm = j > 0 ? j - 1 : j, jp = j < W - 1 ? j + 1 : j;
+  int rowoff[3];
+  bool rok[3];
 #pragma unroll
-  for (int o = 0; o < CO; ++o) acc[o] = 0.f;
+  for (int di = 0; di < 3; ++di) {
+    const int ii = i + di - 1;
+    rok[di] = ii >= 0 && ii < H;
+    rowoff[di] = (rok[di] ? ii : i) * W;
+  }
+  bool tap_ok[9];
 #pragma unroll
-  for (int c = 0; c < CI; ++c) {
+  for (int di = 0; di < 3; ++di) {
+    tap_ok[3 * di] = rok[di] && j > 0;
+    tap_ok[3 * di + 1] = rok[di];
+    tap_ok[3 * di + 2] = rok[di] && j < W - 1;
+  }
+  auto load9 = [&](int c, float (&v)[9]) {
     const float* xc = x + ((int64_t)b * CI + c) * HW;
 #pragma unroll
     for (int di = 0; di < 3; ++di) {
-      const int ii = i + di - 1;
-      if (ii < 0 || ii >= H) continue;
-#pragma unroll
-      for (int dj = 0; dj < 3; ++dj) {
-        const int jj = j + dj - 1;
-        if (jj < 0 || jj >= W) continue;
-        const float v = xc[ii * W + jj];
-#pragma unroll
-        for (int o = 0; o < CO; ++o) acc[o] += ws[((o * CI + c) * 3 + di) * 3 + dj] * v;
-      }
+      v[3 * di] = xc[rowoff[di] + jm];
+      v[3 * di + 1] = xc[rowoff[di] + j];
+      v[3 * di + 2] = xc[rowoff[di] + jp];
     }
+  };
+  float acc[CO];
+#pragma unroll
+  for (int o = 0; o < CO; ++o) acc[o] = 0.f;
+  float cur[9], nxt[9];
+  load9(0, cur);
+#pragma unroll 1
+  for (int c = 0; c < CI; ++c) {
+    if (c + 1 < CI) load9(c + 1, nxt);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const float vv = tap_ok[t] ? cur[t] : 0.f;
+      const float* wt = ws + (c * 9 + t) * CO;
+#pragma unroll
+      for (int o = 0; o < CO; ++o) acc[o] += wt[o] * vv;
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) cur[t] = nxt[t];
   }
 #pragma unroll
   for (int o = 0; o < CO; ++o) {
