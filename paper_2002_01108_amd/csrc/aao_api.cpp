@@ -914,9 +914,12 @@ aao_status cnn_inner_t(aao_ctx* c, void* r, void* e) {
   HIPCHK(c, hipMemcpyAsync(n.phi, n.phik, 4 * nh * sizeof(float), hipMemcpyDeviceToDevice,
                            c->stream));
   TRY(cnn_forward_run(c, nh, m, m, false));
-  HIPCHK(c, cnn_unpack_add<T>(n.Y, n.ss, E, c->lam, n.wxf, n.wyf, m, nh, c->stream));
-  HIPCHK(c, mg_rbgs<T>(E, R, L0.wx, L0.wy, c->lam, m, nh, 0, 0, c->stream));
-  HIPCHK(c, mg_rbgs<T>(E, R, L0.wx, L0.wy, c->lam, m, nh, 1, 0, c->stream));
+  // e1 + correction into the level's second buffer, then one red-black sweep
+  // from there back into E
+  const MgGrid X = compact_view(L0.X, m);
+  HIPCHK(c, cnn_unpack_add<T>(n.Y, n.ss, E, X, c->lam, n.wxf, n.wyf, m, nh, c->stream));
+  HIPCHK(c, mg_sweep<T>(X, E, R, nullptr, 0, nullptr, 0, L0.wx, L0.wy, c->lam, m, nh, 0,
+                        c->stream));
   return AAO_OK;
 }
 

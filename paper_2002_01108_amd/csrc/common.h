@@ -257,9 +257,6 @@ struct MgGrid {
 };
 // Level couplings: face weights wx [m][m+1], wy [m+1][m], or, with wy == nullptr,
 // the four coupling planes [W, E, S, N][m][m] in wx (all pre-scaled by tau).
-template <typename T>
-hipError_t mg_rbgs(const MgGrid& e, const MgGrid& r, const void* wx, const void* wy,
-                   const double* lam, int m, int nh, int color, int zero_init, hipStream_t s);
 // One smoothing step (red then black half sweep) in one launch from the old
 // iterate e into eo (eo may be e only with zero_init: the old iterate is then
 // zero and not read); with ec (coarse grid of mc points, 2 mc + 1 <= m) the
@@ -319,8 +316,10 @@ hipError_t cnn_block_sumsq(const MgGrid& v, int m, int nh, float* part, float* o
 template <typename T>
 hipError_t cnn_pack_input(const MgGrid& v, const float* ss, const float* loga, float* X, int m,
                           int nh, int nch, hipStream_t s);
+// vo = v + s Y / (lambda + d) per block (vo may be v)
 template <typename T>
-hipError_t cnn_unpack_add(const float* Y, const float* ss, const MgGrid& v, const double* lam,
-                          const float* wx, const float* wy, int m, int nh, hipStream_t s);
+hipError_t cnn_unpack_add(const float* Y, const float* ss, const MgGrid& v, const MgGrid& vo,
+                          const double* lam, const float* wx, const float* wy, int m, int nh,
+                          hipStream_t s);
 
 }  // namespace aao

@@ -493,8 +493,9 @@ __global__ void k_pack_input(MgGrid v, const float* __restrict__ ss,
 // tau K_a (sum of the four face weights wx [m][m+1], wy [m+1][m])
 template <typename T>
 __global__ void k_unpack_add(const float* __restrict__ Y, const float* __restrict__ ss, MgGrid v,
-                             const double* __restrict__ lam, const float* __restrict__ wx,
-                             const float* __restrict__ wy, int m, int nh) {
+                             MgGrid vo, const double* __restrict__ lam,
+                             const float* __restrict__ wx, const float* __restrict__ wy, int m,
+                             int nh) {
   const int64_t HW = (int64_t)m * m, total = (int64_t)nh * HW;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -506,9 +507,10 @@ __global__ void k_unpack_add(const float* __restrict__ Y, const float* __restric
     const float c = (float)lam[2 * k] + d, li = (float)lam[2 * k + 1];
     const float inv = s / (c * c + li * li);
     const float yr = Y[((int64_t)k * 2 + 0) * HW + p], yi = Y[((int64_t)k * 2 + 1) * HW + p];
-    T* q = (T*)v.p + k * v.bstride + (int64_t)j * v.pitch + i;
-    q[0] += (T)((yr * c + yi * li) * inv);
-    q[v.pstride] += (T)((yi * c - yr * li) * inv);
+    const T* q = (const T*)v.p + k * v.bstride + (int64_t)j * v.pitch + i;
+    T* qo = (T*)vo.p + k * vo.bstride + (int64_t)j * vo.pitch + i;
+    qo[0] = q[0] + (T)((yr * c + yi * li) * inv);
+    qo[vo.pstride] = q[v.pstride] + (T)((yi * c - yr * li) * inv);
   }
 }
 
@@ -684,10 +686,11 @@ hipError_t cnn_pack_input(const MgGrid& v, const float* ss, const float* loga, f
 }
 
 template <typename T>
-hipError_t cnn_unpack_add(const float* Y, const float* ss, const MgGrid& v, const double* lam,
-                          const float* wx, const float* wy, int m, int nh, hipStream_t s) {
+hipError_t cnn_unpack_add(const float* Y, const float* ss, const MgGrid& v, const MgGrid& vo,
+                          const double* lam, const float* wx, const float* wy, int m, int nh,
+                          hipStream_t s) {
   hipLaunchKernelGGL((k_unpack_add<T>), dim3(grid1((int64_t)nh * m * m)), dim3(256), 0, s, Y, ss,
-                     v, lam, wx, wy, m, nh);
+                     v, vo, lam, wx, wy, m, nh);
   return hipGetLastError();
 }
 
@@ -696,8 +699,8 @@ hipError_t cnn_unpack_add(const float* Y, const float* ss, const MgGrid& v, cons
   template hipError_t cnn_pack_input<T>(const MgGrid&, const float*, const float*, float*, int, \
                                         int, int, hipStream_t);                              \
   template hipError_t cnn_unpack_add<T>(const float*, const float*, const MgGrid&,             \
-                                        const double*, const float*, const float*, int, int,    \
-                                        hipStream_t);
+                                        const MgGrid&, const double*, const float*, const float*, \
+                                        int, int, hipStream_t);
 INST(double)
 INST(float)
 #undef INST

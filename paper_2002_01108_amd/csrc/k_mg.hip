@@ -8,8 +8,8 @@
 // Gauss-Seidel (red: i1 + i2 even), one red and one black half sweep per
 // launch (tiled, see k_rbgs_fused), which also restricts the residual after
 // pre-smoothing and adds the prolonged coarse correction before
-// post-smoothing; the stand-alone residual and half sweep (learned correction)
-// take one thread per grid point and block.
+// post-smoothing; the stand-alone residual (learned correction) takes one
+// thread per grid point and block.
 // Restriction: full weighting (transpose of bilinear interpolation / 4).
 // Prolongation: bilinear.  Coarse operators are rediscretised on the host:
 // face weights w = tau/h_l^2 * a with harmonic face averages (flux form), or
@@ -94,41 +94,6 @@ __device__ __forceinline__ void nbr_sum(const GView<T>& e, int k, int j, int i, 
   if (i < m - 1) { sr += wr * c[1]; si += wr * c[ps + 1]; }
   if (j > 0) { sr += wd * c[-e.pitch]; si += wd * c[ps - e.pitch]; }
   if (j < m - 1) { sr += wu * c[e.pitch]; si += wu * c[ps + e.pitch]; }
-}
-
-// One red or black half sweep.  zero_init: the iterate is zero on entry, so
-// the red sweep writes r / (lambda + d) on red points and 0 on black points.
-template <typename T>
-__global__ void k_rbgs(GView<T> e, GView<T> r, const T* __restrict__ wx,
-                       const T* __restrict__ wy, const double* __restrict__ lam, int m, int nh,
-                       int color, int zero_init) {
-  const int64_t total = (int64_t)nh * m * m;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int k = (int)(idx / ((int64_t)m * m));
-    const int rem = (int)(idx - (int64_t)k * m * m);
-    const int j = rem / m, i = rem - j * m;
-    T* ep = e.at(k, j, i);
-    if (((i + j) & 1) != color) {
-      if (zero_init) { ep[0] = T(0); ep[e.pstride] = T(0); }
-      continue;
-    }
-    T sr, si, d;
-    if (zero_init) {
-      T wl, wr, wd, wu;
-      couplings(wx, wy, j, i, m, wl, wr, wd, wu);
-      d = wl + wr + wd + wu;
-      sr = si = T(0);
-    } else {
-      nbr_sum(e, k, j, i, m, wx, wy, sr, si, d);
-    }
-    const T* rp = r.at(k, j, i);
-    const T ar = rp[0] + sr, ai = rp[r.pstride] + si;
-    const T c = (T)lam[2 * k] + d, dd = (T)lam[2 * k + 1];
-    const T inv = T(1) / (c * c + dd * dd);
-    ep[0] = (ar * c + ai * dd) * inv;
-    ep[e.pstride] = (ai * c - ar * dd) * inv;
-  }
 }
 
 // res = r - (lambda + d) e + s
@@ -314,14 +279,6 @@ template <typename T> GView<T> view(const MgGrid& g) {
 }  // namespace
 
 template <typename T>
-hipError_t mg_rbgs(const MgGrid& e, const MgGrid& r, const void* wx, const void* wy,
-                   const double* lam, int m, int nh, int color, int zero_init, hipStream_t s) {
-  hipLaunchKernelGGL((k_rbgs<T>), dim3(mg_grid((int64_t)nh * m * m)), dim3(256), 0, s, view<T>(e),
-                     view<T>(r), (const T*)wx, (const T*)wy, lam, m, nh, color, zero_init);
-  return hipGetLastError();
-}
-
-template <typename T>
 hipError_t mg_sweep(const MgGrid& e, const MgGrid& eo, const MgGrid& r, const MgGrid* rc,
                     int mcr, const MgGrid* ec, int mc, const void* wx, const void* wy,
                     const double* lam, int m, int nh, int zero_init, hipStream_t s) {
@@ -351,8 +308,6 @@ hipError_t mg_residual(const MgGrid& e, const MgGrid& r, const MgGrid& res, cons
 }
 
 #define INST(T)                                                                                 \
-  template hipError_t mg_rbgs<T>(const MgGrid&, const MgGrid&, const void*, const void*,       \
-                                 const double*, int, int, int, int, hipStream_t);              \
   template hipError_t mg_sweep<T>(const MgGrid&, const MgGrid&, const MgGrid&, const MgGrid*, \
                                   int, const MgGrid*, int, const void*, const void*,           \
                                   const double*, int, int, int, hipStream_t);                  \
