@@ -75,3 +75,24 @@ def test_null_context_is_rejected(lib):
     assert lib.aao_apply_Pinv(None, None, None) == binding.EINVAL
     assert lib.aao_sync(None) == binding.EINVAL
     lib.aao_destroy(None)
+
+
+def test_every_context_entry_point_rejects_null(lib):
+    """Each entry point that takes a context returns EINVAL for a null one
+    before it touches the device (other arguments: null pointers, ones)."""
+    skip = {"aao_destroy", "aao_last_error"}
+    checked = 0
+    for name, (res, args) in binding.SIGNATURES.items():
+        if name in skip or not args or args[0] is not ctypes.c_void_p or res is not ctypes.c_int:
+            continue
+        vals = [None]
+        for t in args[1:]:
+            if t in (ctypes.c_int,):
+                vals.append(1)
+            elif t in (ctypes.c_double, ctypes.c_float):
+                vals.append(1.0)
+            else:
+                vals.append(None)
+        assert getattr(lib, name)(*vals) == binding.EINVAL, name
+        checked += 1
+    assert checked >= 27
