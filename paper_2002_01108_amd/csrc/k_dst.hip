@@ -151,7 +151,12 @@ hipError_t gemm_launch(const T* A, int64_t sA, int lda, const T* B, int64_t sB, 
 // hi = rne_bf16(x), lo = rne_bf16(x - hi) and the other (S) split once on the
 // host; C accumulates hi*hi + hi*lo + lo*hi in FP32 on v_mfma_f32_16x16x32_bf16.
 // Both LDS tiles keep k contiguous so that each lane reads its 8 k values of
-// a fragment with one 16-byte load.
+// a fragment with one 16-byte load.  The B tile is stored transposed, one
+// 16-bit element per store, by lanes that hold 8 consecutive columns: with
+// rows 20 dwords apart the 8 column groups of a wave would all hit the same 4
+// banks, so its 16-byte k chunks are XOR-swizzled by column group
+// (chunk (k/8) ^ ((n/8) & 3)), which leaves the fragment reads of 8 lanes
+// (one column group) conflict-free and spreads the stores over 16 banks.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef short s8v __attribute__((ext_vector_type(8)));
 typedef unsigned short u16;
@@ -219,11 +224,14 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_bf16x3(
       }
     }
   };
+  // swizzled position of k in the B tile row of column n (16-byte chunks permuted)
+  auto bsw = [](int n, int k) { return (((k >> 3) ^ ((n >> 3) & 3)) << 3) | (k & 7); };
   auto stash = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) { Ah[buf][ar][ak + e] = rah[e]; Al[buf][ar][ak + e] = ral[e]; }
+    const int bks = bsw(bn, bk);   // bn + e shares bn's column group
 #pragma unroll
-    for (int e = 0; e < 8; ++e) { Bh[buf][bn + e][bk] = rbh[e]; Bl[buf][bn + e][bk] = rbl[e]; }
+    for (int e = 0; e < 8; ++e) { Bh[buf][bn + e][bks] = rbh[e]; Bl[buf][bn + e][bks] = rbl[e]; }
   };
 
   f4 acc[2][2];
@@ -249,9 +257,9 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_bf16x3(
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const int c = wn * 32 + j * 16 + lr;
-      bhi[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const s8v*>(&Bh[buf][c][lk * 8]));
-      blo[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const s8v*>(&Bl[buf][c][lk * 8]));
+      const int c = wn * 32 + j * 16 + lr, kc = bsw(c, lk * 8);
+      bhi[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const s8v*>(&Bh[buf][c][kc]));
+      blo[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const s8v*>(&Bl[buf][c][kc]));
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
