@@ -201,10 +201,15 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_bf16x3(
   u16 rah[8], ral[8], rbh[8], rbl[8];
   auto fetch = [&](int k0) {
     if (A_DATA) {  // A = data rows (M x K, ldd), B = S (K x N, lds_)
-      const float* p = Dm + (int64_t)(arow_ok ? m0 + ar : 0) * ldd + k0 + ak;
+      // 8 consecutive k of one row: two 16-byte loads (the launcher checks
+      // that the data pointer, ldd and the batch stride keep them aligned)
+      const float4* p = reinterpret_cast<const float4*>(
+          Dm + (int64_t)(arow_ok ? m0 + ar : 0) * ldd + k0 + ak);
+      const float4 q0 = p[0], q1 = p[1];
+      const float xv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const float x = arow_ok ? p[e] : 0.f;
+        const float x = arow_ok ? xv[e] : 0.f;
         rah[e] = bf16_rne(x);
         ral[e] = bf16_rne(x - bf16_val(rah[e]));
       }
@@ -291,6 +296,8 @@ hipError_t bf16x3_launch(const float* D, int64_t sD, int ldd, const u16* Shi, co
                          hipStream_t s) {
   if (N % BN || K % XBK || M <= 0 || batch <= 0) return hipErrorInvalidValue;
   if (!A_DATA && M % BM) return hipErrorInvalidValue;
+  if (A_DATA && (reinterpret_cast<uintptr_t>(D) % 16 || ldd % 4 || sD % 4))
+    return hipErrorInvalidValue;   // the data rows are read 16 bytes at a time
   const int tiles_m = (M + BM - 1) / BM, tiles_n = N / BN;
   const int64_t nblk = (int64_t)tiles_m * tiles_n * batch;
   if (nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
