@@ -143,7 +143,8 @@ hipError_t launch_gemm_f32(const float* A, int64_t sA, int lda, const float* B, 
 hipError_t launch_gemm_bf16x3(const uint16_t* Ahi, const uint16_t* Alo, int64_t sA, int lda,
                               const float* B, int64_t sB, int ldb, float* C, int64_t sC, int ldc,
                               int M, int N, int K, int batch, hipStream_t s);
-// Same with the split operand on the right: C = A * S, A FP32 rows, S pre-split.
+// Same with the split operand on the right: C = A * S, A FP32 rows, S pre-split
+// and symmetric (read row-wise), K = N.
 hipError_t launch_gemm_bf16x3_right(const float* A, int64_t sA, int lda, const uint16_t* Bhi,
                                     const uint16_t* Blo, int64_t sB, int ldb, float* C,
                                     int64_t sC, int ldc, int M, int N, int K, int batch,

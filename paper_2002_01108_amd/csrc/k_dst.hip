@@ -151,8 +151,9 @@ hipError_t gemm_launch(const T* A, int64_t sA, int lda, const T* B, int64_t sB, 
 // hi = rne_bf16(x), lo = rne_bf16(x - hi) and the other (S) split once on the
 // host; C accumulates hi*hi + hi*lo + lo*hi in FP32 on v_mfma_f32_16x16x32_bf16.
 // Both LDS tiles keep k contiguous so that each lane reads its 8 k values of
-// a fragment with one 16-byte load.  The B tile is stored transposed, one
-// 16-bit element per store, by lanes that hold 8 consecutive columns: with
+// a fragment with one 16-byte load.  With the data on the right (B = data
+// rows of k) the B tile is stored transposed, one 16-bit element per store,
+// by lanes that hold 8 consecutive columns: with
 // rows 20 dwords apart the 8 column groups of a wave would all hit the same 4
 // banks, so its 16-byte k chunks are XOR-swizzled by column group
 // (chunk (k/8) ^ ((n/8) & 3)), which leaves the fragment reads of 8 lanes
@@ -213,7 +214,9 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_bf16x3(
         rah[e] = bf16_rne(x);
         ral[e] = bf16_rne(x - bf16_val(rah[e]));
       }
-      const int64_t o = (int64_t)(k0 + bk) * lds_ + n0 + bn;
+      // S is symmetric (the DST-I matrix), so B[k][n] = S[n][k]: 8 consecutive
+      // k of column n are one 16-byte run of row n
+      const int64_t o = (int64_t)(n0 + ar) * lds_ + k0 + ak;
 #pragma unroll
       for (int e = 0; e < 8; ++e) { rbh[e] = Shi[o + e]; rbl[e] = Slo[o + e]; }
     } else {       // A = S (M x K, lds_), B = data (K x N, ldd)
@@ -234,9 +237,15 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_bf16x3(
   auto stash = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) { Ah[buf][ar][ak + e] = rah[e]; Al[buf][ar][ak + e] = ral[e]; }
-    const int bks = bsw(bn, bk);   // bn + e shares bn's column group
+    if (A_DATA) {   // column ar, k chunk ak: one 16-byte store at its swizzled chunk
+      const int bks = bsw(ar, ak);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) { Bh[buf][bn + e][bks] = rbh[e]; Bl[buf][bn + e][bks] = rbl[e]; }
+      for (int e = 0; e < 8; ++e) { Bh[buf][ar][bks + e] = rbh[e]; Bl[buf][ar][bks + e] = rbl[e]; }
+    } else {        // 8 columns of one k: transposed, one element per store
+      const int bks = bsw(bn, bk);   // bn + e shares bn's column group
+#pragma unroll
+      for (int e = 0; e < 8; ++e) { Bh[buf][bn + e][bks] = rbh[e]; Bl[buf][bn + e][bks] = rbl[e]; }
+    }
   };
 
   f4 acc[2][2];
@@ -412,11 +421,12 @@ hipError_t launch_gemm_bf16x3(const uint16_t* Ahi, const uint16_t* Alo, int64_t 
   return bf16x3_launch<false>(B, sB, ldb, Ahi, Alo, lda, C, sC, ldc, M, N, K, batch, s);
 }
 
+// B must be symmetric (the kernel reads B[k][n] as B[n][k]); lda = ldb = K = N.
 hipError_t launch_gemm_bf16x3_right(const float* A, int64_t sA, int lda, const uint16_t* Bhi,
                                     const uint16_t* Blo, int64_t sB, int ldb, float* C,
                                     int64_t sC, int ldc, int M, int N, int K, int batch,
                                     hipStream_t s) {
-  if (sB != 0) return hipErrorInvalidValue;
+  if (sB != 0 || N != K) return hipErrorInvalidValue;   // a symmetric (square) B
   return bf16x3_launch<true>(A, sA, lda, Bhi, Blo, ldb, C, sC, ldc, M, N, K, batch, s);
 }
 
