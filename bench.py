@@ -553,7 +553,7 @@ def main():
     for vp in [v for v in args.variants.split(",") if v and v != prec]:
         try:
             s.set_precision(vp)
-        except Exception as e:     # precision not available in this build
+        except Exception as e:     # precision not available in the library
             variants[vp] = {"error": str(e)}
             continue
         tv, iv, _, uv, _ = time_solver(s, fd, u0d, args.tol, restart, max(1, args.steps // 2),

@@ -14,8 +14,8 @@ channels are a complex field divided pointwise by the diagonal of B_k, so it
 learns a correction relative to a Jacobi step) and S_r is one red-black
 Gauss-Seidel sweep for B_k e = r started from its argument.
 
-N (parity unpinned as a model: its architecture is this build's choice, not the
-paper's; its arithmetic is pinned below):
+N (parity unpinned as a model: its architecture is chosen here, not taken from
+the paper; its arithmetic is pinned below):
     x  = [Re rho/s, Im rho/s, log a - mean log a]          3 channels, H x W
     z1 = conv3x3(x, W1);  h1 = relu((1 + G1 phi) * z1 + H1 phi)     C channels
     z2 = conv3x3(h1, W2); h2 = relu((1 + G2 phi) * z2 + H2 phi)     C channels

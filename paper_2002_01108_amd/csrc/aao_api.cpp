@@ -1,6 +1,6 @@
 // Host side of the C ABI declared in include/aao.h: argument checks, device
 // tables, workspace ownership, the three-step BEC inverse (Section 4) and the
-// right-preconditioned flexible GMRES driver (restarted GMRES of Section 5,
+// right-preconditioned flexible GMRES loop (restarted GMRES of Section 5,
 // with classical Gram-Schmidt applied twice on the device and Givens
 // rotations on the host).
 #include <math.h>
