@@ -130,3 +130,40 @@ def test_layout_size():
     _, total = cnn.layout()
     C = cnn.C_HIDDEN
     assert total == C * 27 + 4 * C * 4 + C * C * 9 + 2 * C * 9 + 2
+
+
+def test_node_log_coefficient_written_out():
+    """Each node's value is the log of the mean of its four faces (west x-face i,
+    east x-face i + 1 of row j; south y-face j, north y-face j + 1 of column i),
+    minus the mean over all nodes; written out node by node."""
+    m = 5
+    rng = np.random.default_rng(30)
+    ax = np.exp(rng.uniform(-2, 2, (m, m + 1)))
+    ay = np.exp(rng.uniform(-2, 2, (m + 1, m)))
+    want = np.empty((m, m))
+    for j in range(m):
+        for i in range(m):
+            want[j, i] = np.log((ax[j, i] + ax[j, i + 1] + ay[j, i] + ay[j + 1, i]) / 4.0)
+    want -= want.mean()
+    assert np.allclose(cnn.node_log_coefficient(ax, ay), want, atol=1e-14)
+
+
+def test_node_log_coefficient_invariances():
+    """A constant coefficient gives zeros; scaling every face by c changes nothing
+    (the channel is centred); one node with all four faces v stands out by log v
+    against a unit background before centring."""
+    m = 7
+    ones_x, ones_y = np.ones((m, m + 1)), np.ones((m + 1, m))
+    assert np.allclose(cnn.node_log_coefficient(3.7 * ones_x, 3.7 * ones_y), 0.0, atol=1e-15)
+    rng = np.random.default_rng(31)
+    ax = np.exp(rng.uniform(-1, 1, (m, m + 1)))
+    ay = np.exp(rng.uniform(-1, 1, (m + 1, m)))
+    assert np.allclose(cnn.node_log_coefficient(50 * ax, 50 * ay),
+                       cnn.node_log_coefficient(ax, ay), atol=1e-13)
+    bx, by = ones_x.copy(), ones_y.copy()
+    v, j, i = 9.0, 3, 2
+    bx[j, i] = bx[j, i + 1] = by[j, i] = by[j + 1, i] = v
+    out = cnn.node_log_coefficient(bx, by)
+    # neighbours share one face of v: log((3 + v) / 4); the rest log 1 = 0
+    assert out[j, i] - out[0, 0] == pytest.approx(np.log(v), rel=1e-14)
+    assert out[j, i + 1] - out[0, 0] == pytest.approx(np.log((3 + v) / 4), rel=1e-14)
