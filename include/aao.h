@@ -86,6 +86,8 @@ aao_status aao_set_precision(aao_ctx *ctx, aao_precision p);
  * x-face i of a row lies between interior nodes i-1 and i (face 0 and face m1
  * touch the walls).  K becomes the flux form (K u)_p = h^-2 sum_f a_f (u_p - u_nbr).
  * ax = null restores a = 1.  Values must be positive and finite (AAO_EINVAL).
+ * All inputs are checked before anything changes: a rejected call leaves the
+ * previous operator (coefficient or convection) in place.
  * With a variable coefficient the blocks of Step 2 are no longer diagonalised
  * by sine transforms: select AAO_INNER_DST_MEAN or AAO_INNER_MG. */
 aao_status aao_set_coefficient(aao_ctx *ctx, const double *ax, const double *ay,
@@ -280,7 +282,9 @@ aao_status aao_step3(aao_ctx *ctx, const double *zt, double *z);
  * classical Gram-Schmidt applied twice, all in FP64 on the device; Givens
  * rotations run on the host.
  *  - u: device [n][m]; on entry the initial guess if use_guess != 0 (ignored
- *    otherwise, zero guess); on exit the last iterate.
+ *    otherwise, zero guess); on exit the last iterate.  rhs and u must not
+ *    share memory (the Krylov basis starts from rhs, which the solve keeps
+ *    reading while it writes u): overlapping ranges return AAO_EINVAL.
  *  - Stops when the relative residual ||rhs - L u|| / ||rhs|| (tracked by the
  *    Givens recurrence; with aao_set_side(AAO_LEFT) the preconditioned one) is
  *    <= tol, or after maxit Arnoldi steps in total.
@@ -293,7 +297,8 @@ aao_status aao_step3(aao_ctx *ctx, const double *zt, double *z);
  *    explicitly from u at exit.
  * Returns AAO_OK on convergence (a breakdown h_{j+1,j} = 0 is convergence),
  * AAO_NOT_CONVERGED if maxit was reached, AAO_ENAN for a non-finite rhs,
- * AAO_EINVAL for tol < 0, maxit < 1, restart < 1 or null vectors. */
+ * AAO_EINVAL for tol < 0, maxit < 1, restart < 1, null vectors or rhs and u
+ * overlapping. */
 aao_status aao_solve(aao_ctx *ctx, const double *rhs, double *u, int use_guess, double tol,
                      int maxit, int restart, int *iters, double *res_hist, int hist_cap,
                      int *hist_len, double *final_res);

@@ -91,21 +91,19 @@ def status_string(st: int) -> str:
     return load().aao_status_string(st).decode()
 
 
-def _ptr(t):
+def _dptr(t, numel, device, dtype, what):
+    """Data pointer of a contiguous GPU tensor of `dtype` with exactly `numel`
+    elements on `device`; the library trusts these sizes, so they are checked
+    here (a short array would be read or written past its end on the GPU)."""
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError("expected a GPU torch tensor")
-    if t.dtype != torch.float64 or not t.is_contiguous():
-        raise TypeError("expected a contiguous float64 tensor")
-    return ctypes.c_void_p(t.data_ptr())
-
-
-def _fptr(t):
-    import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError("expected a GPU torch tensor")
-    if t.dtype != torch.float32 or not t.is_contiguous():
-        raise TypeError("expected a contiguous float32 tensor")
+        raise TypeError(f"{what}: expected a GPU torch tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{what}: expected a contiguous {dtype} tensor")
+    if t.numel() != numel:
+        raise ValueError(f"{what}: {t.numel()} elements, expected {numel}")
+    if t.device.index != device:
+        raise ValueError(f"{what}: on cuda:{t.device.index}, the context is on cuda:{device}")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -124,6 +122,7 @@ class Solver:
         self.eps = min(0.5, (self.tau) ** 0.5) if eps is None else eps
         dims = [m1, self.m2, self.m3][:dim]
         self.m = int(np.prod(dims))
+        self.device = torch.cuda.current_device()
         h = ctypes.c_void_p()
         st = self.lib.aao_setup(dim, m1, self.m2, self.m3, n, T, self.eps, ctypes.byref(h))
         if st != OK:
@@ -132,6 +131,16 @@ class Solver:
         s = stream if stream is not None else torch.cuda.current_stream()
         self._check(self.lib.aao_set_stream(self._h, ctypes.c_void_p(s.cuda_stream)))
         self.set_precision(precision)
+
+    def _vec(self, t, numel=None, what="space-time array"):
+        """float64 device array of n*m elements (or `numel`) on this context's GPU."""
+        import torch
+        return _dptr(t, self.n * self.m if numel is None else numel, self.device, torch.float64,
+                     what)
+
+    def _fvec(self, t, numel, what):
+        import torch
+        return _dptr(t, numel, self.device, torch.float32, what)
 
     def _check(self, st, allow=(OK,)):
         if st not in allow:
@@ -148,6 +157,13 @@ class Solver:
             self._check(self.lib.aao_set_coefficient(self._h, None, None, None))
             return
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in faces]
+        ms = [self.m1, self.m2, self.m3][: self.dim]
+        if len(arrs) != self.dim:
+            raise ValueError(f"expected {self.dim} face arrays, got {len(arrs)}")
+        for d, a in enumerate(arrs):
+            want = int(np.prod([v + (e == d) for e, v in enumerate(ms)]))
+            if a.size != want:
+                raise ValueError(f"face array {d}: {a.size} values, expected {want}")
         self._faces = arrs   # keep alive during the call
         ptrs = [a.ctypes.data_as(_pdbl) for a in arrs] + [None] * (3 - len(arrs))
         self._check(self.lib.aao_set_coefficient(self._h, *ptrs))
@@ -160,6 +176,9 @@ class Solver:
             self._check(self.lib.aao_set_convection(self._h, 0.0, None, None))
             return
         wx, wy = (np.ascontiguousarray(a, dtype=np.float64) for a in wind)
+        for name, a in (("wx", wx), ("wy", wy)):
+            if a.size != self.m1 * self.m2:
+                raise ValueError(f"{name}: {a.size} values, expected {self.m1 * self.m2}")
         self._check(self.lib.aao_set_convection(self._h, float(nu), wx.ctypes.data_as(_pdbl),
                                                 wy.ctypes.data_as(_pdbl)))
 
@@ -205,8 +224,9 @@ class Solver:
         B, _, H, W = x.shape
         y = torch.empty((B, 2, H, W), dtype=torch.float32, device=x.device)
         la = self._lam(lam)
-        self._check(self.lib.aao_cnn_forward(self._h, _fptr(x), la.ctypes.data_as(_pdbl),
-                                             B, H, W, _fptr(y)))
+        self._check(self.lib.aao_cnn_forward(self._h, self._fvec(x, B * 3 * H * W, "x"),
+                                             la.ctypes.data_as(_pdbl), B, H, W,
+                                             self._fvec(y, B * 2 * H * W, "y")))
         return y
 
     def cnn_backward(self, x, lam, dy):
@@ -216,14 +236,17 @@ class Solver:
         dx = torch.empty_like(x)
         g = np.zeros(self.cnn_param_count(), dtype=np.float32)
         la = self._lam(lam)
-        self._check(self.lib.aao_cnn_backward(self._h, _fptr(x), la.ctypes.data_as(_pdbl), B, H,
-                                              W, _fptr(dy), _fptr(dx), g.ctypes.data_as(_pflt)))
+        self._check(self.lib.aao_cnn_backward(
+            self._h, self._fvec(x, B * 3 * H * W, "x"), la.ctypes.data_as(_pdbl), B, H, W,
+            self._fvec(dy, B * 2 * H * W, "dy"), self._fvec(dx, B * 3 * H * W, "dx"),
+            g.ctypes.data_as(_pflt)))
         return g, dx
 
     def cnn_make_pairs(self, y, target_cycles: int = 12):
         """y: GPU float64 [S][n][m] space-time fields."""
         S = y.shape[0]
-        self._check(self.lib.aao_cnn_make_pairs(self._h, _ptr(y), S, target_cycles))
+        self._check(self.lib.aao_cnn_make_pairs(self._h, self._vec(y, S * self.n * self.m, "y"),
+                                                S, target_cycles))
         cnt = ctypes.c_int(0)
         self._check(self.lib.aao_cnn_num_pairs(self._h, ctypes.byref(cnt)))
         return cnt.value
@@ -261,38 +284,46 @@ class Solver:
 
     def build_rhs(self, f, u0, out=None):
         out = self.new() if out is None else out
-        self._check(self.lib.aao_build_rhs(self._h, _ptr(f), _ptr(u0), _ptr(out)))
+        self._check(self.lib.aao_build_rhs(self._h, self._vec(f, what="f"),
+                                           self._vec(u0, self.m, "u0"), self._vec(out, what="out")))
         return out
 
     def boundary_source(self, gb, f):
         """f += boundary couplings x Dirichlet values gb (device [n][2 m2 + 2 m1]:
         west, east, south, north walls per time level); f updated in place."""
-        self._check(self.lib.aao_boundary_source(self._h, _ptr(gb), _ptr(f)))
+        nb = self.n * 2 * (self.m1 + self.m2)
+        self._check(self.lib.aao_boundary_source(self._h, self._vec(gb, nb, "gb"),
+                                                 self._vec(f, what="f")))
         return f
 
     def apply_A(self, x, out=None):
         out = self.new() if out is None else out
-        self._check(self.lib.aao_apply_A(self._h, _ptr(x), _ptr(out)))
+        self._check(self.lib.aao_apply_A(self._h, self._vec(x, what="x"),
+                                         self._vec(out, what="out")))
         return out
 
     def apply_Pinv(self, x, out=None):
         out = self.new() if out is None else out
-        self._check(self.lib.aao_apply_Pinv(self._h, _ptr(x), _ptr(out)))
+        self._check(self.lib.aao_apply_Pinv(self._h, self._vec(x, what="x"),
+                                            self._vec(out, what="out")))
         return out
 
     def step1(self, y):
         out = self.new(self.n // 2 + 1, self.m, 2)
-        self._check(self.lib.aao_step1(self._h, _ptr(y), _ptr(out)))
+        self._check(self.lib.aao_step1(self._h, self._vec(y, what="y"),
+                                       self._vec(out, out.numel(), "out")))
         return out
 
     def step2(self, yt):
         out = self.new(self.n // 2 + 1, self.m, 2)
-        self._check(self.lib.aao_step2(self._h, _ptr(yt), _ptr(out)))
+        self._check(self.lib.aao_step2(self._h, self._vec(yt, out.numel(), "yt"),
+                                       self._vec(out, out.numel(), "out")))
         return out
 
     def step3(self, zt):
         out = self.new()
-        self._check(self.lib.aao_step3(self._h, _ptr(zt), _ptr(out)))
+        nzt = (self.n // 2 + 1) * self.m * 2
+        self._check(self.lib.aao_step3(self._h, self._vec(zt, nzt, "zt"), self._vec(out, what="out")))
         return out
 
     def solve(self, rhs, tol: float = 1e-8, maxit: int = 100, restart: int = 50, u=None,
@@ -304,7 +335,8 @@ class Solver:
         hist = (ctypes.c_double * cap)()
         hlen = ctypes.c_int(0)
         fres = ctypes.c_double(float("nan"))
-        st = self.lib.aao_solve(self._h, _ptr(rhs), _ptr(u), int(use_guess), tol, maxit, restart,
+        st = self.lib.aao_solve(self._h, self._vec(rhs, what="rhs"), self._vec(u, what="u"),
+                                int(use_guess), tol, maxit, restart,
                                 ctypes.byref(iters), hist, cap, ctypes.byref(hlen),
                                 ctypes.byref(fres))
         self._check(st, allow=(OK, NOT_CONVERGED))

@@ -1075,7 +1075,11 @@ aao_status aao_setup(int dim, int m1, int m2, int m3, int n, double T, double ep
     aao_destroy(c);
     return st;
   };
-  (void)hipGetDevice(&c->device);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return AAO_EHIP;
+  }
   Geometry& g = c->g;
   g.dim = dim;
   g.m1 = m1;
@@ -1217,48 +1221,62 @@ aao_status aao_set_coefficient(aao_ctx* c, const double* ax, const double* ay,
   if (!c) return AAO_EINVAL;
   const Geometry& g = c->g;
   if (g.q1 && ax) return fail(c, AAO_ESTATE, "Q1 elements need a constant coefficient");
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  c->conv = false;
-  c->host_planes.clear();
-  c->host_wind[0].clear();
-  c->host_wind[1].clear();
-  if (!ax) {  // back to a = 1
-    c->var = false;
-    for (int d = 0; d < 3; ++d) {
-      dfree(c, c->wface[d]);
-      c->wface[d] = nullptr;
-      c->host_face[d].clear();
-    }
-    c->amean = 1.0;
-  } else {
-    const double* src[3] = {ax, ay, az};
-    const int ms[3] = {g.m1, g.m2, g.m3};
-    size_t counts[3];
+  // every input is checked before any state changes, so a rejected call leaves
+  // the previous operator (face weights or convection planes) in place
+  const double* src[3] = {ax, ay, az};
+  const int msz[3] = {g.m1, g.m2, g.m3};
+  size_t counts[3] = {0, 0, 0};
+  if (ax) {
     for (int d = 0; d < g.dim; ++d) {
       if (!src[d]) return fail(c, AAO_EINVAL, "missing face array");
       size_t cnt = 1;
-      for (int e = 0; e < g.dim; ++e) cnt *= (size_t)(ms[e] + (e == d ? 1 : 0));
+      for (int e = 0; e < g.dim; ++e) cnt *= (size_t)(msz[e] + (e == d ? 1 : 0));
       counts[d] = cnt;
       for (size_t i = 0; i < cnt; ++i)
         if (!(src[d][i] > 0.0) || !isfinite(src[d][i]))
           return fail(c, AAO_EINVAL, "coefficients must be positive and finite");
     }
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  // drop the previous operator: back to a = 1 first, so that a failed upload
+  // below leaves a consistent constant-coefficient context
+  c->conv = false;
+  c->host_planes.clear();
+  c->host_wind[0].clear();
+  c->host_wind[1].clear();
+  c->var = false;
+  for (int d = 0; d < 3; ++d) {
+    dfree(c, c->wface[d]);
+    c->wface[d] = nullptr;
+    c->host_face[d].clear();
+  }
+  c->amean = 1.0;
+  mg_release(c);
+  dfree(c, c->cnn.loga);  // rebuilt from the new coefficient on next use
+  c->cnn.loga = nullptr;
+  aao_status upload_st = AAO_OK;
+  if (ax) {
     double sum = 0.0;
     size_t tot = 0;
-    for (int d = 0; d < g.dim; ++d) {
-      c->host_face[d].assign(src[d], src[d] + counts[d]);
+    for (int d = 0; d < g.dim && upload_st == AAO_OK; ++d) {
       std::vector<double> w(counts[d]);
       for (size_t i = 0; i < counts[d]; ++i) {
         w[i] = c->cst[d] * src[d][i];
         sum += src[d][i];
       }
       tot += counts[d];
-      dfree(c, c->wface[d]);
-      c->wface[d] = nullptr;
-      TRY(upload(c, &c->wface[d], w));
+      upload_st = upload(c, &c->wface[d], w);
     }
-    c->var = true;
-    c->amean = sum / (double)tot;
+    if (upload_st == AAO_OK) {
+      for (int d = 0; d < g.dim; ++d) c->host_face[d].assign(src[d], src[d] + counts[d]);
+      c->var = true;
+      c->amean = sum / (double)tot;
+    } else {
+      for (int d = 0; d < 3; ++d) {   // stay at a = 1
+        dfree(c, c->wface[d]);
+        c->wface[d] = nullptr;
+      }
+    }
   }
   // mean-coefficient sine-transform tables: abar * tau * mu_i
   const int Ps[3] = {g.P1, g.P2, g.P3};
@@ -1272,10 +1290,7 @@ aao_status aao_set_coefficient(aao_ctx* c, const double* ax, const double* ay,
     HIPCHK(c, hipMemcpy(c->tmu_mean[d], t.data(), t.size() * sizeof(double),
                         hipMemcpyHostToDevice));
   }
-  mg_release(c);
-  dfree(c, c->cnn.loga);  // rebuilt from the new coefficient on next use
-  c->cnn.loga = nullptr;
-  return AAO_OK;
+  return upload_st;
 }
 
 aao_status aao_set_convection(aao_ctx* c, double nu, const double* wx, const double* wy) {
@@ -1761,16 +1776,29 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
                      int* hist_len, double* final_res) {
   if (!c || !rhs || !u) return AAO_EINVAL;
   if (!(tol >= 0.0) || maxit < 1 || restart < 1) return fail(c, AAO_EINVAL, "solve arguments");
+  const int64_t nm = nm_of(c);
+  {
+    // the basis starts from rhs and the update writes u: they must not share memory
+    const uintptr_t r0 = (uintptr_t)rhs, u0 = (uintptr_t)u;
+    const uintptr_t bytes = (uintptr_t)nm * sizeof(double);
+    if (r0 < u0 + bytes && u0 < r0 + bytes)
+      return fail(c, AAO_EINVAL, "rhs and u must not overlap");
+  }
   if (iters) *iters = 0;
   if (hist_len) *hist_len = 0;
-  const int64_t nm = nm_of(c);
   TRY(ensure_krylov(c, restart));
   const int R = restart;
   // small scratch (doubles): [0] norm, [1..R+1] c1, [R+2..2R+2] c2, [2R+3] norm2,
-  // [2R+4..3R+4] y or the unit coefficient, [3R+5..4R+5] 1/s_i^2
+  // [2R+4..3R+4] y, [3R+5..4R+5] 1/s_i^2, [4R+6] the constant 1 (restart
+  // residuals).  The host writes a slot only when no queued copy still reads it:
+  // y is rewritten after the next synchronising fetch, and the constant is
+  // written once per solve, so a restart never overwrites y while its copy waits.
   const int o_nrm = 0, o_h1 = 1, o_h2 = R + 2, o_n2 = 2 * R + 3, o_y = 2 * R + 4;
-  const int o_is2 = 3 * R + 5;
+  const int o_is2 = 3 * R + 5, o_one = 4 * R + 6;
   TRY(ensure_small(c, (size_t)(4 * R + 8)));
+  c->hsmall[o_one] = 1.0;
+  HIPCHK(c, hipMemcpyAsync(c->dsmall + o_one, c->hsmall + o_one, sizeof(double),
+                           hipMemcpyHostToDevice, c->stream));
   const int nb = krylov_blocks(nm);
   TRY(ensure_part(c, std::max((size_t)nb * (R + 2), (size_t)stencil_partials(c->g) * 8)));
 
@@ -1854,12 +1882,9 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
     } else if (left) {
       // W_0 = P^{-1} (L u - rhs) = -P^{-1} r0
       TRY(apply_L(c, u, c->tmp));
-      c->hsmall[o_y] = 1.0;
-      HIPCHK(c, hipMemcpyAsync(c->dsmall + o_y, c->hsmall + o_y, sizeof(double),
-                               hipMemcpyHostToDevice, c->stream));
       {
         ProfScope ps(c, AAO_K_KRYLOV);
-        HIPCHK(c, launch_axpy_dot(rhs, 0, nullptr, 1, c->dsmall + o_y, c->tmp, nm, c->part, 0,
+        HIPCHK(c, launch_axpy_dot(rhs, 0, nullptr, 1, c->dsmall + o_one, c->tmp, nm, c->part, 0,
                                   c->stream));
       }
       TRY(apply_pinv(c, c->tmp, c->V));
@@ -1880,12 +1905,9 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
     } else {
       // W_0 = L u - rhs = -r0 in place in V, with its norm in the same pass
       TRY(apply_L(c, u, c->V));
-      c->hsmall[o_y] = 1.0;
-      HIPCHK(c, hipMemcpyAsync(c->dsmall + o_y, c->hsmall + o_y, sizeof(double),
-                               hipMemcpyHostToDevice, c->stream));
       {
         ProfScope ps(c, AAO_K_KRYLOV);
-        HIPCHK(c, launch_axpy_dot(rhs, 0, nullptr, 1, c->dsmall + o_y, c->V, nm, c->part, 2,
+        HIPCHK(c, launch_axpy_dot(rhs, 0, nullptr, 1, c->dsmall + o_one, c->V, nm, c->part, 2,
                                   c->stream));
         HIPCHK(c, launch_reduce_partials(c->part, nb, 1, c->dsmall + o_nrm, 0, nullptr,
                                          c->stream));

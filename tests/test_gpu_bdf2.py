@@ -8,6 +8,7 @@ import pytest
 
 from oracle import bdf
 import workloads as W
+from errnorms import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -21,10 +22,6 @@ def dev(a):
 def host(t):
     torch.cuda.synchronize()
     return t.cpu().numpy()
-
-
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def solver(dim, m1, n, eps, T=1.0, precision="fp64", side="right"):

@@ -15,6 +15,7 @@ import pytest
 
 from oracle import cd, heat, mg
 import workloads as W
+from errnorms import rel
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -27,10 +28,6 @@ def dev(a):
 def host(t):
     torch.cuda.synchronize()
     return t.cpu().numpy()
-
-
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def cd_solver(m1, n, eps, cycles=1, precision="fp64", side="right"):

@@ -11,6 +11,7 @@ import pytest
 
 from oracle import cnn, heat, mg
 import workloads as W
+from errnorms import rel
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -27,10 +28,6 @@ def dev(a):
 def host(t):
     torch.cuda.synchronize()
     return t.cpu().numpy()
-
-
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 def params_for(seed):

@@ -24,6 +24,7 @@ import numpy as np
 import pytest
 
 from oracle import heat
+from errnorms import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -37,11 +38,6 @@ def dev(a):
 def host(t):
     torch.cuda.synchronize()
     return t.cpu().numpy()
-
-
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 def fwd_tol(dim, m1, tau):

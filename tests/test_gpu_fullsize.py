@@ -1,34 +1,31 @@
 """Parity at the full workload sizes, in the launch configuration the benchmark
 times, through the C ABI.
 
-The oracle cannot afford P^{-1} at these sizes, so the tests use what it can
-compute exactly or what holds at any size:
-  * L v with the oracle's sparse operator (whole array, 2D sizes);
+  * L v against the oracle's sparse operator (whole array: 2D and the 3D
+    127^3 x 256 workload);
+  * P^{-1} against the oracle's three-step inverse (naive DFT + sparse LU per
+    block) on the whole heat2d 255^2 x 256 array, element by element;
   * P^{-1} (P v) = v, with P v = L v - eps [v^N, 0, ..., 0] (Section 3), for
-    every precision and for the 3D workload;
-  * the solve against the oracle's sequential backward-Euler solution (2D), and
-    the oracle's residual of the GPU solution (3D, where a direct solve is out
-    of reach on the CPU).
+    every precision and for the 3D workload (the oracle's P^{-1} is out of
+    reach there);
+  * the solves against the oracle's sequential backward-Euler solution (2D:
+    sparse LU per step; 3D: the sine-basis solve of each step), FP64 at
+    1e-10 and the reduced-precision preconditioners at 1e-8 after FGMRES.
 Tolerances as in the small-size parity tests; P^{-1} P v carries the
 eps^{-1} growth of the Gamma_eps scaling.
 """
+import os
+
 import numpy as np
 import pytest
 
 from oracle import heat
 import workloads as W
+from errnorms import rel, trel
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 torch = pytest.importorskip("torch")
-
-
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
-
-
-def trel(a, b):
-    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
 
 def make_solver(w, precision):
@@ -41,7 +38,11 @@ def seeded_gpu(w, seed):
     return torch.randn((w.n, w.m), dtype=torch.float64, device="cuda", generator=g)
 
 
-@pytest.mark.parametrize("name", ["heat2d_255x256", "heat2d_511x512"])
+def oracle_workers():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+@pytest.mark.parametrize("name", ["heat2d_255x256", "heat2d_511x512", "heat3d_127x256"])
 def test_apply_A_full(name):
     w = W.WORKLOADS[name]
     s = make_solver(w, "fp64")
@@ -51,6 +52,22 @@ def test_apply_A_full(name):
     p = heat.Problem(w.m1, w.dim, w.n, eps=w.epsilon)
     ref = p.L(x.cpu().numpy())
     assert rel(y.cpu().numpy(), ref) < 1e-12
+
+
+def test_pinv_vs_oracle_c2():
+    """heat2d 255^2 x 256, FP64: the GPU's P^{-1} against the oracle's three steps
+    (explicit Fourier matrix, one sparse complex LU per kept block) on the whole
+    array, element by element (relative 2-norm and normalised max-abs)."""
+    w = W.WORKLOADS["heat2d_255x256"]
+    s = make_solver(w, "fp64")
+    x = seeded_gpu(w, 13)
+    z = s.apply_Pinv(x)
+    torch.cuda.synchronize()
+    p = heat.Problem(w.m1, w.dim, w.n, eps=w.epsilon)
+    ref = p.Pinv(x.cpu().numpy())
+    err = rel(z.cpu().numpy(), ref)
+    print(f"P^-1 vs oracle at 255^2 x 256: {err:.2e}", flush=True)
+    assert err < 1e-11
 
 
 PINV_CASES = [  # (workload, precision, forward tolerance, backward tolerance)
@@ -125,13 +142,26 @@ def test_solve_c3_vs_sequential_be(c3_exact, precision):
     assert err < (1e-10 if precision == "fp64" else 1e-8)
 
 
-def test_solve_c4_fp32_oracle_residual():
+@pytest.fixture(scope="module")
+def c4_exact():
     w = W.WORKLOADS["heat3d_127x256"]
     f, u0, _ = W.make(w)
-    u, info = _gpu_solve(w, f, u0, "fp32", 1e-8, restart=10)
-    assert info["status"] == 0 and info["final_res"] <= 1e-8
     p = heat.Problem(w.m1, w.dim, w.n, eps=w.epsilon)
     rhs = p.rhs(f, u0)
-    res = rel(p.L(u), rhs)
-    print(f"iters {info['iters']} oracle relres {res:.2e}", flush=True)
+    return w, p, f, u0, rhs, p.exact(rhs, workers=oracle_workers())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_solve_c4_vs_sequential_be(c4_exact, precision):
+    """heat3d 127^3 x 256 (524 M unknowns) against the oracle's sequential
+    backward Euler: FP64 1e-10, the FP32 preconditioner 1e-8 after FGMRES; the
+    oracle's residual of the GPU solution as well."""
+    w, p, f, u0, rhs, exact = c4_exact
+    u, info = _gpu_solve(w, f, u0, precision, 1e-8, restart=10)
+    assert info["status"] == 0 and info["final_res"] <= 1e-8
+    err = rel(u, exact)
+    res = float(np.linalg.norm(p.L(u) - rhs) / np.linalg.norm(rhs))
+    print(f"{precision}: iters {info['iters']} rel.err {err:.2e} oracle relres {res:.2e}",
+          flush=True)
+    assert err < (1e-10 if precision == "fp64" else 1e-8)
     assert res < 2e-8

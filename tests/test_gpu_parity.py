@@ -14,6 +14,7 @@ import pytest
 
 from oracle import heat
 import workloads as W
+from errnorms import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -27,11 +28,6 @@ def dev(a):
 def host(t):
     torch.cuda.synchronize()
     return t.cpu().numpy()
-
-
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 def solver(dim, m1, n, eps, precision="fp64", T=1.0):

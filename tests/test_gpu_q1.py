@@ -26,6 +26,7 @@ import pytest
 
 from oracle import bdf, fe
 import workloads as W
+from errnorms import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -41,10 +42,6 @@ def dev(a):
 def host(t):
     torch.cuda.synchronize()
     return t.cpu().numpy()
-
-
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def solver(m1, n, eps, T=1.0, order=1, precision="fp64", side="right"):
@@ -93,7 +90,12 @@ def test_fp32_Pinv_backward_error():
     s64 = solver(m1, n, eps)
     Pz = host(s64.apply_A(dev(z)))
     Pz[0] -= eps * (p.M @ z[-1])          # P = L + the eps-wrapped corner (BDF1)
-    assert rel(Pz, v) <= 3e-5
+    # 2-norm: 3e-5 as for every FP32 P^{-1}.  Max-abs: the FP32 rounding of the
+    # spectrum reaches time level j amplified by eps^{-j/n} (Step 3), the last
+    # level by eps^{-(n-1)/n} = 16.6 here, against the root-mean-square growth of
+    # 7.4 over all levels that the 2-norm sees: 1e-4.
+    assert np.linalg.norm(Pz - v) / np.linalg.norm(v) <= 3e-5
+    assert np.abs(Pz - v).max() / np.abs(v).max() <= 1e-4
 
 
 @pytest.mark.parametrize("order", [1, 2])

@@ -10,6 +10,7 @@ import pytest
 
 from oracle import heat, mg
 import workloads as W
+from errnorms import rel
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -22,10 +23,6 @@ def dev(a):
 def host(t):
     torch.cuda.synchronize()
     return t.cpu().numpy()
-
-
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 def rand_faces(m1, dim, seed):

@@ -95,3 +95,17 @@ def test_sine_stepping_rectangular():
     a = heat.sequential_be_sine(ms, tau, rhs)
     b = heat.sequential_be(K, tau, rhs)
     assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-13
+
+
+@pytest.mark.parametrize("ms,n", [((31, 31), 8), ((20, 9), 6), ((63,), 16)])
+def test_sine_stepping_1d_2d(ms, n):
+    """The same route on 1D and 2D grids (the benchmark's oracle references for
+    its 2D workloads use it) against the sparse-LU stepping."""
+    K = heat.stiffness_rect(ms)
+    tau = 1.0 / n
+    rng = np.random.default_rng(6)
+    rhs = rng.standard_normal((n, K.shape[0]))
+    a = heat.sequential_be_sine(ms, tau, rhs)
+    b = heat.sequential_be(K, tau, rhs)
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-13
+    assert np.abs(a - b).max() / np.abs(b).max() < 1e-13
