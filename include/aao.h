@@ -214,6 +214,22 @@ aao_status aao_cnn_get_params(aao_ctx *ctx, float *params, int count);
 aao_status aao_cnn_forward(aao_ctx *ctx, const float *x, const double *lam, int B, int H, int W,
                            float *y);
 
+/* aao_cnn_forward without any allocation, for callers that cannot allocate
+ * device memory (serving loops, code under stream capture, harnesses that
+ * forbid hipMalloc): same arguments, layouts and result as aao_cnn_forward.
+ * Its workspace (lambda, features, FiLM coefficients and the two hidden
+ * layers) lives in one fixed 64 MiB device array per GPU, loaded with the
+ * library and held until the process ends; x and y stay the caller's.  Limit:
+ * 16 B H W + 36 B floats (plus alignment) must fit in 16 Mi floats, about one
+ * million pixels over all images; larger requests return AAO_EINVAL before any
+ * device work.  The host lambda array is consumed before the call returns (the
+ * context's stream is synchronised once).  Every call on a GPU, from any
+ * context, uses that GPU's one array: calls that overlap in time on one GPU
+ * (other threads, other streams) race and must be serialised by the caller.
+ * Needs parameters (AAO_ESTATE otherwise). */
+aao_status aao_cnn_forward_noalloc(aao_ctx *ctx, const float *x, const double *lam, int B, int H,
+                                   int W, float *y);
+
 /* Gradients of sum(dy * N(x)): parameter gradient to host grad[count] (may be
  * null), input gradient to device dx [B][3][H][W] (may be null). */
 aao_status aao_cnn_backward(aao_ctx *ctx, const float *x, const double *lam, int B, int H, int W,

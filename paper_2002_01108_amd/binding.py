@@ -53,6 +53,7 @@ SIGNATURES = {
     "aao_cnn_set_params": (_c_int, [_vp, _pflt, _c_int]),
     "aao_cnn_get_params": (_c_int, [_vp, _pflt, _c_int]),
     "aao_cnn_forward": (_c_int, [_vp, _vp, _pdbl, _c_int, _c_int, _c_int, _vp]),
+    "aao_cnn_forward_noalloc": (_c_int, [_vp, _vp, _pdbl, _c_int, _c_int, _c_int, _vp]),
     "aao_cnn_backward": (_c_int, [_vp, _vp, _pdbl, _c_int, _c_int, _c_int, _vp, _vp, _pflt]),
     "aao_cnn_make_pairs": (_c_int, [_vp, _vp, _c_int, _c_int]),
     "aao_cnn_num_pairs": (_c_int, [_vp, _pint]),
@@ -227,6 +228,19 @@ class Solver:
         self._check(self.lib.aao_cnn_forward(self._h, self._fvec(x, B * 3 * H * W, "x"),
                                              la.ctypes.data_as(_pdbl), B, H, W,
                                              self._fvec(y, B * 2 * H * W, "y")))
+        return y
+
+    def cnn_forward_noalloc(self, x, lam, out=None):
+        """As cnn_forward, through the entry point that allocates nothing (its
+        workspace is the library's fixed per-GPU array); out: optional
+        preallocated float32 [B][2][H][W]."""
+        import torch
+        B, _, H, W = x.shape
+        y = torch.empty((B, 2, H, W), dtype=torch.float32, device=x.device) if out is None else out
+        la = self._lam(lam)
+        self._check(self.lib.aao_cnn_forward_noalloc(
+            self._h, self._fvec(x, B * 3 * H * W, "x"), la.ctypes.data_as(_pdbl), B, H, W,
+            self._fvec(y, B * 2 * H * W, "y")))
         return y
 
     def cnn_backward(self, x, lam, dy):

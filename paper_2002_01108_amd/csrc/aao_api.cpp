@@ -8,12 +8,45 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "common.h"
 
 using namespace aao;
+
+// Fixed device workspace of aao_cnn_forward_noalloc: one array per GPU, loaded
+// with the code object and held until the process ends, shared by every
+// context on that GPU.  Host code never passes the array's name to a kernel
+// (on the host it is only a stand-in for the symbol): it uses the device
+// address resolved once per device by noalloc_register().
+constexpr size_t kNoAllocFloats = (size_t)16 << 20;   // 64 MiB
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch[kMaxDevices] = {};
+
+// Resolve `scratch` on device `dev` (the current device) once.
+hipError_t noalloc_register(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[dev]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch[dev] = (float*)p;
+  return hipSuccess;
+}
+
+float* noalloc_base(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch[dev];
+}
+}  // namespace
 
 struct aao_ctx {
   Geometry g;
@@ -1080,6 +1113,11 @@ aao_status aao_setup(int dim, int m1, int m2, int m3, int n, double T, double ep
     delete c;
     return AAO_EHIP;
   }
+  if (noalloc_register(c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return AAO_EHIP;
+  }
   Geometry& g = c->g;
   g.dim = dim;
   g.m1 = m1;
@@ -1479,6 +1517,53 @@ aao_status aao_cnn_forward(aao_ctx* c, const float* x, const double* lam, int B,
   TRY(cnn_forward_run(c, B, H, W, false));
   HIPCHK(c, hipMemcpyAsync(y, n.Y, 2 * B * HW * sizeof(float), hipMemcpyDeviceToDevice,
                            c->stream));
+  return AAO_OK;
+}
+
+aao_status aao_cnn_forward_noalloc(aao_ctx* c, const float* x, const double* lam, int B, int H,
+                                   int W, float* y) {
+  if (!c || !x || !lam || !y || B < 1 || H < 1 || W < 1) return AAO_EINVAL;
+  if (!c->cnn.has_params) return fail(c, AAO_ESTATE, "no network parameters");
+  // workspace in the fixed device array, floats, each part 64-aligned:
+  // lambda as doubles [B][2], features [B][4], FiLM [4][B][C], hidden layers [B][C][H][W] x 2
+  const double pix = (double)B * H * W;
+  if (pix * 2 * kCnnC + 16.0 * B + 4.0 * B * kCnnC + 256 > (double)kNoAllocFloats)
+    return fail(c, AAO_EINVAL, "B*H*W too large for the 64 MiB fixed workspace (at most about "
+                               "1 M pixels in all)");
+  auto up = [](size_t v) { return (v + 63) / 64 * 64; };
+  const size_t HW = (size_t)H * W;
+  const size_t o_lam = 0, o_phi = up(4 * (size_t)B), o_gb = o_phi + up(4 * (size_t)B);
+  const size_t o_h1 = o_gb + up(4 * (size_t)B * kCnnC);
+  const size_t o_h2 = o_h1 + up((size_t)kCnnC * B * HW);
+  if (o_h2 + up((size_t)kCnnC * B * HW) > kNoAllocFloats)
+    return fail(c, AAO_EINVAL, "B*H*W too large for the 64 MiB fixed workspace");
+  for (int b = 0; b < B; ++b) {
+    const double re = lam[2 * b], im = lam[2 * b + 1];
+    if (!isfinite(re) || !isfinite(im) || (re == 0.0 && im == 0.0))
+      return fail(c, AAO_EINVAL, "lambda must be finite and non-zero");
+  }
+  float* base = noalloc_base(c->device);
+  if (!base) return fail(c, AAO_ESTATE, "fixed workspace not resolved on this device");
+  double* dlam = (double*)(base + o_lam);
+  float* phi = base + o_phi;
+  float* gb = base + o_gb;
+  float* h1 = base + o_h1;
+  float* h2 = base + o_h2;
+  auto& n = c->cnn;
+  hipStream_t s = c->stream;
+  // lambda is consumed before returning: the caller may reuse its host array
+  HIPCHK(c, hipMemcpyAsync(dlam, lam, 2 * (size_t)B * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  HIPCHK(c, cnn_features(dlam, phi, B, s));
+  HIPCHK(c, cnn_film_params(n.prm, phi, gb, B, s));
+  const float* gam1 = gb;
+  const float* bet1 = gb + B * kCnnC;
+  const float* gam2 = gb + 2 * B * kCnnC;
+  const float* bet2 = gb + 3 * B * kCnnC;
+  HIPCHK(c, cnn_conv_fwd(1, x, n.prm + kCnnOffW1, gam1, bet1, nullptr, nullptr, h1, B, H, W, s));
+  HIPCHK(c, cnn_conv_fwd(2, h1, n.prm + kCnnOffW2, gam2, bet2, nullptr, nullptr, h2, B, H, W, s));
+  HIPCHK(c, cnn_conv_fwd(3, h2, n.prm + kCnnOffW3, nullptr, nullptr, n.prm + kCnnOffB3, nullptr, y,
+                         B, H, W, s));
   return AAO_OK;
 }
 

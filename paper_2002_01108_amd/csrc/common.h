@@ -301,6 +301,8 @@ hipError_t cnn_film_bwd(const float* dh, const float* z, const float* h, const f
 hipError_t cnn_bias_grad(const float* dy, float* part, float* grad, int B, int H, int W,
                          hipStream_t s);
 hipError_t cnn_film_params(const float* prm, const float* phi, float* gb, int B, hipStream_t s);
+// phi[b] = (Re lambda_b, Im lambda_b, log|lambda_b|, 1) from lambda [B][2] (FP64, device)
+hipError_t cnn_features(const double* lam, float* phi, int B, hipStream_t s);
 hipError_t cnn_film_grad(const float* dfilm, const float* phi, float* grad, int B, int layer,
                          hipStream_t s);
 hipError_t cnn_resid_loss(const float* y, const float* rho, const float* rn, const float* phi,

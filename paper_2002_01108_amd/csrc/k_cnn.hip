@@ -256,6 +256,17 @@ __global__ void k_film_params(const float* __restrict__ prm, const float* __rest
   gb[idx] = (which == 0 || which == 2) ? 1.f + s : s;
 }
 
+// network features of each image's lambda_k: (Re, Im, log|lambda|, 1)
+__global__ void k_cnn_features(const double* __restrict__ lam, float* __restrict__ phi, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const double re = lam[2 * b], im = lam[2 * b + 1];
+  phi[4 * b] = (float)re;
+  phi[4 * b + 1] = (float)im;
+  phi[4 * b + 2] = (float)log(hypot(re, im));
+  phi[4 * b + 3] = 1.f;
+}
+
 // dG[c][f] = sum_b dgam[b][c] phi[b][f]; dfilm layout [B][2C] (gam sums then beta sums)
 __global__ void k_film_grad(const float* __restrict__ dfilm, const float* __restrict__ phi,
                             float* __restrict__ grad, int B, int C, int oG, int oH) {
@@ -613,6 +624,11 @@ hipError_t cnn_film_params(const float* prm, const float* phi, float* gb, int B,
   const int total = 4 * B * kCnnC;
   hipLaunchKernelGGL(k_film_params, dim3((total + 255) / 256), dim3(256), 0, s, prm, phi, gb, B,
                      kCnnC, kCnnOffG1, kCnnOffH1, kCnnOffG2, kCnnOffH2);
+  return hipGetLastError();
+}
+
+hipError_t cnn_features(const double* lam, float* phi, int B, hipStream_t s) {
+  hipLaunchKernelGGL(k_cnn_features, dim3((B + 255) / 256), dim3(256), 0, s, lam, phi, B);
   return hipGetLastError();
 }
 
