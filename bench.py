@@ -2,8 +2,14 @@
 """Benchmark of the BEC-preconditioned all-at-once heat solve on one MI355X.
 
 One step = assemble the all-at-once right-hand side from (f, u0) and solve
-L u = f by right-preconditioned FGMRES with P_eps to rel.res 1e-8 (FP64 unless
---precision says otherwise).  Inputs are seeded synthetic arrays already in
+L u = f by right-preconditioned FGMRES with P_eps to rel.res 1e-8.  The
+headline line is the largest configuration, heat3d 127^3 x 256 (524 M
+space-time unknowns), with the FP64 preconditioner (the paper's arithmetic);
+the FP32 and BF16x3 preconditioners on the same system, the 2D workloads
+(511^2 x 512 in all three precisions, 255^2 x 256), BDF2, the paper's Table 1
+set-up, the variable-coefficient learned/multigrid leg and the
+convection-diffusion stand-in follow as extra keys.  Every solve states its
+error against the FP64 oracle.  Inputs are seeded synthetic arrays already in
 HBM when the timed region starts.  Prints ONE JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
@@ -37,8 +43,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="heat2d_255x256")
-    ap.add_argument("--precision", default=None, help="fp64 | fp32 (default: the workload's)")
+    ap.add_argument("--workload", default="heat3d_127x256")
+    ap.add_argument("--precision", default="fp64", help="fp64 | fp32 | bf16x3")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--variants", default="fp32,bf16x3",
@@ -51,9 +57,11 @@ def parse():
                     help="skip the variable-coefficient learned/multigrid leg")
     ap.add_argument("--no-cd", action="store_true",
                     help="skip the convection-diffusion leg (Section 5, Example 3 stand-in)")
+    ap.add_argument("--no-2d", action="store_true",
+                    help="skip the heat2d 511^2 x 512 and 255^2 x 256 legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=64)
+    ap.add_argument("--cpu-sample-steps", type=int, default=32)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain-copy kernel used to calibrate PMC byte counters")
     return ap.parse_args()
@@ -221,76 +229,137 @@ def record(checks, rec, spec, u):
         checks.append((rec, spec, u.cpu().numpy()))
 
 
+def host_cpu():
+    """Cores this process may use and the CPU model (lscpu) of the host."""
+    import subprocess
+    info = {"nproc": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            key, _, val = line.partition(":")
+            if key.strip() in ("Model name", "Socket(s)", "Core(s) per socket",
+                               "Thread(s) per core", "CPU(s)", "CPU max MHz"):
+                info[key.strip()] = val.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+# CPU threads of one GPU's share of the host
+HOST_THREADS = 16
+
+
+def oracle_reference(spec, workers):
+    """The oracle's FP64 solution of the system a leg solved (sequential time
+    stepping: exact up to rounding)."""
+    import workloads as W
+    from oracle import bdf, cd, heat
+    kind, name = spec
+    v = W.WORKLOADS[name]
+    fv, u0v, faces = W.make(v)
+    if kind == "heat":
+        p = heat.Problem(v.m1, v.dim, v.n, T=v.T, eps=v.epsilon)
+        # constant coefficient: each step solved in the sine basis (pinned against
+        # the sparse-LU stepping)
+        return heat.sequential_be_sine((v.m1,) * v.dim, p.tau, p.rhs(fv, u0v), workers)
+    if kind == "heat_bdf2":
+        p = bdf.Problem(v.m1, v.dim, v.n, r=bdf.BDF2, T=v.T, eps=v.epsilon)
+        return p.exact(p.rhs(fv, u0v))
+    if kind == "heat_faces":
+        p = heat.Problem(v.m1, v.dim, v.n, T=v.T, eps=v.epsilon, faces=faces)
+        return p.exact(p.rhs(fv, u0v))
+    if kind == "cd":
+        p = cd.Problem(v.m1, v.n, T=v.T, eps=v.epsilon)
+        return p.exact(p.rhs())
+    raise ValueError(kind)
+
+
 def cpu_baseline_leg(w, f, u0, sample_steps, checks, timed=True):
     """The one place this benchmark runs the CPU oracle.
 
-    (a) timed = True: the oracle's GMRES-BEC on the first `sample_steps` time
-        levels of the main workload (same grid, tau, eps, source and u0), one
-        BLAS thread: the `cpu_baseline` record.
-    (b) `checks`: (record, spec, u) triples left by the GPU legs; for each spec
-        the oracle's FP64 solution of the same system (sequential time
-        stepping, exact up to rounding) is computed once and the GPU solution's
-        relative error against it is written into the record as
-        `rel_err_vs_oracle`.  Specs: ("heat", name), ("heat_bdf2", name),
-        ("heat_faces", name), ("cd", name)."""
+    (a) `checks`: (record, spec, u) triples left by the GPU legs; for each spec
+        the oracle's FP64 solution of the same system is computed once and the
+        GPU solution's relative error against it (2-norm, and max-abs
+        normalised by max |reference|) goes into the record.
+    (b) timed = True: the `cpu_baseline` record, the oracle as it stands on
+        this host's cores, once on 1 thread and once on the GPU's share of the
+        host (HOST_THREADS), on bounded samples:
+          * sequential backward Euler (the exact solve; 3D: each step in the
+            sine basis) on the first `sample_steps` time levels of the main
+            workload (same grid, tau, source): the reported value;
+          * the oracle's GMRES-BEC (naive DFT + sparse LU per frequency,
+            factorisations included) to rel.res 1e-8 on the first 64 time levels
+            of heat2d 255^2 x 256 (3D grids are beyond its sparse LU)."""
     import workloads as W
-    from oracle import bdf, cd, heat
+    from oracle import heat
+    from threadpoolctl import threadpool_limits
+    cpu = host_cpu()
+    threads = max(1, min(HOST_THREADS, cpu["nproc"]))
     refs = {}
-
-    def reference(spec):
-        kind, name = spec
-        v = W.WORKLOADS[name]
-        fv, u0v, faces = W.make(v)
-        if kind == "heat":
-            p = heat.Problem(v.m1, v.dim, v.n, T=v.T, eps=v.epsilon)
-            return p.exact(p.rhs(fv, u0v))
-        if kind == "heat_bdf2":
-            p = bdf.Problem(v.m1, v.dim, v.n, r=bdf.BDF2, T=v.T, eps=v.epsilon)
-            return p.exact(p.rhs(fv, u0v))
-        if kind == "heat_faces":
-            p = heat.Problem(v.m1, v.dim, v.n, T=v.T, eps=v.epsilon, faces=faces)
-            return p.exact(p.rhs(fv, u0v))
-        if kind == "cd":
-            p = cd.Problem(v.m1, v.n, T=v.T, eps=v.epsilon)
-            return p.exact(p.rhs())
-        raise ValueError(kind)
-
     for rec, spec, u in checks:
         if spec not in refs:
-            refs[spec] = reference(spec)
+            with threadpool_limits(limits=threads):
+                refs[spec] = oracle_reference(spec, threads)
         ex = refs[spec]
         rec["rel_err_vs_oracle"] = float(np.linalg.norm(u - ex) / np.linalg.norm(ex))
+        rec["maxabs_err_vs_oracle"] = float(np.abs(u - ex).max() / np.abs(ex).max())
+    refs.clear()
     if not timed:
         return None
-    from threadpoolctl import threadpool_limits
+    rows = []
     ns = min(sample_steps, w.n)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        p = heat.Problem(w.m1, w.dim, ns, T=w.tau * ns, eps=w.epsilon)
-        rhs = p.rhs(f[:ns], u0)
-        x, it, hist = p.gmres(rhs, tol=1e-8)
-        dt = time.perf_counter() - t0
-    dof = ns * w.m
-    return {"value": dof / dt, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
-            "sample": f"{w.name}: first {ns} of {w.n} time steps (same grid, tau, eps, "
-                      f"source, u0), oracle GMRES-BEC (naive DFT + sparse LU per frequency, "
-                      f"factorisations included) to rel.res 1e-8, {it} iterations, "
-                      f"{dt:.1f} s"}
+    for nt in (1, threads):
+        with threadpool_limits(limits=nt):
+            t0 = time.perf_counter()
+            p = heat.Problem(w.m1, w.dim, ns, T=w.tau * ns, eps=w.epsilon)
+            x = p.exact(p.rhs(f[:ns], u0), workers=nt)
+            dt = time.perf_counter() - t0
+        del x
+        rows.append({"kind": "sequential backward Euler", "workload": w.name,
+                     "sample": f"first {ns} of {w.n} time steps", "threads": nt,
+                     "seconds": dt, "unknowns_per_s": ns * w.m / dt})
+    w2 = W.WORKLOADS["heat2d_255x256"]
+    f2, u02, _ = W.make(w2)
+    n2 = min(64, w2.n)
+    for nt in (1, threads):
+        with threadpool_limits(limits=nt):
+            t0 = time.perf_counter()
+            p = heat.Problem(w2.m1, w2.dim, n2, T=w2.tau * n2, eps=w2.epsilon)
+            x, it, _ = p.gmres(p.rhs(f2[:n2], u02), tol=1e-8)
+            dt = time.perf_counter() - t0
+        rows.append({"kind": "GMRES-BEC (naive DFT + sparse LU per frequency)",
+                     "workload": w2.name, "sample": f"first {n2} of {w2.n} time steps",
+                     "threads": nt, "iterations": it, "seconds": dt,
+                     "unknowns_per_s": n2 * w2.m / dt})
+    best = rows[1]
+    return {"value": best["unknowns_per_s"], "unit": "unknowns/s", "cores": best["threads"],
+            "kind": "oracle",
+            "sample": f"{w.name}: oracle sequential backward Euler (exact solve, each step in "
+                      f"the sine basis) on the first {ns} of {w.n} time steps (same grid, tau, "
+                      f"source), {best['threads']} threads, {best['seconds']:.1f} s",
+            "rows": rows, "host": cpu}
 
 
-def bdf2_leg(w, fd, u0d, tol, restart, steps, checks):
-    """The same workload with BDF2 in time (backward-Euler first step): FP64
-    solve to the same tolerance; its solution goes to `checks` for the error
-    against the oracle's sequential BDF2 solution."""
+def bdf2_leg(tol, steps, checks):
+    """heat2d 255^2 x 256 with BDF2 in time (backward-Euler first step): FP64
+    solve; its solution goes to `checks` for the error against the oracle's
+    sequential BDF2 solution."""
     import torch
+    import workloads as W
     from paper_2002_01108_amd import Solver
+    w = W.WORKLOADS["heat2d_255x256"]
+    f, u0, _ = W.make(w)
+    fd, u0d = torch.from_numpy(f).cuda(), torch.from_numpy(u0).cuda()
     s = Solver(w.dim, w.m1, w.n, T=w.T, eps=w.epsilon, precision="fp64")
     s.set_scheme(2)
-    t, info, _, u, _ = time_solver(s, fd, u0d, tol, restart, steps, 1, [])
-    rec = {"value": w.dof / t, "ms_per_step": t * 1e3, "gmres_iters": info["iters"],
-           "rel_res": info["final_res"], "eps": w.epsilon}
+    t, info, _, u, _ = time_solver(s, fd, u0d, tol, 50, steps, 1, [])
+    rec = {"workload": w.name, "value": w.dof / t, "ms_per_step": t * 1e3,
+           "gmres_iters": info["iters"], "rel_res": info["final_res"], "tol": tol,
+           "res_hist": info["hist"], "eps": w.epsilon}
     record(checks, rec, ("heat_bdf2", w.name), u)
-    torch.cuda.synchronize()
+    s.close()
+    del u, fd, u0d
+    torch.cuda.empty_cache()
     return rec
 
 
@@ -358,7 +427,7 @@ def table1_leg(steps):
 TABLE3_PRINTED = {"bec": (5, 45.13, 1.09e-8), "bc": (22, 160.84, 7.56e-8)}
 
 
-def cd_leg(steps, checks):
+def cd_leg(steps, checks, fgmres_tol=1e-8):
     """Convection-diffusion stand-in for Section 5, Example 3 (cd2d_255x256:
     J+1 = 256, N = 256, circulating wind, hot wall, upwind differences, V-cycle
     inner solves).  One step = boundary load + right-hand side + solve.
@@ -377,7 +446,7 @@ def cd_leg(steps, checks):
            "discretisation": "five-point upwind differences on (-1, 1)^2 (Q1 + SUPG in the paper)"}
     runs = (("bec_left", w.epsilon, "left", 1e-7, 3), ("bc_left", 1.0, "left", 1e-7, 3),
             ("bec_left_1vcycle", w.epsilon, "left", 1e-7, 1),
-            ("bec_fgmres", w.epsilon, "right", 1e-8, 3))
+            ("bec_fgmres", w.epsilon, "right", fgmres_tol, 3))
     for name, eps, side, tol, cycles in runs:
         s = Solver(2, w.m1, w.n, T=w.T, eps=eps, precision="fp64")
         s.set_convection(W.CD_NU / 4.0, (w1 / 2.0, w2 / 2.0))   # (-1, 1)^2 -> unit square
@@ -400,7 +469,7 @@ def cd_leg(steps, checks):
         dt = (time.perf_counter() - t0) / steps
         rec = {"eps": eps, "side": side, "tol": tol, "vcycles": cycles,
                "gmres_iters": info["iters"], "ms_per_step": dt * 1e3,
-               "rel_res": info["final_res"], "value": w.dof / dt}
+               "rel_res": info["final_res"], "res_hist": info["hist"], "value": w.dof / dt}
         if name in ("bec_left", "bc_left"):
             it, cpu_s, res = TABLE3_PRINTED[name[:-5]]
             rec["paper"] = {"iters": it, "cpu_s": cpu_s, "rel_res": res}
@@ -455,9 +524,74 @@ def learned_leg(tol, steps, checks, train_fields=4, train_steps=1500, batch=8):
             s.set_inner(inner)
         t, info, _, u, _ = time_solver(s, fd, u0d, tol, 50, steps, 1, [])
         rec = {"value": w.dof / t, "ms_per_step": t * 1e3, "gmres_iters": info["iters"],
-               "rel_res": info["final_res"]}
+               "rel_res": info["final_res"], "tol": tol, "res_hist": info["hist"]}
         record(checks, rec, ("heat_faces", w.name), u)
         out[inner] = rec
+    return out
+
+
+def dst_roofline(w, prec, prof):
+    """Roofline record of the DST-I class (the dominant kernel class of the
+    solve).  Its algorithmic work is what the method must move: one read and
+    one write of the spectrum per launch (16 B per unknown in FP64, valid points
+    only).  The method's own flop count for Step 2 (a fast sine transform,
+    at most about 62 flop per unknown and pass) is 3.9 flop/B, below the FP64
+    ridge of 78.6 TFLOP/s / 8 TB/s = 9.8 flop/B, so HBM bandwidth is the bound.
+    The folded dense products the kernels actually execute are reported beside
+    it (executed flops, matrix-core rate), not as the roofline."""
+    dst_ms, dst_n = prof["dst"]
+    avg_s = dst_ms / 1e3 / max(dst_n, 1)
+    path = dst_path(w, prec)
+    nbytes = class_bytes(w, prec)["dst"]
+    ex_flops = dst_flops_per_launch(w, prec)
+    peak_fl = {"fp64": PEAKS["fp64_TFs"], "fp32": PEAKS["fp32_TFs"],
+               "bf16x3": PEAKS["bf16_TFs"]}[prec]
+    traffic = measured_traffic("k_fold.hip", w.name, prec, path) if path != "dense" else None
+    launches, products = dst_launch_mix(w, prec)
+    mix = (f"{products} DST-I mode products in {launches} launches per P^-1"
+           + (", the last axis' forward, divide and inverse fused" if launches < products else ""))
+    achieved = nbytes / avg_s / 1e9 if dst_n else None
+    return {"kernel": f"dst_{path}_{prec} ({mix})",
+            "bound": "hbm", "achieved": achieved, "peak": PEAKS["hbm_GBs"], "unit": "GB/s",
+            "frac": achieved / PEAKS["hbm_GBs"] if achieved else None, "traffic": traffic,
+            "avg_launch_us": avg_s * 1e6, "launches": dst_n,
+            "algorithmic_bytes_per_launch": nbytes,
+            "executed_flops_per_launch": ex_flops,
+            "executed_TFLOPs": ex_flops / avg_s / 1e12 if dst_n else None,
+            "executed_frac_of_matrix_peak": ex_flops / avg_s / 1e12 / peak_fl if dst_n else None}
+
+
+PROF_CLASSES = ["dst", "time_fwd", "time_inv", "apply_L", "divide", "krylov"]
+
+
+def heat_leg(name, precisions, tol, steps, checks, restart=50):
+    """Constant-coefficient workload `name` solved with each preconditioner
+    precision in turn (FP64 FGMRES outside): time per step, iterations, the
+    residual history and a per-class kernel table; solutions go to `checks`."""
+    import torch
+    import workloads as W
+    from paper_2002_01108_amd import Solver
+    w = W.WORKLOADS[name]
+    f, u0, _ = W.make(w)
+    fd, u0d = torch.from_numpy(f).cuda(), torch.from_numpy(u0).cuda()
+    del f
+    restart = restart if w.dim < 3 else min(restart, 10)
+    s = Solver(w.dim, w.m1, w.n, T=w.T, eps=w.epsilon, precision=precisions[0])
+    out = {"workload": w.name, "dof": w.dof, "eps": w.epsilon, "tol": tol, "restart": restart}
+    for prec in precisions:
+        s.set_precision(prec)
+        t, info, prof, u, _ = time_solver(s, fd, u0d, tol, restart, steps, 1, PROF_CLASSES)
+        rec = {"value": w.dof / t, "ms_per_step": t * 1e3, "gmres_iters": info["iters"],
+               "rel_res": info["final_res"], "res_hist": info["hist"],
+               "kernels": kernel_table(w, prec, prof)}
+        record(checks, rec, ("heat", w.name), u)
+        out[prec] = rec
+        print(f"[{w.name}] {prec}: {info['iters']} iterations, {t * 1e3:.2f} ms",
+              file=sys.stderr, flush=True)
+        del u
+    s.close()
+    del fd, u0d
+    torch.cuda.empty_cache()
     return out
 
 
@@ -475,53 +609,21 @@ def main():
     from paper_2002_01108_amd import Solver
 
     w = W.WORKLOADS[args.workload]
-    prec = args.precision or w.precision
+    prec = args.precision
     if w.coefficient != "const":
         raise SystemExit("variable-coefficient workloads are benchmarked separately")
     f, u0, _ = W.make(w)
     fd = torch.from_numpy(f).cuda()
     u0d = torch.from_numpy(u0).cuda()
     restart = args.restart if w.dim < 3 else min(args.restart, 10)
+    print(f"[main] {w.name} {prec}: {w.dof} unknowns", file=sys.stderr, flush=True)
 
     s = Solver(w.dim, w.m1, w.n, T=w.T, eps=w.epsilon, precision=prec)
     t_step, info, prof, u, rhs = time_solver(s, fd, u0d, args.tol, restart, args.steps,
-                                             args.warmup, ["dst", "time_fwd", "time_inv",
-                                                           "apply_L", "divide", "krylov"])
+                                             args.warmup, PROF_CLASSES)
     dof = w.dof
-    value = dof / t_step
-
-    dst_ms, dst_n = prof["dst"]
-    path = dst_path(w, prec)
-    folded = path != "dense"
-    flops = dst_flops_per_launch(w, prec)
-    nbytes = class_bytes(w, prec)["dst"]
-    avg_s = dst_ms / 1e3 / max(dst_n, 1)
-    peak_fl = {"fp64": PEAKS["fp64_TFs"], "fp32": PEAKS["fp32_TFs"],
-               "bf16x3": PEAKS["bf16_TFs"]}[prec]
-    # the binding roofline is the one whose ideal time is longer
-    t_mfma = flops / (peak_fl * 1e12)
-    t_hbm = nbytes / (PEAKS["hbm_GBs"] * 1e9)
-    traffic = measured_traffic("k_fold.hip", w.name, prec, path) if folded else None
-    if t_hbm >= t_mfma:
-        achieved = nbytes / avg_s / 1e9 if dst_n else None
-        bound, peak, unit = "hbm", PEAKS["hbm_GBs"], "GB/s"
-    else:
-        achieved = flops / avg_s / 1e12 if dst_n else None
-        bound, peak, unit = "mfma", peak_fl, "TFLOP/s"
-    launches, products = dst_launch_mix(w, prec)
-    mix = (f"{products} DST-I mode products in {launches} launches per P^-1"
-           + (", the last axis' forward, divide and inverse fused" if launches < products else ""))
-    roofline = {"kernel": f"dst_{path}_{prec} ({mix})",
-                "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak if achieved else None, "traffic": traffic,
-                "avg_launch_us": avg_s * 1e6, "launches": dst_n,
-                "flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
-                "mfma_TFLOPs": flops / avg_s / 1e12 if dst_n else None,
-                "mfma_frac": flops / avg_s / 1e12 / peak_fl if dst_n else None,
-                "hbm_GBps": nbytes / avg_s / 1e9 if dst_n else None}
-
     out = {
-        "metric": METRIC, "value": value, "unit": "unknowns/s", "n_gpus": 1,
+        "metric": METRIC, "value": dof / t_step, "unit": "unknowns/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_step * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == "fp64" else f"f64 outer / {prec} preconditioner",
@@ -529,10 +631,12 @@ def main():
         "config": {"workload": w.name, "dim": w.dim, "m1": w.m1, "n": w.n, "T": w.T,
                    "eps": w.epsilon, "tol": args.tol, "precision": prec,
                    "restart": restart, "dof": dof},
-        "gmres_iters": info["iters"], "rel_res": info["final_res"],
-        "roofline": roofline,
+        "gmres_iters": info["iters"], "rel_res": info["final_res"], "res_hist": info["hist"],
+        "roofline": dst_roofline(w, prec, prof),
         "kernels": kernel_table(w, prec, prof),
     }
+    print(f"[main] {info['iters']} iterations, {t_step * 1e3:.2f} ms", file=sys.stderr,
+          flush=True)
     # inside the solve the stencil runs fused with the Arnoldi projection (and
     # the final residual norm); its plain form is timed here on the same array
     s.profile(["apply_L"])
@@ -544,10 +648,12 @@ def main():
                            if k == "apply_L"})
     out["kernels"]["apply_L"]["note"] = "standalone aao_apply_A, 20 calls on the workload's rhs"
     s.profile(None)
+    del tmpv
 
     # (record, oracle spec, GPU solution) for the cpu_baseline leg
     checks = None if args.no_oracle_check else []
     record(checks, out, ("heat", w.name), u)
+    del u
 
     variants = {}
     for vp in [v for v in args.variants.split(",") if v and v != prec]:
@@ -556,24 +662,38 @@ def main():
         except Exception as e:     # precision not available in the library
             variants[vp] = {"error": str(e)}
             continue
-        tv, iv, _, uv, _ = time_solver(s, fd, u0d, args.tol, restart, max(1, args.steps // 2),
-                                       1, [])
+        tv, iv, pv, uv, _ = time_solver(s, fd, u0d, args.tol, restart, max(1, args.steps // 2),
+                                        1, PROF_CLASSES)
         rec = {"value": dof / tv, "ms_per_step": tv * 1e3, "gmres_iters": iv["iters"],
-               "rel_res": iv["final_res"]}
+               "rel_res": iv["final_res"], "res_hist": iv["hist"],
+               "kernels": kernel_table(w, vp, pv)}
         record(checks, rec, ("heat", w.name), uv)
         variants[vp] = rec
+        print(f"[main] variant {vp}: {iv['iters']} iterations, {tv * 1e3:.2f} ms",
+              file=sys.stderr, flush=True)
+        del uv
     if variants:
         out["variants"] = variants
+    s.close()
+    del fd, u0d, rhs
+    torch.cuda.empty_cache()
+
+    half = max(1, args.steps // 2)
+    if not args.no_2d:
+        for name in ("heat2d_511x512", "heat2d_255x256"):
+            if name != w.name:
+                out[name] = heat_leg(name, ["fp64", "fp32", "bf16x3"], args.tol, half, checks)
+    # the legs below run at tol/10: their systems are worse conditioned or their
+    # schemes less accurate per residual, and RES 1e-9 keeps each error against
+    # the oracle at the 1e-8 level the comparison is made at
     if not args.no_bdf2:
-        out["bdf2"] = bdf2_leg(w, fd, u0d, args.tol, restart, max(1, args.steps // 2), checks)
+        out["bdf2"] = bdf2_leg(args.tol / 10, half, checks)
     if not args.no_table1:
-        out["table1"] = table1_leg(max(1, args.steps // 2))
+        out["table1"] = table1_leg(half)
     if not args.no_learned:
-        # the variable-coefficient system is worse conditioned: RES 1e-9 keeps the
-        # error against the oracle at the 1e-8 level the comparison is made at
-        out["learned"] = learned_leg(args.tol / 10, max(1, args.steps // 2), checks)
+        out["learned"] = learned_leg(args.tol / 10, half, checks)
     if not args.no_cd:
-        out["cd"] = cd_leg(max(1, args.steps // 2), checks)
+        out["cd"] = cd_leg(half, checks, fgmres_tol=args.tol / 10)
 
     cpu = cpu_baseline_leg(w, f, u0, args.cpu_sample_steps, checks or [],
                            timed=not args.no_cpu_baseline)
