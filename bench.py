@@ -47,8 +47,10 @@ def parse():
     ap.add_argument("--precision", default="fp64", help="fp64 | fp32 | bf16x3")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--restart", type=int, default=50)
-    ap.add_argument("--variants", default="fp32,bf16x3",
-                    help="comma list of extra preconditioner precisions to time")
+    ap.add_argument("--variants", default="fp32,bf16x3,fp32_first,bf16x3_first",
+                    help="comma list of extra preconditioners to time: a precision, or "
+                         "<precision>_first (that precision for the first Arnoldi step, the "
+                         "workload's precision after it)")
     ap.add_argument("--no-bdf2", action="store_true",
                     help="skip the BDF2 solve on the same workload")
     ap.add_argument("--no-table1", action="store_true",
@@ -564,6 +566,18 @@ def dst_roofline(w, prec, prof):
 PROF_CLASSES = ["dst", "time_fwd", "time_inv", "apply_L", "divide", "krylov"]
 
 
+def set_variant(s, name, base="fp64"):
+    """Preconditioner variant `name`: a precision ("fp64", "fp32", "bf16x3"), or
+    "<precision>_first": that precision for the first Arnoldi step of each solve
+    and `base` after it (aao_set_precision_schedule)."""
+    if name.endswith("_first"):
+        s.set_precision(base)
+        s.set_precision_schedule(name[: -len("_first")], 1)
+    else:
+        s.set_precision_schedule("fp64", 0)
+        s.set_precision(name)
+
+
 def heat_leg(name, precisions, tol, steps, checks, restart=50):
     """Constant-coefficient workload `name` solved with each preconditioner
     precision in turn (FP64 FGMRES outside): time per step, iterations, the
@@ -576,14 +590,14 @@ def heat_leg(name, precisions, tol, steps, checks, restart=50):
     fd, u0d = torch.from_numpy(f).cuda(), torch.from_numpy(u0).cuda()
     del f
     restart = restart if w.dim < 3 else min(restart, 10)
-    s = Solver(w.dim, w.m1, w.n, T=w.T, eps=w.epsilon, precision=precisions[0])
+    s = Solver(w.dim, w.m1, w.n, T=w.T, eps=w.epsilon, precision="fp64")
     out = {"workload": w.name, "dof": w.dof, "eps": w.epsilon, "tol": tol, "restart": restart}
     for prec in precisions:
-        s.set_precision(prec)
+        set_variant(s, prec)
         t, info, prof, u, _ = time_solver(s, fd, u0d, tol, restart, steps, 1, PROF_CLASSES)
         rec = {"value": w.dof / t, "ms_per_step": t * 1e3, "gmres_iters": info["iters"],
                "rel_res": info["final_res"], "res_hist": info["hist"],
-               "kernels": kernel_table(w, prec, prof)}
+               "kernels": kernel_table(w, prec.split("_")[0], prof)}
         record(checks, rec, ("heat", w.name), u)
         out[prec] = rec
         print(f"[{w.name}] {prec}: {info['iters']} iterations, {t * 1e3:.2f} ms",
@@ -658,15 +672,15 @@ def main():
     variants = {}
     for vp in [v for v in args.variants.split(",") if v and v != prec]:
         try:
-            s.set_precision(vp)
-        except Exception as e:     # precision not available in the library
+            set_variant(s, vp, base=prec)
+        except Exception as e:     # variant not available in the library
             variants[vp] = {"error": str(e)}
             continue
         tv, iv, pv, uv, _ = time_solver(s, fd, u0d, args.tol, restart, max(1, args.steps // 2),
                                         1, PROF_CLASSES)
         rec = {"value": dof / tv, "ms_per_step": tv * 1e3, "gmres_iters": iv["iters"],
                "rel_res": iv["final_res"], "res_hist": iv["hist"],
-               "kernels": kernel_table(w, vp, pv)}
+               "kernels": kernel_table(w, vp.split("_")[0], pv)}
         record(checks, rec, ("heat", w.name), uv)
         variants[vp] = rec
         print(f"[main] variant {vp}: {iv['iters']} iterations, {tv * 1e3:.2f} ms",
@@ -682,7 +696,8 @@ def main():
     if not args.no_2d:
         for name in ("heat2d_511x512", "heat2d_255x256"):
             if name != w.name:
-                out[name] = heat_leg(name, ["fp64", "fp32", "bf16x3"], args.tol, half, checks)
+                out[name] = heat_leg(name, ["fp64", "fp32", "bf16x3", "fp32_first",
+                                            "bf16x3_first"], args.tol, half, checks)
     # the legs below run at tol/10: their systems are worse conditioned or their
     # schemes less accurate per residual, and RES 1e-9 keeps each error against
     # the oracle at the 1e-8 level the comparison is made at

@@ -79,6 +79,21 @@ aao_status aao_set_stream(aao_ctx *ctx, void *hip_stream);
  * differently sized spectrum workspace. */
 aao_status aao_set_precision(aao_ctx *ctx, aao_precision p);
 
+/* Precision schedule of aao_solve.  Flexible GMRES admits a different
+ * preconditioner at every step, so the first `steps` Arnoldi steps of each
+ * solve may apply P_eps^{-1} in `first` (typically AAO_FP32: its first step
+ * leaves about the residual the FP64 preconditioner leaves, since that
+ * residual is set by the method, not by rounding) and the later steps in the
+ * context's precision (typically AAO_FP64, whose accuracy the last steps need:
+ * rounding after the shifted divide is white in space, and L amplifies it by
+ * up to 1 + 4 d tau / h^2).  steps = 0 (default) applies the context's
+ * precision throughout; aao_apply_Pinv and aao_step1-3 always use it.
+ * Needs right preconditioning and the exact sine-transform inner solve of a
+ * constant coefficient (aao_solve returns AAO_ESTATE otherwise).  The spectrum
+ * workspace is sized for the larger of the two precisions.
+ * AAO_EINVAL for an unknown precision or steps < 0. */
+aao_status aao_set_precision_schedule(aao_ctx *ctx, aao_precision first, int steps);
+
 /* Variable coefficient a(x) of -div(a grad u) (Section 2, eq. (heateq)), given
  * on cell faces as HOST arrays (copied; the caller keeps ownership):
  *   1D: ax[m1+1];  2D: ax[m2][m1+1], ay[m2+1][m1];

@@ -30,6 +30,7 @@ SIGNATURES = {
     "aao_destroy": (None, [_vp]),
     "aao_set_stream": (_c_int, [_vp, _vp]),
     "aao_set_precision": (_c_int, [_vp, _c_int]),
+    "aao_set_precision_schedule": (_c_int, [_vp, _c_int, _c_int]),
     "aao_build_rhs": (_c_int, [_vp, _vp, _vp, _vp]),
     "aao_apply_A": (_c_int, [_vp, _vp, _vp]),
     "aao_apply_Pinv": (_c_int, [_vp, _vp, _vp]),
@@ -151,6 +152,12 @@ class Solver:
     def set_precision(self, precision: str):
         self.precision = precision
         self._check(self.lib.aao_set_precision(self._h, PRECISIONS[precision]))
+
+    def set_precision_schedule(self, first: str = "fp32", steps: int = 1):
+        """The first `steps` Arnoldi steps of each solve apply P^{-1} in `first`,
+        the later ones in the context's precision (include/aao.h); steps = 0
+        switches the schedule off."""
+        self._check(self.lib.aao_set_precision_schedule(self._h, PRECISIONS[first], int(steps)))
 
     def set_coefficient(self, faces=None):
         """Face coefficients (host numpy arrays, see include/aao.h); None: a = 1."""

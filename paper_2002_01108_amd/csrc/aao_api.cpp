@@ -55,6 +55,10 @@ struct aao_ctx {
   double cst[3] = {0, 0, 0};     // tau / h_d^2
   hipStream_t stream = nullptr;
   aao_precision prec = AAO_FP64;
+  // precision schedule of aao_solve: the first sched_steps Arnoldi steps of a
+  // solve apply P^{-1} in sched_prec (aao_set_precision_schedule)
+  aao_precision sched_prec = AAO_FP64;
+  int sched_steps = 0;
   int device = 0;
 
   // device tables (FP64 and FP32 copies)
@@ -297,8 +301,13 @@ float bf16_value_host(uint16_t h) {
 
 size_t spec_elems(const Geometry& g) { return (size_t)g.nh * 2 * (size_t)g.PS; }
 
+size_t prec_bytes(aao_precision p) { return p == AAO_FP64 ? 8 : 4; }
+
+// Spectrum workspace for the context's precision, and for the scheduled one
+// when a precision schedule is set (the larger of the two element sizes).
 aao_status ensure_spec(aao_ctx* c) {
-  const size_t esz = (c->prec == AAO_FP64) ? 8 : 4;
+  size_t esz = prec_bytes(c->prec);
+  if (c->sched_steps > 0) esz = std::max(esz, prec_bytes(c->sched_prec));
   const size_t bytes = spec_elems(c->g) * esz;
   if (bytes == c->spec_bytes && c->specA) return AAO_OK;
   dfree(c, c->specA);
@@ -1254,6 +1263,19 @@ aao_status aao_set_precision(aao_ctx* ctx, aao_precision p) {
   return ensure_spec(ctx);
 }
 
+aao_status aao_set_precision_schedule(aao_ctx* c, aao_precision first, int steps) {
+  if (!c) return AAO_EINVAL;
+  if (first != AAO_FP64 && first != AAO_FP32 && first != AAO_BF16X3)
+    return fail(c, AAO_EINVAL, "unsupported precision");
+  if (steps < 0 || steps > 100000) return fail(c, AAO_EINVAL, "schedule length out of range");
+  if (c->g.q1 && first == AAO_BF16X3 && steps > 0)
+    return fail(c, AAO_ESTATE, "Q1 elements need the FP64/FP32 DST preconditioner");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->sched_prec = first;
+  c->sched_steps = steps;
+  return ensure_spec(c);
+}
+
 aao_status aao_set_coefficient(aao_ctx* c, const double* ax, const double* ay,
                                const double* az) {
   if (!c) return AAO_EINVAL;
@@ -1414,7 +1436,8 @@ aao_status aao_set_discretisation(aao_ctx* c, aao_discretisation disc) {
     if (g.dim != 2 || g.m1 != g.m2)
       return fail(c, AAO_EINVAL, "Q1 elements need a square 2D grid");
     if (c->var) return fail(c, AAO_ESTATE, "Q1 elements need a constant coefficient");
-    if (c->prec == AAO_BF16X3 || c->inner != AAO_INNER_DST)
+    if (c->prec == AAO_BF16X3 || c->inner != AAO_INNER_DST ||
+        (c->sched_steps > 0 && c->sched_prec == AAO_BF16X3))
       return fail(c, AAO_ESTATE, "Q1 elements need the FP64/FP32 DST preconditioner");
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1871,6 +1894,11 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
   }
   if (iters) *iters = 0;
   if (hist_len) *hist_len = 0;
+  const bool sched = c->sched_steps > 0 && c->sched_prec != c->prec;
+  if (sched && (c->side != AAO_RIGHT || c->inner != AAO_INNER_DST || c->var))
+    return fail(c, AAO_ESTATE,
+                "a precision schedule needs right preconditioning and the exact sine-transform "
+                "inner solve");
   TRY(ensure_krylov(c, restart));
   const int R = restart;
   // small scratch (doubles): [0] norm, [1..R+1] c1, [R+2..2R+2] c2, [2R+3] norm2,
@@ -2033,6 +2061,15 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
       if (left) {
         TRY(apply_L(c, wj, c->tmp));
         TRY(apply_pinv(c, c->tmp, w));
+      } else if (sched && total < c->sched_steps) {
+        // flexible GMRES takes a different preconditioner per step: the first
+        // steps in the scheduled (reduced) precision, the later ones in the
+        // context's
+        const aao_precision keep = c->prec;
+        c->prec = c->sched_prec;
+        const aao_status st = apply_pinv(c, wj, zj);
+        c->prec = keep;
+        TRY(st);
       } else {
         TRY(apply_pinv(c, wj, zj));
       }

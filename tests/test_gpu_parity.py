@@ -49,6 +49,7 @@ GRIDS = [  # (dim, m1, n, eps): ragged tiles, several tiles, every FFT length cl
     (2, 127, 32, 0.15),
     (3, 13, 16, 0.25),
     (3, 20, 64, 0.125),
+    (3, 9, 2, 0.3),       # fewer time levels than one chunk
 ]
 
 
@@ -63,6 +64,23 @@ def test_apply_A(dim, m1, n, eps):
     s = solver(dim, m1, n, eps)
     y = host(s.apply_A(dev(x)))
     assert rel(y, p.L(x)) <= 1e-12
+
+
+@pytest.mark.parametrize("m1,n,two", [(70, 8, False), (70, 8, True), (130, 2, False),
+                                      (67, 16, True)])
+def test_apply_A_3d_walk(m1, n, two):
+    """3D L v (backward Euler, and BDF2's three-term rows) across several z
+    ranges of the z-marching walk (64 planes each, ragged last range) and time
+    chunks, including fewer levels than one chunk."""
+    from oracle import bdf
+    x = _rand((n, m1 ** 3), 31)
+    s = solver(3, m1, n, 0.2)
+    if two:
+        s.set_scheme(2)
+        want = bdf.Problem(m1, 3, n, r=bdf.BDF2, eps=0.2).L(x)
+    else:
+        want = heat.Problem(m1, 3, n, eps=0.2).L(x)
+    assert rel(host(s.apply_A(dev(x))), want) <= 1e-12
 
 
 @pytest.mark.parametrize("dim,m1,n,eps", GRIDS)
@@ -179,7 +197,7 @@ def test_solve_metric_run_c1():
     np.testing.assert_allclose(info["hist"], hist_or, rtol=1e-6)
 
 
-@pytest.mark.parametrize("dim,m1,n", [(2, 100, 32), (3, 20, 16), (2, 65, 512)])
+@pytest.mark.parametrize("dim,m1,n", [(2, 100, 32), (3, 20, 16), (2, 65, 512), (3, 70, 8)])
 def test_solve_grids(dim, m1, n):
     p = heat.Problem(m1, dim, n)
     f = _rand((n, p.m), 8)
@@ -299,6 +317,7 @@ RECT = [  # (dim, (m1, m2[, m3]), n, eps)
     (2, (64, 127), 8, 0.1),
     (3, (13, 9, 5), 8, 0.25),
     (3, (65, 20, 33), 4, 0.2),
+    (3, (9, 33, 130), 4, 0.2),   # 3D walk: three z ranges (64 + 64 + 2 planes)
 ]
 
 

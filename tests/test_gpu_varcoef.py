@@ -40,7 +40,8 @@ def solver(dim, m1, n, eps=None, precision="fp64", faces=None, inner=None, cycle
     return s
 
 
-@pytest.mark.parametrize("dim,m1,n", [(1, 37, 16), (2, 63, 32), (2, 70, 8), (3, 13, 8)])
+@pytest.mark.parametrize("dim,m1,n", [(1, 37, 16), (2, 63, 32), (2, 70, 8), (3, 13, 8),
+                                      (3, 66, 4)])
 def test_apply_A_variable(dim, m1, n):
     faces = rand_faces(m1, dim, 1)
     p = heat.Problem(m1, dim, n, faces=faces)
