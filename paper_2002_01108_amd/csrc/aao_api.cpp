@@ -1023,17 +1023,24 @@ int64_t nm_of(const aao_ctx* c) { return (int64_t)c->g.n * c->g.m; }
 // reduced (optionally scaled) into dsmall[slot..].
 bool fused_stencil(const aao_ctx* c, int q) { return c->g.dim >= 2 && q <= kStencilDotsMax; }
 
+// wslot >= 0 (epi 2): ||L x||^2 is reduced into dsmall[wslot] as well.
 aao_status stencil_fused(aao_ctx* c, int epi, const double* x, double* y, const double* f,
-                         const double* const* basis, int q, int slot, const double* scale) {
+                         const double* const* basis, int q, int slot, const double* scale,
+                         int wslot = -1) {
   ProfScope ps(c, AAO_K_KRYLOV);
   const int64_t nb = stencil_partials(c->g);
   const int nq = epi == 2 ? q : 1;
-  TRY(ensure_part(c, (size_t)nb * nq));
+  const bool wsq = epi == 2 && wslot >= 0;
+  TRY(ensure_part(c, (size_t)nb * (nq + (wsq ? 1 : 0))));
+  double* wpart = wsq ? c->part + nb * nq : nullptr;
   const double* wx = c->var ? c->wface[0] : nullptr;
-  HIPCHK(c, launch_apply_L_epi(c->g, epi, x, y, f, basis, q, c->part, c->cst[0], c->cst[1],
-                               c->cst[2], wx, c->var ? c->wface[1] : nullptr,
+  HIPCHK(c, launch_apply_L_epi(c->g, epi, x, y, f, basis, q, c->part, wpart, c->cst[0],
+                               c->cst[1], c->cst[2], wx, c->var ? c->wface[1] : nullptr,
                                c->var ? c->wface[2] : nullptr, c->stream));
   HIPCHK(c, launch_reduce_partials(c->part, (int)nb, nq, c->dsmall + slot, 0, scale, c->stream));
+  if (wsq)
+    HIPCHK(c, launch_reduce_partials(wpart, (int)nb, 1, c->dsmall + wslot, 0, nullptr,
+                                     c->stream));
   return AAO_OK;
 }
 
@@ -1044,6 +1051,16 @@ aao_status sqnorm_dev(aao_ctx* c, const double* a, const double* b, int slot) {
   TRY(ensure_part(c, (size_t)nb));
   HIPCHK(c, launch_diffnorm(a, b, len, c->part, c->stream));
   HIPCHK(c, launch_reduce_partials(c->part, nb, 1, c->dsmall + slot, 0, nullptr, c->stream));
+  return AAO_OK;
+}
+
+// two ranges of the small scratch to the host, one synchronisation
+aao_status fetch_small2(aao_ctx* c, int off1, int count1, int off2, int count2) {
+  HIPCHK(c, hipMemcpyAsync(c->hsmall + off1, c->dsmall + off1, count1 * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->hsmall + off2, c->dsmall + off2, count2 * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return AAO_OK;
 }
 
@@ -1903,11 +1920,11 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
   const int R = restart;
   // small scratch (doubles): [0] norm, [1..R+1] c1, [R+2..2R+2] c2, [2R+3] norm2,
   // [2R+4..3R+4] y, [3R+5..4R+5] 1/s_i^2, [4R+6] the constant 1 (restart
-  // residuals).  The host writes a slot only when no queued copy still reads it:
+  // residuals), [4R+7] ||L z||^2 of the fused stencil (early convergence test).  The host writes a slot only when no queued copy still reads it:
   // y is rewritten after the next synchronising fetch, and the constant is
   // written once per solve, so a restart never overwrites y while its copy waits.
   const int o_nrm = 0, o_h1 = 1, o_h2 = R + 2, o_n2 = 2 * R + 3, o_y = 2 * R + 4;
-  const int o_is2 = 3 * R + 5, o_one = 4 * R + 6;
+  const int o_is2 = 3 * R + 5, o_one = 4 * R + 6, o_w2 = 4 * R + 7;
   TRY(ensure_small(c, (size_t)(4 * R + 8)));
   c->hsmall[o_one] = 1.0;
   HIPCHK(c, hipMemcpyAsync(c->dsmall + o_one, c->hsmall + o_one, sizeof(double),
@@ -1966,6 +1983,37 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
   }
 
   std::vector<double> H((size_t)(R + 1) * R), cs(R), sn(R), gv(R + 1), y(R), sc(R + 1);
+  std::vector<double> colv(R + 1);
+  // Givens step on column j of H (entries 0..j+1 in col): the previous
+  // rotations, then the new one (cs_j, sn_j); returns the residual estimate
+  // it would give, without touching the solver state
+  auto givens = [&](int j, double* col, double& csj, double& snj) -> double {
+    for (int i = 0; i < j; ++i) {
+      const double a = col[i], b = col[i + 1];
+      col[i] = cs[i] * a + sn[i] * b;
+      col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double rho = hypot(a, b);
+    csj = rho > 0 ? a / rho : 1.0;
+    snj = rho > 0 ? b / rho : 0.0;
+    col[j] = rho;
+    col[j + 1] = 0.0;
+    return fabs(snj * gv[j]) / ref;
+  };
+  auto commit = [&](int j, const double* col, double csj, double snj) {
+    for (int i = 0; i <= j + 1; ++i) H[(size_t)i * R + j] = col[i];
+    cs[j] = csj;
+    sn[j] = snj;
+    gv[j + 1] = -snj * gv[j];
+    gv[j] = csj * gv[j];
+  };
+  // Early convergence test on large systems with the fused stencil: the
+  // stencil also returns ||w||^2, so ||w - W c1||^2 = ||w||^2 - sum_i (c1_i s_i)^2
+  // (W_i orthogonal) bounds h_{j+1,j} from above once a rounding allowance is
+  // added; if even that bound meets tol the step is the last one, and neither
+  // Gram-Schmidt pass over w is needed.  One extra synchronisation per step.
+  const bool probe = !left && tol > 0.0 && nm >= ((int64_t)1 << 22);
   int total = 0, nhist = 0;
   bool converged = false;
   bool first = true;
@@ -2076,7 +2124,34 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
       if (fuse) {
         const double* basis[kStencilDotsMax];
         for (int i = 0; i < q; ++i) basis[i] = (i == 0 && v0) ? v0 : c->V + (int64_t)i * nm;
-        TRY(stencil_fused(c, 2, zj, w, nullptr, basis, q, o_h1, is2));
+        TRY(stencil_fused(c, 2, zj, w, nullptr, basis, q, o_h1, is2, probe ? o_w2 : -1));
+        if (probe) {
+          TRY(fetch_small2(c, o_h1, q, o_w2, 1));
+          const double w2 = c->hsmall[o_w2];
+          double proj2 = 0.0;
+          for (int i = 0; i < q; ++i) {
+            const double pr = c->hsmall[o_h1 + i] * sc[i];   // projection on v_i = W_i / s_i
+            proj2 += pr * pr;
+            colv[i] = pr / sc[j];
+          }
+          if (isfinite(w2) && isfinite(proj2)) {
+            // rounding of the dots and of the basis' orthogonality: a few ulps per
+            // term relative to ||w||^2
+            const double wp2 = std::max(w2 - proj2, 0.0) + 1e-13 * (q + 1) * w2;
+            colv[j + 1] = sqrt(wp2) / sc[j];
+            double csj, snj;
+            const double est_ub = givens(j, colv.data(), csj, snj);
+            if (est_ub <= tol) {
+              commit(j, colv.data(), csj, snj);
+              ++total;
+              if (res_hist && nhist < hist_cap) res_hist[nhist] = est_ub;
+              ++nhist;
+              converged = true;
+              stop = true;
+              break;
+            }
+          }
+        }
       } else if (!left) {
         TRY(apply_L(c, zj, w));
       }
@@ -2110,7 +2185,7 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
       TRY(fetch_small(c, 0, o_n2 + 1));
       // H in the orthonormal basis: h_ij = (c1_i + c2_i) s_i / s_j, h_{j+1,j} = ||w''|| / s_j
       for (int i = 0; i < q; ++i)
-        H[(size_t)i * R + j] = (c->hsmall[o_h1 + i] + c->hsmall[o_h2 + i]) * sc[i] / sc[j];
+        colv[i] = (c->hsmall[o_h1 + i] + c->hsmall[o_h2 + i]) * sc[i] / sc[j];
       double wn2 = c->hsmall[o_n2];
       const bool deferred = q <= 8;   // second correction not yet applied
       if (deferred)
@@ -2120,25 +2195,12 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
         TRY(clear_u());
         return fail(c, AAO_ENAN, "Arnoldi vector is not finite");
       }
-      const double hn = wn / sc[j];
-      H[(size_t)(j + 1) * R + j] = hn;
+      colv[j + 1] = wn / sc[j];
       sc[j + 1] = wn;
-      // apply previous rotations, then a new one (real Givens)
-      for (int i = 0; i < j; ++i) {
-        const double a = H[(size_t)i * R + j], b = H[(size_t)(i + 1) * R + j];
-        H[(size_t)i * R + j] = cs[i] * a + sn[i] * b;
-        H[(size_t)(i + 1) * R + j] = -sn[i] * a + cs[i] * b;
-      }
-      const double a = H[(size_t)j * R + j], b = H[(size_t)(j + 1) * R + j];
-      const double rho = hypot(a, b);
-      cs[j] = rho > 0 ? a / rho : 1.0;
-      sn[j] = rho > 0 ? b / rho : 0.0;
-      H[(size_t)j * R + j] = rho;
-      H[(size_t)(j + 1) * R + j] = 0.0;
-      gv[j + 1] = -sn[j] * gv[j];
-      gv[j] = cs[j] * gv[j];
+      double csj, snj;
+      const double est = givens(j, colv.data(), csj, snj);
+      commit(j, colv.data(), csj, snj);
       ++total;
-      const double est = fabs(gv[j + 1]) / ref;
       if (res_hist && nhist < hist_cap) res_hist[nhist] = est;
       ++nhist;
       const bool breakdown = (wn == 0.0);

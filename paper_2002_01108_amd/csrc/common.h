@@ -107,14 +107,14 @@ hipError_t launch_apply_L_var(const Geometry& g, const double* x, double* y, con
 // Fused stencil passes (2D/3D only; AAO dim 1 uses the plain kernel).
 // epi 1: partial sums of (f - L x)^2, one per block, y unused (may be null);
 // epi 2: y = L x and partial dots of y with basis[0..q-1] (q <= kStencilDotsMax),
-// q per block.
+// q per block, and (wsq non-null) partial sums of y^2, one per block in wsq.
 // Constant coefficient: c1..c3 with ax = null; variable: ax, ay, az face weights.
-// part must hold stencil_partials(g) * q doubles.
+// part must hold stencil_partials(g) * q doubles, wsq stencil_partials(g).
 constexpr int kStencilDotsMax = 4;
 int64_t stencil_partials(const Geometry& g);
 hipError_t launch_apply_L_epi(const Geometry& g, int epi, const double* x, double* y,
                               const double* f, const double* const* basis, int q, double* part,
-                              double c1, double c2, double c3, const double* ax,
+                              double* wsq, double c1, double c2, double c3, const double* ax,
                               const double* ay, const double* az, hipStream_t s);
 
 // Step 1: Gamma_eps scaling + forward time DFT (theta = e^{+2 pi i/n}) of a real
