@@ -80,6 +80,8 @@ struct aao_ctx {
   double* Foo64[3] = {nullptr, nullptr, nullptr};
   float* Foe32[3] = {nullptr, nullptr, nullptr};
   float* Foo32[3] = {nullptr, nullptr, nullptr};
+  // BF16 hi/lo splits of Foe32/Foo32: {hi oe, lo oe, hi oo, lo oo} per axis
+  uint16_t* Fbf[3][4] = {};
   // two-level fold tables [4][P_d/4][P_d/4] (odd m_d, P_d % 128 == 0), else null,
   // and their transposes [table][t][q] for the fused forward-divide-inverse kernel
   double* Fq64[3] = {nullptr, nullptr, nullptr};
@@ -367,9 +369,9 @@ hipError_t run_time_inv(aao_ctx* c, const void* spec, double* z) {
   return launch_time_inv_f32(c->g, (const float*)spec, z, c->ginv32, c->tw32, c->stream);
 }
 
-// Folded product (2D/3D, FP64 or FP32 preconditioner) along axis d; with
+// Folded product (2D/3D, any preconditioner precision) along axis d; with
 // `divtm` the shifted divide by lambda_k + sum_d divtm_d runs in its epilogue.
-bool use_fold(const aao_ctx* c) { return c->g.dim >= 2 && c->prec != AAO_BF16X3; }
+bool use_fold(const aao_ctx* c) { return c->g.dim >= 2; }
 
 FoldArgs fold_args(const aao_ctx* c, int d, bool real_ends) {
   const Geometry& g = c->g;
@@ -462,12 +464,15 @@ hipError_t fold_product(aao_ctx* c, int d, const void* in, void* out, double* co
   if (c->prec == AAO_FP64)
     return launch_dst_fold<double>((const double*)in, (double*)out, c->Foe64[d], c->Foo64[d], f,
                                    d != 0, lam, t1, t2, t3, c->stream);
+  if (c->prec == AAO_BF16X3)
+    return launch_dst_fold_bf16x3((const float*)in, (float*)out, c->Fbf[d], f, d != 0, lam, t1,
+                                  t2, t3, c->stream);
   return launch_dst_fold<float>((const float*)in, (float*)out, c->Foe32[d], c->Foo32[d], f,
                                 d != 0, lam, t1, t2, t3, c->stream);
 }
 
 // One mode product along axis d (0 = x, 1 = y, 2 = z) from `in` to `out`
-// as a dense batched GEMM (1D, and the BF16x3 preconditioner).
+// as a dense batched GEMM (1D).
 hipError_t mode_product(aao_ctx* c, int d, const void* in, void* out) {
   ProfScope ps(c, AAO_K_DST);
   const Geometry& g = c->g;
@@ -1232,6 +1237,18 @@ aao_status aao_setup(int dim, int m1, int m2, int m3, int n, double T, double ep
     if ((st = upload(c, &c->Foo64[d], fo)) != AAO_OK) return bail(st);
     if ((st = upload(c, &c->Foe32[d], fe32)) != AAO_OK) return bail(st);
     if ((st = upload(c, &c->Foo32[d], fo32)) != AAO_OK) return bail(st);
+    {
+      std::vector<uint16_t> sp[4];
+      for (auto& v : sp) v.resize((size_t)Hp * Hp);
+      for (size_t e = 0; e < (size_t)Hp * Hp; ++e) {
+        sp[0][e] = bf16_rne_host(fe32[e]);
+        sp[1][e] = bf16_rne_host(fe32[e] - bf16_value_host(sp[0][e]));
+        sp[2][e] = bf16_rne_host(fo32[e]);
+        sp[3][e] = bf16_rne_host(fo32[e] - bf16_value_host(sp[2][e]));
+      }
+      for (int q = 0; q < 4; ++q)
+        if ((st = upload(c, &c->Fbf[d][q], sp[q])) != AAO_OK) return bail(st);
+    }
     // second fold (odd m): S_{r, 2t'+b} = (-1)^r S_{r, 2t+b} for the mirror
     // t' = h-1-t (b = 0) / h-2-t (b = 1); tables A+ A- B+ B- over pair indices
     if (md % 2 == 1 && P % 128 == 0) {

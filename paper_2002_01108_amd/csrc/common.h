@@ -178,6 +178,13 @@ hipError_t launch_dst_fold(const T* in, T* out, const T* Soe, const T* Soo, cons
                            bool left, const double* lam, const double* tmu1, const double* tmu2,
                            const double* tmu3, hipStream_t s);
 
+// BF16x3 one-level fold (FP32 data): tabs = {hi(S_oe), lo(S_oe), hi(S_oo), lo(S_oo)},
+// the BF16 splits of the FP32 folded tables; otherwise as launch_dst_fold.
+hipError_t launch_dst_fold_bf16x3(const float* in, float* out, const uint16_t* const* tabs,
+                                  const FoldArgs& f, bool left, const double* lam,
+                                  const double* tmu1, const double* tmu2, const double* tmu3,
+                                  hipStream_t s);
+
 // Two-level fold for odd m (P_d a multiple of 128): tabs = [4][Hq][Hq], Hq = P_d/4,
 // the quarter tables A+, A-, B+, B- (rows q: output rows 2q for +, 2q+1 for -;
 // columns: pair index t of the even (A) / odd (B) inputs).  Same arguments and

@@ -47,6 +47,122 @@ constexpr int FC = 64;     // column (LEFT) / row (RIGHT) tile
 // fall on disjoint banks
 constexpr int PD = 16;
 
+// Position of a block's tile and its lane in the one-level fold kernels.
+struct FoldTile {
+  int tid, w, lr, lk, rt, r0, d0, o, k;
+  bool real_pair;
+  int64_t base0, base1;
+};
+
+// Epilogue of the one-level fold (shared by the FP64/FP32 and BF16x3 kernels:
+// their accumulators have the same 16x16 layout): y_r = O + E,
+// y_{m-1-r} = O - E, the optional complex divide (tax: tau mu along the
+// product's axis, in LDS), Q1 scaling, and zero padding.
+template <typename T, int NS, bool LEFT, bool DIVIDE, typename V>
+__device__ __forceinline__ void fold_epilogue(const V (&acc)[2][2][NS], const FoldTile& tl,
+                                              T* __restrict__ out, const FoldArgs& f,
+                                              const double* tax, const double* __restrict__ lam,
+                                              const double* __restrict__ tmu1,
+                                              const double* __restrict__ tmu2,
+                                              const double* __restrict__ tmu3) {
+  const int tid = tl.tid, w = tl.w, lr = tl.lr, lk = tl.lk, rt = tl.rt;
+  const int r0 = tl.r0, d0 = tl.d0, o = tl.o, k = tl.k;
+  const bool real_pair = tl.real_pair;
+  const int64_t base0 = tl.base0, base1 = tl.base1;
+  const int m = f.m, h = (m + 1) / 2;
+  T* ob0 = out + base0;
+  T* ob1 = out + base1;
+  const double lre = DIVIDE ? lam[2 * k] : 0.0, lim = DIVIDE ? lam[2 * k + 1] : 0.0;
+  // real pair: lambda_0 and lambda_{n/2} are real
+  const double lre1 = (DIVIDE && real_pair) ? lam[2 * f.nk] : 0.0;
+  // divisor terms of the two non-product axes: constant per lane (LEFT) or
+  // per accumulator row v (RIGHT)
+  double cst[4] = {0.0, 0.0, 0.0, 0.0};
+  if (DIVIDE) {
+    if (LEFT) {
+      const int dl = d0 + w * 16 + lr;
+      const double c0 = f.axis == 1 ? tmu1[dl] + (tmu3 ? tmu3[o] : 0.0)
+                                    : tmu1[dl % f.P1] + tmu2[dl / f.P1];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) cst[v] = c0;
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int dr = d0 + w * 16 + Mf<T>::row(lk, v);
+        cst[v] = tmu2[dr % f.P2] + (tmu3 ? tmu3[dr / f.P2] : 0.0);
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int r, dpos;   // half index and data position (column for LEFT, row for RIGHT)
+      if (LEFT) { r = r0 + s * 16 + Mf<T>::row(lk, v); dpos = d0 + w * 16 + lr; }
+      else { r = r0 + s * 16 + lr; dpos = d0 + w * 16 + Mf<T>::row(lk, v); }
+      if (r >= h) continue;
+      // position of the data index in the full grid (for validity and the divide)
+      int i1, i2, i3;
+      if (LEFT) {
+        if (f.axis == 1) { i1 = dpos; i2 = 0; i3 = o; }          // y-mode: column = x, outer = z
+        else { i1 = dpos % f.P1; i2 = dpos / f.P1; i3 = 0; }    // z-mode: column = (y, x)
+      } else {
+        i1 = 0; i2 = dpos % f.P2; i3 = dpos / f.P2;              // x-mode: row = (z, y)
+      }
+      const bool dvalid = i1 < f.m1 && i2 < f.m2 && i3 < f.m3;
+      const T ore = acc[0][0][s][v], ere = acc[0][1][s][v];
+      const T oim = acc[1][0][s][v], eim = acc[1][1][s][v];
+      const int a_top = r, a_bot = m - 1 - r;
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const int a = half ? a_bot : a_top;
+        if (half && a_bot <= a_top) break;
+        T vr = half ? ore - ere : ore + ere;
+        T vi = half ? oim - eim : oim + eim;
+        if (!dvalid) {
+          vr = T(0);
+          vi = T(0);
+        } else if (DIVIDE) {
+          const double mu = cst[v] + tax[a];
+          if (real_pair) {
+            vr = vr / (T)(lre + mu);
+            vi = vi / (T)(lre1 + mu);
+          } else {
+            const T cc = (T)(lre + mu), dd = (T)lim;
+            const T inv = T(1) / (cc * cc + dd * dd);
+            const T nr = (vr * cc + vi * dd) * inv;
+            const T ni = (vi * cc - vr * dd) * inv;
+            vr = nr;
+            vi = ni;
+          }
+          if (LEFT && f.ims_r) {
+            // Q1 elements: B_k = M (lambda_k I + tau M^{-1} K) in the sine basis
+            const T ms = (T)(f.ims_c[dpos] * f.ims_r[a]);
+            vr *= ms;
+            vi *= ms;
+          }
+        }
+        int64_t off;
+        if (LEFT) off = (int64_t)a * f.R + dpos;
+        else off = (int64_t)dpos * f.R + a;
+        ob0[off] = vr;
+        ob1[off] = vi;
+      }
+    }
+  }
+  // output indices m .. 2 Hp - 1 along the axis are padding: zero them for this data tile
+  if (rt == 0) {
+    const int np = 2 * f.Hp - m, cnt = 2 * np * FC;
+    for (int e = tid; e < cnt; e += 256) {
+      const int pl = e / (np * FC), rem = e % (np * FC);
+      int64_t off;
+      if (LEFT) off = (int64_t)(m + rem / FC) * f.R + d0 + rem % FC;
+      else off = (int64_t)(d0 + rem / np) * f.R + m + rem % np;
+      (pl ? ob1 : ob0)[off] = T(0);
+    }
+  }
+}
+
 template <typename T, int FR, bool LEFT, bool DIVIDE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_dst_fold(const T* __restrict__ in, T* __restrict__ out,
                                                   const T* __restrict__ Soe,
@@ -193,99 +309,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     __syncthreads();
   }
 
-  // epilogue: y_r = O + E, y_{m-1-r} = O - E, optional complex divide, zero padding
-  const int m = f.m, h = (m + 1) / 2;
-  T* ob0 = out + base0;
-  T* ob1 = out + base1;
-  const double lre = DIVIDE ? lam[2 * k] : 0.0, lim = DIVIDE ? lam[2 * k + 1] : 0.0;
-  // real pair: lambda_0 and lambda_{n/2} are real
-  const double lre1 = (DIVIDE && real_pair) ? lam[2 * f.nk] : 0.0;
-  // divisor terms of the two non-product axes: constant per lane (LEFT) or
-  // per accumulator row v (RIGHT)
-  double cst[4] = {0.0, 0.0, 0.0, 0.0};
-  if (DIVIDE) {
-    if (LEFT) {
-      const int dl = d0 + w * 16 + lr;
-      const double c0 = f.axis == 1 ? tmu1[dl] + (tmu3 ? tmu3[o] : 0.0)
-                                    : tmu1[dl % f.P1] + tmu2[dl / f.P1];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) cst[v] = c0;
-    } else {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int dr = d0 + w * 16 + Mf<T>::row(lk, v);
-        cst[v] = tmu2[dr % f.P2] + (tmu3 ? tmu3[dr / f.P2] : 0.0);
-      }
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      int r, dpos;   // half index and data position (column for LEFT, row for RIGHT)
-      if (LEFT) { r = r0 + s * 16 + Mf<T>::row(lk, v); dpos = d0 + w * 16 + lr; }
-      else { r = r0 + s * 16 + lr; dpos = d0 + w * 16 + Mf<T>::row(lk, v); }
-      if (r >= h) continue;
-      // position of the data index in the full grid (for validity and the divide)
-      int i1, i2, i3;
-      if (LEFT) {
-        if (f.axis == 1) { i1 = dpos; i2 = 0; i3 = o; }          // y-mode: column = x, outer = z
-        else { i1 = dpos % f.P1; i2 = dpos / f.P1; i3 = 0; }    // z-mode: column = (y, x)
-      } else {
-        i1 = 0; i2 = dpos % f.P2; i3 = dpos / f.P2;              // x-mode: row = (z, y)
-      }
-      const bool dvalid = i1 < f.m1 && i2 < f.m2 && i3 < f.m3;
-      const T ore = acc[0][0][s][v], ere = acc[0][1][s][v];
-      const T oim = acc[1][0][s][v], eim = acc[1][1][s][v];
-      const int a_top = r, a_bot = m - 1 - r;
-#pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        const int a = half ? a_bot : a_top;
-        if (half && a_bot <= a_top) break;
-        T vr = half ? ore - ere : ore + ere;
-        T vi = half ? oim - eim : oim + eim;
-        if (!dvalid) {
-          vr = T(0);
-          vi = T(0);
-        } else if (DIVIDE) {
-          const double mu = cst[v] + tax[a];
-          if (real_pair) {
-            vr = vr / (T)(lre + mu);
-            vi = vi / (T)(lre1 + mu);
-          } else {
-            const T cc = (T)(lre + mu), dd = (T)lim;
-            const T inv = T(1) / (cc * cc + dd * dd);
-            const T nr = (vr * cc + vi * dd) * inv;
-            const T ni = (vi * cc - vr * dd) * inv;
-            vr = nr;
-            vi = ni;
-          }
-          if (LEFT && f.ims_r) {
-            // Q1 elements: B_k = M (lambda_k I + tau M^{-1} K) in the sine basis
-            const T ms = (T)(f.ims_c[dpos] * f.ims_r[a]);
-            vr *= ms;
-            vi *= ms;
-          }
-        }
-        int64_t off;
-        if (LEFT) off = (int64_t)a * f.R + dpos;
-        else off = (int64_t)dpos * f.R + a;
-        ob0[off] = vr;
-        ob1[off] = vi;
-      }
-    }
-  }
-  // output indices m .. 2 Hp - 1 along the axis are padding: zero them for this data tile
-  if (rt == 0) {
-    const int np = 2 * f.Hp - m, cnt = 2 * np * FC;
-    for (int e = tid; e < cnt; e += 256) {
-      const int pl = e / (np * FC), rem = e % (np * FC);
-      int64_t off;
-      if (LEFT) off = (int64_t)(m + rem / FC) * f.R + d0 + rem % FC;
-      else off = (int64_t)(d0 + rem / np) * f.R + m + rem % np;
-      (pl ? ob1 : ob0)[off] = T(0);
-    }
-  }
+  fold_epilogue<T, NS, LEFT, DIVIDE>(acc, FoldTile{tid, w, lr, lk, rt, r0, d0, o, k, real_pair, base0, base1},
+                                     out, f, tax, lam, tmu1, tmu2, tmu3);
 }
 
 template <typename T, int FR>
@@ -314,6 +339,228 @@ hipError_t launch_fold_fr(const T* in, T* out, const T* Soe, const T* Soo, const
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------- BF16x3 fold
+// The one-level fold with BF16 hi/lo splits on v_mfma_f32_16x16x32_bf16: the
+// FP32 data are split while staged (hi = rne(x), lo = rne(x - hi)), the folded
+// tables once on the host, and every product accumulates lo*hi + hi*lo + hi*hi
+// in FP32.  Three BF16 products cost 3/16 of one FP32 matrix-core product, so
+// the pass is bound by HBM even at P_d = 512.  Both LDS operands keep t
+// contiguous (a fragment is 8 consecutive t of one row or column: one 16-byte
+// read), K slices of 32 half indices, one LDS buffer with the next slice
+// prefetched into registers (two buffers would not leave room for two blocks
+// per CU).  Rows of 32 + 8 elements (80 bytes): the 16-byte accesses of 16
+// consecutive rows cover distinct banks.  Tiles, planes and epilogue as
+// k_dst_fold.
+typedef __bf16 fbf16x8 __attribute__((ext_vector_type(8)));
+typedef short fs8v __attribute__((ext_vector_type(8)));
+typedef unsigned short fu16;
+
+typedef __bf16 fbf16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t fu32x4 __attribute__((ext_vector_type(4)));
+// hi = rne(x), lo = rne(x - hi) of two values, as packed pairs (the
+// conversions are v_cvt_pk_bf16_f32: round to nearest even)
+__device__ __forceinline__ void fold_split2(float a, float b, uint32_t& hi, uint32_t& lo) {
+  const fbf16x2 h = {(__bf16)a, (__bf16)b};
+  hi = __builtin_bit_cast(uint32_t, h);
+  const fbf16x2 l = {(__bf16)(a - __uint_as_float(hi << 16)),
+                     (__bf16)(b - __uint_as_float(hi & 0xFFFF0000u))};
+  lo = __builtin_bit_cast(uint32_t, l);
+}
+
+constexpr int XK3 = 32, XR3 = XK3 + 8;   // K slice and LDS row length (bf16 elements)
+
+template <int FR, bool LEFT, bool DIVIDE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_dst_fold_bf3(
+    const float* __restrict__ in, float* __restrict__ out, const fu16* __restrict__ Shi_oe,
+    const fu16* __restrict__ Slo_oe, const fu16* __restrict__ Shi_oo,
+    const fu16* __restrict__ Slo_oo, FoldArgs f, const double* __restrict__ lam,
+    const double* __restrict__ tmu1, const double* __restrict__ tmu2,
+    const double* __restrict__ tmu3) {
+  constexpr int NS = FR / 16;               // 16-wide sub-tiles per wave
+  constexpr int SPT = 2 * FR * XK3 / 256;   // table elements per thread and slice (16 or 8)
+  constexpr int SQ = SPT / 8;               // 16-byte words of them
+  // tables [buffer][hi/lo][O/E][r][t]
+  __shared__ __attribute__((aligned(16))) fu16 S3[2][2][2][FR][XR3];
+  __shared__ double tax[DIVIDE ? 1024 : 1];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int nrt = f.Hp / FR;
+  const int rt = bid % nrt;
+  bid /= nrt;
+  const int dt = bid % f.ndt;
+  bid /= f.ndt;
+  const int o = bid % f.nout;
+  const int k = bid / f.nout;
+  const int r0 = rt * FR, d0 = dt * FC;
+  const bool real_pair = f.packed && k == 0;
+  const int64_t base0 = (int64_t)k * 2 * f.PS + (int64_t)o * f.OS;
+  const int64_t base1 = real_pair ? (int64_t)f.nk * 2 * f.PS + (int64_t)o * f.OS : base0 + f.PS;
+
+  // tables: thread -> (O/E, row, SPT consecutive t)
+  const int s_mat = tid >> 7;
+  const int s_r = (tid & 127) / (XK3 / SPT), s_t = ((tid & 127) % (XK3 / SPT)) * SPT;
+  const fu32x4* Sh = reinterpret_cast<const fu32x4*>(s_mat ? Shi_oo : Shi_oe);
+  const fu32x4* Sl = reinterpret_cast<const fu32x4*>(s_mat ? Slo_oo : Slo_oe);
+  // data: lane (lr, lk) of wave w reads its own operand fragments, the 8 half
+  // indices t = t0 + 8 lk + j (j < 8) of both parities and planes at data
+  // position d0 + 16 w + lr (LEFT: a column; RIGHT: a row)
+  const int dpos = d0 + w * 16 + lr;
+  const float* src0 = in + base0;
+  const float* src1 = in + base1;
+
+  struct Stage {
+    fu32x4 sh[SQ], sl[SQ];
+    float d[2][2][8];   // [plane][parity][j]
+  };
+  auto fetch = [&](int t0, Stage& g) {
+    const int64_t so = ((int64_t)(r0 + s_r) * f.Hp + t0 + s_t) / 8;
+#pragma unroll
+    for (int q = 0; q < SQ; ++q) {
+      g.sh[q] = Sh[so + q];
+      g.sl[q] = Sl[so + q];
+    }
+    const int i0 = 2 * (t0 + 8 * lk);   // first input index of the lane
+#pragma unroll
+    for (int pl = 0; pl < 2; ++pl) {
+      const float* src = pl ? src1 : src0;
+      if (LEFT) {
+        // 16 consecutive input rows of one column, parities interleaved
+        const float* p = src + (int64_t)i0 * f.R + dpos;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) g.d[pl][e & 1][e >> 1] = p[(int64_t)e * f.R];
+      } else {
+        // 16 consecutive inputs of one data row: four 16-byte loads
+        const float4* p = reinterpret_cast<const float4*>(src + (int64_t)dpos * f.R + i0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float4 v = p[q];
+          g.d[pl][0][2 * q] = v.x;
+          g.d[pl][1][2 * q] = v.y;
+          g.d[pl][0][2 * q + 1] = v.z;
+          g.d[pl][1][2 * q + 1] = v.w;
+        }
+      }
+    }
+  };
+  auto stash = [&](int buf, const Stage& g) {
+#pragma unroll
+    for (int q = 0; q < SQ; ++q) {
+      *reinterpret_cast<fu32x4*>(&S3[buf][0][s_mat][s_r][s_t + 8 * q]) = g.sh[q];
+      *reinterpret_cast<fu32x4*>(&S3[buf][1][s_mat][s_r][s_t + 8 * q]) = g.sl[q];
+    }
+  };
+  auto frag = [](const fu16* p) {
+    return __builtin_bit_cast(fbf16x8, *reinterpret_cast<const fs8v*>(p));
+  };
+  auto tofrag = [](const uint32_t (&u)[4]) {
+    return __builtin_bit_cast(fbf16x8, fu32x4{u[0], u[1], u[2], u[3]});
+  };
+
+  f4 acc[2][2][NS];   // [plane][O/E][sub-tile]
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc[a][b][s] = f4{0, 0, 0, 0};
+
+  // one K slice: the data fragments split in registers, the table fragments
+  // from LDS buffer `buf`; oe is a constant so that the accumulators stay in
+  // registers
+  auto product = [&](auto oe_c, int buf, const fbf16x8 (&dh)[2], const fbf16x8 (&dl)[2]) {
+    constexpr int oe = decltype(oe_c)::value;
+    const int kc = lk * 8;
+    fbf16x8 th[NS], tl[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      th[i] = frag(&S3[buf][0][oe][i * 16 + lr][kc]);
+      tl[i] = frag(&S3[buf][1][oe][i * 16 + lr][kc]);
+    }
+#pragma unroll
+    for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        f4 c = acc[pl][oe][i];
+        if (LEFT) {   // table rows x data columns
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(tl[i], dh[pl], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th[i], dl[pl], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th[i], dh[pl], c, 0, 0, 0);
+        } else {      // data rows x table rows (S^T)
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dl[pl], th[i], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dh[pl], tl[i], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dh[pl], th[i], c, 0, 0, 0);
+        }
+        acc[pl][oe][i] = c;
+      }
+  };
+  auto compute = [&](int buf, const Stage& g) {
+    // parity par multiplies the O (par 0) or E (par 1) table
+    fbf16x8 dh[2][2], dl[2][2];   // [parity][plane]
+#pragma unroll
+    for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {
+        uint32_t h[4], l[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          fold_split2(g.d[pl][par][2 * e], g.d[pl][par][2 * e + 1], h[e], l[e]);
+        dh[par][pl] = tofrag(h);
+        dl[par][pl] = tofrag(l);
+      }
+    product(std::integral_constant<int, 0>{}, buf, dh[0], dl[0]);
+    product(std::integral_constant<int, 1>{}, buf, dh[1], dl[1]);
+  };
+
+  if (DIVIDE) {
+    const double* ax_tab = LEFT ? (f.axis == 1 ? tmu2 : tmu3) : tmu1;
+    for (int i = tid; i < 2 * f.Hp; i += 256) tax[i] = ax_tab[i];
+  }
+  const int nk = f.Hp / XK3;
+  // tables double-buffered in LDS (one barrier per slice); the next slice's
+  // tables and data are loaded into registers while this one computes
+  Stage cur, nxt;
+  fetch(0, cur);
+  stash(0, cur);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) fetch((kt + 1) * XK3, nxt);
+    compute(buf, cur);
+    if (kt + 1 < nk) {
+      stash(buf ^ 1, nxt);
+      cur = nxt;
+    }
+    __syncthreads();
+  }
+  fold_epilogue<float, NS, LEFT, DIVIDE>(
+      acc, FoldTile{tid, w, lr, lk, rt, r0, d0, o, k, real_pair, base0, base1}, out, f, tax, lam,
+      tmu1, tmu2, tmu3);
+}
+
+template <int FR>
+hipError_t launch_fold_bf3_fr(const float* in, float* out, const fu16* const* T, const FoldArgs& f,
+                              bool left, const double* lam, const double* tmu1,
+                              const double* tmu2, const double* tmu3, hipStream_t s) {
+  const int64_t nblk = (int64_t)(f.Hp / FR) * f.ndt * f.nout * f.nk;
+  if (nblk > 0x7fffffff || nblk < 1) return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)nblk), blk(256);
+#define AAO_BF3(L, D)                                                                        \
+  hipLaunchKernelGGL((k_dst_fold_bf3<FR, L, D>), grid, blk, 0, s, in, out, T[0], T[1], T[2], \
+                     T[3], f, lam, tmu1, tmu2, tmu3)
+  if (left) {
+    if (lam) AAO_BF3(true, true);
+    else AAO_BF3(true, false);
+  } else {
+    if (lam) AAO_BF3(false, true);
+    else AAO_BF3(false, false);
+  }
+#undef AAO_BF3
+  return hipGetLastError();
+}
 
 // ---------------------------------------------------------------- two-level fold (odd m)
 // For odd m (h = (m+1)/2) the halves fold once more.  With a the even (b = 0)
@@ -1043,6 +1290,20 @@ hipError_t launch_dst_fold2_rows(const double* in, double* out, const double* tt
                        s, in, out, tt, f, (int)ntiles);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_dst_fold_bf16x3(const float* in, float* out, const uint16_t* const* tabs,
+                                  const FoldArgs& f, bool left, const double* lam,
+                                  const double* tmu1, const double* tmu2, const double* tmu3,
+                                  hipStream_t s) {
+  if (f.Hp % 32 || f.Hp < 32 || f.ndt < 1 || f.nout < 1 || f.nk < 1 || 2 * f.Hp > 1024)
+    return hipErrorInvalidValue;
+  if (f.m < 1 || f.m > 2 * f.Hp) return hipErrorInvalidValue;
+  for (int i = 0; i < 4; ++i)
+    if (!tabs[i]) return hipErrorInvalidValue;
+  if (f.Hp % 64 == 0)
+    return launch_fold_bf3_fr<64>(in, out, tabs, f, left, lam, tmu1, tmu2, tmu3, s);
+  return launch_fold_bf3_fr<32>(in, out, tabs, f, left, lam, tmu1, tmu2, tmu3, s);
 }
 
 template hipError_t launch_dst_fold2<double>(const double*, double*, const double*,

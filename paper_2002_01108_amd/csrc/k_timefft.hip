@@ -10,7 +10,8 @@
 // of each time row, every load and store instruction is contiguous.  Two
 // real sequences a, b travel as one complex sequence a + i b ("two for one"),
 // untangled after the forward transform and re-tangled before the inverse.
-// The FFT is a Stockham autosort sequence of radix-16 (last: smaller) passes;
+// The FFT is a Stockham autosort sequence of radix-16 (last: smaller) passes
+// (radix 8 where radix 16 would spill registers);
 // each thread keeps its butterfly's points in registers and the passes
 // exchange through one LDS tile of n x CW complex values.  The forward runs its
 // first pass on the values it loaded; the inverse stages the half spectrum in
@@ -28,8 +29,8 @@ namespace {
 
 // TH threads per block: 256, or 512 for long transforms of HBM-resident data
 // (wider column strips per block keep more of each DRAM page per request).
-template <int N, int TH> struct Cfg {
-  static constexpr int R1 = N < 16 ? N : 16;
+template <int N, int TH, int RX> struct Cfg {
+  static constexpr int R1 = N < RX ? N : RX;
   static constexpr int TPC = N / R1;     // threads per column
   static constexpr int CW = TH / TPC;    // complex columns per block
 };
@@ -106,12 +107,12 @@ __device__ __forceinline__ cplx<T> twiddle(const cplx<T>* __restrict__ tw, int e
 // One Stockham pass (accumulated length NS -> NS*R) from the LDS tile.
 // Results go back to LDS unless FINAL, in which case sink(i0, di, value) gets
 // the one at index i0 + di (di a compile-time multiple of NS, i0 per thread).
-template <typename T, int N, int TH, int SIGN, int NS, bool FINAL, typename Sink>
+template <typename T, int N, int TH, int RX, int SIGN, int NS, bool FINAL, typename Sink>
 __device__ __forceinline__ void lds_pass(cplx<T>* lds, const cplx<T>* __restrict__ tw, int t,
                                          int c, Sink&& sink) {
   using C = cplx<T>;
-  constexpr int TPC = Cfg<N, TH>::TPC, CW = Cfg<N, TH>::CW;
-  constexpr int R = (N / NS) < 16 ? (N / NS) : 16;
+  constexpr int TPC = Cfg<N, TH, RX>::TPC, CW = Cfg<N, TH, RX>::CW;
+  constexpr int R = (N / NS) < RX ? (N / NS) : RX;
   constexpr int NB = N / R;
   constexpr int PER = NB / TPC;
   C v[PER][R];
@@ -143,43 +144,44 @@ __device__ __forceinline__ void lds_pass(cplx<T>* lds, const cplx<T>* __restrict
 }
 
 // All passes after the first, writing back to LDS, ending with a barrier.
-template <typename T, int N, int TH, int SIGN, int NS>
+template <typename T, int N, int TH, int RX, int SIGN, int NS>
 __device__ __forceinline__ void lds_passes_all(cplx<T>* lds, const cplx<T>* __restrict__ tw, int t,
                                                int c) {
   if constexpr (NS < N) {
-    lds_pass<T, N, TH, SIGN, NS, false>(lds, tw, t, c, [](int, cplx<T>) {});
-    constexpr int R = (N / NS) < 16 ? (N / NS) : 16;
-    lds_passes_all<T, N, TH, SIGN, NS * R>(lds, tw, t, c);
+    lds_pass<T, N, TH, RX, SIGN, NS, false>(lds, tw, t, c, [](int, cplx<T>) {});
+    constexpr int R = (N / NS) < RX ? (N / NS) : RX;
+    lds_passes_all<T, N, TH, RX, SIGN, NS * R>(lds, tw, t, c);
   } else {
     __syncthreads();
   }
 }
 
 // Passes after the first except the last (which the caller runs as FINAL).
-template <typename T, int N, int TH, int SIGN, int NS>
+template <typename T, int N, int TH, int RX, int SIGN, int NS>
 __device__ __forceinline__ void lds_passes_but_last(cplx<T>* lds, const cplx<T>* __restrict__ tw,
                                                     int t, int c) {
-  constexpr int R = (N / NS) < 16 ? (N / NS) : 16;
+  constexpr int R = (N / NS) < RX ? (N / NS) : RX;
   if constexpr (NS * R < N) {
-    lds_pass<T, N, TH, SIGN, NS, false>(lds, tw, t, c, [](int, cplx<T>) {});
-    lds_passes_but_last<T, N, TH, SIGN, NS * R>(lds, tw, t, c);
+    lds_pass<T, N, TH, RX, SIGN, NS, false>(lds, tw, t, c, [](int, cplx<T>) {});
+    lds_passes_but_last<T, N, TH, RX, SIGN, NS * R>(lds, tw, t, c);
   }
 }
 
-template <int N, int NS> struct LastNS {
-  static constexpr int R = (N / NS) < 16 ? (N / NS) : 16;
-  static constexpr int value = (NS * R >= N) ? NS : LastNS<N, (NS * R >= N ? N : NS * R)>::value;
+template <int N, int NS, int RX> struct LastNS {
+  static constexpr int R = (N / NS) < RX ? (N / NS) : RX;
+  static constexpr int value =
+      (NS * R >= N) ? NS : LastNS<N, (NS * R >= N ? N : NS * R), RX>::value;
 };
-template <int N> struct LastNS<N, N> { static constexpr int value = N; };
+template <int N, int RX> struct LastNS<N, N, RX> { static constexpr int value = N; };
 
 // ---------------------------------------------------------------- forward (Step 1)
-template <typename T, int N, int TH>
+template <typename T, int N, int TH, int RX>
 __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(2))) void k_time_fwd(
     const double* __restrict__ x, T* __restrict__ spec, const T* __restrict__ gam,
     const cplx<T>* __restrict__ tw, int m1, int m2, int m3, int P1, int P2, int64_t PS,
     int nseg, int nstrip) {
   using C = cplx<T>;
-  constexpr int R1 = Cfg<N, TH>::R1, TPC = Cfg<N, TH>::TPC, CW = Cfg<N, TH>::CW;
+  constexpr int R1 = Cfg<N, TH, RX>::R1, TPC = Cfg<N, TH, RX>::TPC, CW = Cfg<N, TH, RX>::CW;
   __shared__ C lds[N * CW];
   __shared__ C twl[N];
   __shared__ T gl[N];
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(2))) void k_
     __syncthreads();  // the previous strip's untangle has read lds
 #pragma unroll
     for (int r = 0; r < R1; ++r) lds[(t * R1 + r) * CW + c] = v[r];
-    lds_passes_all<T, N, TH, +1, R1>(lds, twl, t, c);
+    lds_passes_all<T, N, TH, RX, +1, R1>(lds, twl, t, c);
 
     // untangle: A(k) = (C(k) + conj C(n-k))/2, B(k) = (C(k) - conj C(n-k))/(2i)
     const int sg = b % nseg, row = b / nseg, i2 = row % P2, i3 = row / P2;
@@ -267,13 +269,13 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(2))) void k_
 // No register cap beyond the launch bound: with 256 threads the kernel runs
 // one wave per SIMD without spilling, which measures faster than two waves
 // with spills (spill reloads share the counter the prefetched loads wait on).
-template <typename T, int N, int TH>
+template <typename T, int N, int TH, int RX>
 __global__ __launch_bounds__(TH) void k_time_inv(
     const T* __restrict__ spec, double* __restrict__ z, const T* __restrict__ ginv,
     const cplx<T>* __restrict__ tw, int m1, int m2, int m3, int P1, int P2, int64_t PS,
     int nseg, int nstrip) {
   using C = cplx<T>;
-  constexpr int TPC = Cfg<N, TH>::TPC, CW = Cfg<N, TH>::CW;
+  constexpr int TPC = Cfg<N, TH, RX>::TPC, CW = Cfg<N, TH, RX>::CW;
   constexpr int KI = (N / 2) / TPC + 1;  // loads per thread cover k = t + TPC i <= n/2
   __shared__ C lds[N * CW];
   __shared__ C twl[N];
@@ -340,36 +342,36 @@ __global__ __launch_bounds__(TH) void k_time_inv(
       if (va) zp[0] = (double)(val.x * g);
       if (vb) zp[CW] = (double)(val.y * g);
     };
-    lds_passes_but_last<T, N, TH, -1, 1>(lds, twl, t, c);
-    constexpr int NSL = LastNS<N, 1>::value;
-    lds_pass<T, N, TH, -1, NSL, true>(lds, twl, t, c, store);
+    lds_passes_but_last<T, N, TH, RX, -1, 1>(lds, twl, t, c);
+    constexpr int NSL = LastNS<N, 1, RX>::value;
+    lds_pass<T, N, TH, RX, -1, NSL, true>(lds, twl, t, c, store);
   }
 }
 
-template <typename T, int N, int TH>
+template <typename T, int N, int TH, int RX = 16>
 hipError_t launch_fwd_n(const Geometry& g, const double* x, T* spec, const T* gam,
                         const cplx<T>* tw, hipStream_t s) {
-  constexpr int CW = Cfg<N, TH>::CW;
+  constexpr int CW = Cfg<N, TH, RX>::CW;
   const int nseg = (g.P1 + 2 * CW - 1) / (2 * CW);
   const int64_t ns = (int64_t)nseg * g.P2 * g.P3;
   if (ns > INT32_MAX) return hipErrorInvalidValue;
-  static const int resident = persistent_grid(k_time_fwd<T, N, TH>, TH);
+  static const int resident = persistent_grid(k_time_fwd<T, N, TH, RX>, TH);
   if (resident < 8) return hipErrorInvalidDeviceFunction;
-  hipLaunchKernelGGL((k_time_fwd<T, N, TH>), dim3(strip_grid(resident, ns)), dim3(TH), 0, s,
+  hipLaunchKernelGGL((k_time_fwd<T, N, TH, RX>), dim3(strip_grid(resident, ns)), dim3(TH), 0, s,
                      x, spec, gam, tw, g.m1, g.m2, g.m3, g.P1, g.P2, g.PS, nseg, (int)ns);
   return hipGetLastError();
 }
 
-template <typename T, int N, int TH>
+template <typename T, int N, int TH, int RX = 16>
 hipError_t launch_inv_n(const Geometry& g, const T* spec, double* z, const T* ginv,
                         const cplx<T>* tw, hipStream_t s) {
-  constexpr int CW = Cfg<N, TH>::CW;
+  constexpr int CW = Cfg<N, TH, RX>::CW;
   const int nseg = (g.m1 + 2 * CW - 1) / (2 * CW);
   const int64_t ns = (int64_t)nseg * g.m2 * g.m3;
   if (ns > INT32_MAX) return hipErrorInvalidValue;
-  static const int resident = persistent_grid(k_time_inv<T, N, TH>, TH);
+  static const int resident = persistent_grid(k_time_inv<T, N, TH, RX>, TH);
   if (resident < 8) return hipErrorInvalidDeviceFunction;
-  hipLaunchKernelGGL((k_time_inv<T, N, TH>), dim3(strip_grid(resident, ns)), dim3(TH), 0, s,
+  hipLaunchKernelGGL((k_time_inv<T, N, TH, RX>), dim3(strip_grid(resident, ns)), dim3(TH), 0, s,
                      spec, z, ginv, tw, g.m1, g.m2, g.m3, g.P1, g.P2, g.PS, nseg, (int)ns);
   return hipGetLastError();
 }
@@ -399,6 +401,15 @@ hipError_t dispatch_fwd(const Geometry& g, const double* x, T* spec, const T* ga
   return hipErrorInvalidValue;
 }
 
+// Largest radix of the inverse passes.  The FP64 n = 256 inverse with radix
+// 16 needs more than the 256 registers two waves per SIMD leave it and spills
+// (54 registers); radix 8 (three passes instead of two) fits in 148 without
+// spilling and measured 2.55 ms against 2.78 ms per launch at 127^3 x 256.
+// At n = 512 the radix-16 spill is small (5 registers) and radix 16 is faster.
+template <typename T, int N> struct InvRadix {
+  static constexpr int value = (sizeof(T) == 8 && N == 256) ? 8 : 16;
+};
+
 template <typename T>
 hipError_t dispatch_inv(const Geometry& g, const T* spec, double* z, const T* ginv, const T* tw,
                         hipStream_t s) {
@@ -406,8 +417,10 @@ hipError_t dispatch_inv(const Geometry& g, const T* spec, double* z, const T* gi
   switch (g.n) {
 #define CASE(NN) \
   case NN:                                                                         \
-    return wide_strips<NN>(g) ? launch_inv_n<T, NN, WideTH<NN>::value>(g, spec, z, ginv, twc, s) \
-                              : launch_inv_n<T, NN, 256>(g, spec, z, ginv, twc, s);
+    return wide_strips<NN>(g)                                                          \
+               ? launch_inv_n<T, NN, WideTH<NN>::value, InvRadix<T, NN>::value>(          \
+                     g, spec, z, ginv, twc, s)                                             \
+               : launch_inv_n<T, NN, 256>(g, spec, z, ginv, twc, s);
     AAO_FOR_EACH_N(CASE)
 #undef CASE
   }
