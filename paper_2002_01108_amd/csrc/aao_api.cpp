@@ -2200,12 +2200,26 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
         }
       }
       TRY(fetch_small(c, 0, o_n2 + 1));
+      const bool deferred = q <= 8;   // second correction not yet applied
+      // The second-pass dots measure what the first pass left: w' makes the
+      // angle cos_i = |c2_i| s_i / ||w'|| with v_i.  When every cos_i is below
+      // 1e-3 tol, w' itself becomes the next basis vector and H takes c1 alone
+      // (for w' the Arnoldi relation holds as computed); the basis is then
+      // orthogonal to that level, which moves the least-squares residual by a
+      // relative amount far below tol, and the second correction's pass over
+      // w and W is saved.
+      bool second = true;
+      if (deferred && tol > 0.0) {
+        const double n1 = sqrt(std::max(c->hsmall[o_n2], 0.0));
+        double cmax = 0.0;
+        for (int i = 0; i < q; ++i) cmax = std::max(cmax, fabs(c->hsmall[o_h2 + i]) * sc[i]);
+        if (isfinite(cmax) && n1 > 0.0 && cmax <= 1e-3 * tol * n1) second = false;
+      }
       // H in the orthonormal basis: h_ij = (c1_i + c2_i) s_i / s_j, h_{j+1,j} = ||w''|| / s_j
       for (int i = 0; i < q; ++i)
-        colv[i] = (c->hsmall[o_h1 + i] + c->hsmall[o_h2 + i]) * sc[i] / sc[j];
+        colv[i] = (c->hsmall[o_h1 + i] + (second ? c->hsmall[o_h2 + i] : 0.0)) * sc[i] / sc[j];
       double wn2 = c->hsmall[o_n2];
-      const bool deferred = q <= 8;   // second correction not yet applied
-      if (deferred)
+      if (deferred && second)
         for (int i = 0; i < q; ++i) wn2 -= c->hsmall[o_h2 + i] * c->hsmall[o_h2 + i] * sc[i] * sc[i];
       const double wn = sqrt(std::max(wn2, 0.0));
       if (!isfinite(wn)) {
@@ -2226,7 +2240,7 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
         stop = true;
         break;
       }
-      if (deferred) {
+      if (deferred && second) {
         ProfScope ps(c, AAO_K_KRYLOV);
         HIPCHK(c, launch_axpy_dot(c->V, nm, v0, q, c->dsmall + o_h2, w, nm, c->part, 0,
                                   c->stream));

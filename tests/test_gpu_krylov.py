@@ -14,6 +14,11 @@ passes of that step.  Checked here:
   error stays within the conditioning bound;
 * at tol = 1e-14 (unreachable by the bound) the solve runs the passes and
   reaches the same solution.
+The solves at tol = 1e-8 also take the selective second correction: after the
+first Gram-Schmidt pass the second-pass dots give the cosines of w' with the
+basis, and when all are below 1e-3 tol (here about 1e-12 after the first step)
+w' is kept without the second correction; the accuracy checks above cover that
+path (at tol = 1e-14 it is never taken).
 """
 import numpy as np
 import pytest
