@@ -63,7 +63,10 @@ def parse():
                     help="skip the heat2d 511^2 x 512 and 255^2 x 256 legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=32)
+    ap.add_argument("--cpu-sample-steps", type=int, default=256,
+                    help="time levels of the main workload in the CPU baseline's sequential "
+                         "backward Euler (256 = the whole heat3d 127^3 x 256 workload, about "
+                         "10 s on one core)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain-copy kernel used to calibrate PMC byte counters")
     return ap.parse_args()
@@ -71,11 +74,12 @@ def parse():
 
 def dst_path(w, prec):
     """Which DST-I product the library runs: 'fold2' (FP64, odd m, padded
-    length a multiple of 128), 'fold' (2D/3D FP64/FP32 otherwise), 'dense'."""
+    length a multiple of 128), 'fold' (2D/3D otherwise, BF16x3 included),
+    'dense' (1D)."""
     P = -(-w.m1 // 64) * 64
     if w.dim >= 2 and prec == "fp64" and w.m1 % 2 == 1 and P % 128 == 0:
         return "fold2"
-    if w.dim >= 2 and prec in ("fp64", "fp32"):
+    if w.dim >= 2:
         return "fold"
     return "dense"
 
@@ -163,9 +167,9 @@ def class_bytes(w, prec):
     nm = w.n * w.m
     spec = (w.n // 2 + 1) * 2 * w.m * sT
     spec_real_ends = w.n * w.m * sT     # (n/2 - 1) complex + 2 real blocks
-    # the folded product (2D/3D, FP64/FP32) skips the zero imaginary planes of
-    # the two real blocks; the dense product moves every plane
-    folded = w.dim >= 2 and prec in ("fp64", "fp32")
+    # the folded product (2D/3D) skips the zero imaginary planes of the two
+    # real blocks; the dense product (1D) moves every plane
+    folded = w.dim >= 2
     return {"apply_L": 2 * nm * 8,
             "time_fwd": nm * 8 + spec,
             "time_inv": spec_real_ends + nm * 8,
@@ -545,7 +549,8 @@ def dst_roofline(w, prec, prof):
     avg_s = dst_ms / 1e3 / max(dst_n, 1)
     path = dst_path(w, prec)
     nbytes = class_bytes(w, prec)["dst"]
-    ex_flops = dst_flops_per_launch(w, prec)
+    # BF16x3 runs three BF16 products (lo*hi, hi*lo, hi*hi) per product
+    ex_flops = dst_flops_per_launch(w, prec) * (3 if prec == "bf16x3" else 1)
     peak_fl = {"fp64": PEAKS["fp64_TFs"], "fp32": PEAKS["fp32_TFs"],
                "bf16x3": PEAKS["bf16_TFs"]}[prec]
     traffic = measured_traffic("k_fold.hip", w.name, prec, path) if path != "dense" else None
