@@ -88,11 +88,13 @@ def dst_launch_mix(w, prec):
     """(launches, products) of the DST class per application of P^{-1}: one
     product per spatial axis each way, 2 dim in all.  On the two-level fold
     path with a last-axis padded length of 128 or 256 the last axis' forward
-    product, shifted divide and inverse product run as one launch."""
+    product, shifted divide and inverse product run as one launch; in 3D with
+    P1 = P2 = 128 the x and y products run as one launch each way."""
     products = 2 * w.dim
     P = -(-w.m1 // 64) * 64
     fused = dst_path(w, prec) == "fold2" and P in (128, 256)
-    return products - (1 if fused else 0), products
+    slab = dst_path(w, prec) == "fold2" and w.dim == 3 and P == 128
+    return products - (1 if fused else 0) - (2 if slab else 0), products
 
 
 def dst_product_flops(w, prec):
@@ -195,22 +197,30 @@ def kernel_table(w, prec, prof):
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-def measured_traffic(kernel_file, workload, prec, dst_kind):
-    """HBM bytes per launch of the DST kernel from the committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE summary, if it was taken on the current source of
-    that kernel (sha256 recorded in the summary); else None."""
+DST_SOURCES = ("k_fold.hip", "k_slab.hip")
+
+
+def dst_source_sha():
+    """sha256 over the DST kernels' sources (in DST_SOURCES order)."""
     import hashlib
+    h = hashlib.sha256()
+    for f in DST_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2002_01108_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, prec, dst_kind):
+    """HBM bytes per launch of the DST class from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, if it was taken on the current sources of
+    those kernels (sha256 recorded in the summary); else None."""
     import re
     path = os.path.join(PROFILES, f"pmc_dst_{dst_kind}_{prec}_{workload}.md")
-    src = os.path.join(ROOT, "paper_2002_01108_amd", "csrc", kernel_file)
-    if not (os.path.exists(path) and os.path.exists(src)):
+    if not os.path.exists(path):
         return None
     text = open(path).read()
     sha = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
     tb = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not (sha and tb):
-        return None
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != sha.group(1):
+    if not (sha and tb) or dst_source_sha() != sha.group(1):
         return None
     return float(tb.group(1))
 
@@ -553,7 +563,7 @@ def dst_roofline(w, prec, prof):
     ex_flops = dst_flops_per_launch(w, prec) * (3 if prec == "bf16x3" else 1)
     peak_fl = {"fp64": PEAKS["fp64_TFs"], "fp32": PEAKS["fp32_TFs"],
                "bf16x3": PEAKS["bf16_TFs"]}[prec]
-    traffic = measured_traffic("k_fold.hip", w.name, prec, path) if path != "dense" else None
+    traffic = measured_traffic(w.name, prec, path) if path != "dense" else None
     launches, products = dst_launch_mix(w, prec)
     mix = (f"{products} DST-I mode products in {launches} launches per P^-1"
            + (", the last axis' forward, divide and inverse fused" if launches < products else ""))

@@ -26,6 +26,12 @@ FLAGS = [
 ]
 
 
+# per-file additions: the slab kernel runs one wave per SIMD, where the
+# compiler's default MFMA form puts the accumulators in AGPRs and copies the
+# loop-carried ones to VGPRs and back on every K step
+FILE_FLAGS = {"k_slab.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
                   if f.endswith((".hip", ".cpp")))
@@ -33,9 +39,10 @@ def sources():
 
 def _compile(src):
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    extra = FILE_FLAGS.get(os.path.basename(src), [])
+    cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
-        cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", src, "-o", obj]
+        cmd = [HIPCC, *FLAGS, *extra, "-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -471,6 +471,30 @@ hipError_t fold_product(aao_ctx* c, int d, const void* in, void* out, double* co
                                 d != 0, lam, t1, t2, t3, c->stream);
 }
 
+// Both in-plane products (x, y) of a 3D FP64 spectrum in one in-place launch:
+// P1 = P2 = 128 and m1 = m2 odd (one set of second-fold quarter tables).
+bool use_xy(const aao_ctx* c) {
+  const Geometry& g = c->g;
+  return g.dim == 3 && c->prec == AAO_FP64 && g.P1 == 128 && g.P2 == 128 && g.m1 % 2 == 1 &&
+         g.m1 == g.m2 && c->Fq64[0];
+}
+
+hipError_t xy_product(aao_ctx* c, void* spec, bool real_ends) {
+  ProfScope ps(c, AAO_K_DST);
+  const Geometry& g = c->g;
+  SlabArgs a;
+  a.PS = g.PS;
+  a.nk = real_ends ? g.nh - 1 : g.nh;
+  a.packed = real_ends ? 1 : 0;
+  a.m1 = g.m1;
+  a.m2 = g.m2;
+  a.m3 = g.m3;
+  a.P1 = g.P1;
+  a.P2 = g.P2;
+  a.P3 = g.P3;
+  return launch_dst_xy((double*)spec, c->Fq64[0], a, c->stream);
+}
+
 // One mode product along axis d (0 = x, 1 = y, 2 = z) from `in` to `out`
 // as a dense batched GEMM (1D).
 hipError_t mode_product(aao_ctx* c, int d, const void* in, void* out) {
@@ -558,6 +582,21 @@ aao_status dst_solve(aao_ctx* c, void** cur, void** other, bool mean, bool real_
       HIPCHK(c, fold_product(c, 0, *cur, *cur, nullptr, real_ends));
       HIPCHK(c, fused_last(c, *cur, *cur, tm, real_ends));
       HIPCHK(c, fold_product(c, 0, *cur, *cur, nullptr, real_ends));
+      return AAO_OK;
+    }
+    if (use_xy(c)) {
+      // x and y in one in-place launch each way around the z products
+      HIPCHK(c, xy_product(c, *cur, real_ends));
+      if (fuse) {
+        HIPCHK(c, fused_last(c, *cur, *other, tm, real_ends));
+        std::swap(*cur, *other);
+      } else {
+        HIPCHK(c, fold_product(c, 2, *cur, *other, tm, real_ends));
+        std::swap(*cur, *other);
+        HIPCHK(c, fold_product(c, 2, *cur, *other, nullptr, real_ends));
+        std::swap(*cur, *other);
+      }
+      HIPCHK(c, xy_product(c, *cur, real_ends));
       return AAO_OK;
     }
     for (int d = 0; d < dim; ++d) {
@@ -2207,9 +2246,13 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
       // (for w' the Arnoldi relation holds as computed); the basis is then
       // orthogonal to that level, which moves the least-squares residual by a
       // relative amount far below tol, and the second correction's pass over
-      // w and W is saved.
+      // w and W is saved.  Right preconditioning only: with left
+      // preconditioning the stop is on the preconditioned residual and the
+      // reported true residual of that iterate moves by far more than the
+      // basis does when P^{-1} is ill-conditioned (the block-circulant
+      // epsilon = 1 case: 10 % at cosines of 1e-10).
       bool second = true;
-      if (deferred && tol > 0.0) {
+      if (deferred && tol > 0.0 && !left) {
         const double n1 = sqrt(std::max(c->hsmall[o_n2], 0.0));
         double cmax = 0.0;
         for (int i = 0; i < q; ++i) cmax = std::max(cmax, fabs(c->hsmall[o_h2 + i]) * sc[i]);

@@ -1,0 +1,207 @@
+// Both in-plane DST-I products of a 3D spectrum in one pass (constant
+// coefficient Step 2, Section 4, eq. (blockdiaginv)).
+// This file is compiled with the MFMA results in VGPRs (build.py): left to
+// its default the compiler keeps them in AGPRs here and copies the loop
+// accumulators between the two register files on every K step.
+#include "common.h"
+
+namespace aao {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Both in-plane products of a 3D spectrum (x and y, P1 = P2 = 128, odd m1 and
+// m2 with the same quarter tables) in one pass: a z slab of one plane
+// (128 x 128 FP64 = 128 KB) sits in LDS while the x product (rows) and then
+// the y product (columns) run on it, so the spectrum crosses HBM once for two
+// products instead of twice.  The two products commute (S_y X S_x), so the
+// same launch serves the forward and the inverse sweep.  Both use the second
+// fold: element j = 2t + par < 64 of a row (column) pairs with its mirror
+// m-1-j into x_j +- x_{m-1-j} (the middle keeps x_j alone in +, beyond the
+// pairs both are zero), the quarter tables ([4][32][32]: A+, A-, B+, B-)
+// multiply them, and output r = 2q + s2 < h takes O = table s2 and
+// E = table 2 + s2: y_r = O + E, y_{m-1-r} = O - E.
+// LDS: the slab (128 KB; element (row, col) at row * 128 + (col ^ (row & 15)),
+// so that 16 rows of one column, as well as 16 columns of one row, fall on
+// distinct banks) and the tables (32 KB, loaded once per block): 160 KB, one
+// block per CU.  No global load in the K loops: a table wait there would also
+// wait for the next slab's prefetch (the vector memory counter is in order).
+// A block of 8 waves (two per SIMD, so that one wave's matrix-core work covers
+// the other's LDS latency) walks slabs (xcd_strips): it stages the slab
+// prefetched into registers, loads the next one while it computes, and
+// writes the result back in place.  Phase x: wave w owns rows 16w .. 16w+15
+// (the data as the MFMA A operand, the table as B); phase y: wave w owns
+// columns 16w .. 16w+15 (the table as A, the data as B).  A wave reads and
+// writes only its own rows (columns) within a phase, so one barrier separates
+// the phases.  Padding (rows >= m2, columns >= m1) must be zero on input and
+// stays zero.
+constexpr int XYP = 128, XYQ = 32;
+
+__device__ __forceinline__ int xy_at(int row, int col) { return row * XYP + (col ^ (row & 15)); }
+
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_dst_xy(
+    double* __restrict__ spec, const double* __restrict__ tab, SlabArgs a) {
+  __shared__ double X[XYP * XYP];
+  __shared__ double T[4 * XYQ * XYQ];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // lane coordinates of the MFMA fragments, renewed opaquely for every slab
+  // (below) so that the compiler does not hoist the phases' per-lane
+  // addresses and store masks out of the slab loop and hold them in registers
+  int lr = lane & 15, lk = lane >> 4;
+  const int nslab = a.nk * 2 * a.m3;
+  const int64_t zs = (int64_t)XYP * XYP;   // one z slab of a plane
+
+  for (int i = tid; i < 4 * XYQ * XYQ; i += 512) T[i] = tab[i];
+
+  auto slab_base = [&](int s) -> int64_t {
+    const int z = s % a.m3, rest = s / a.m3, pl = rest & 1, k = rest >> 1;
+    const int64_t b0 = (int64_t)k * 2 * a.PS;
+    const int64_t b = pl ? ((a.packed && k == 0) ? (int64_t)a.nk * 2 * a.PS : b0 + a.PS) : b0;
+    return b + (int64_t)z * zs;
+  };
+  // thread -> rows w + 8 i (i < 16), columns 2 lane, 2 lane + 1: a wave-uniform
+  // row address plus one per-lane offset, so no per-row address registers
+  const int loff = w * (XYP / 2) + lane;   // in double2
+  double2 pf[16];
+  auto load = [&](int s) {
+    const double* sb = spec + slab_base(s);
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      pf[i] = reinterpret_cast<const double2*>(sb + (int64_t)8 * i * XYP)[loff];
+  };
+  // table fragment: lane (lr, lk) takes T[tb][q = 16 qt + lr][t = 4 ks + lk]
+  auto tfrag = [&](int tb, int qt, int ks) {
+    return T[(tb * XYQ + 16 * qt + lr) * XYQ + 4 * ks + lk];
+  };
+  // combos of element j with its mirror m-1-j (x_j, x_m: their values)
+  auto combo = [](int j, int m, double xj, double xm, double& p, double& q) {
+    const int jm = m - 1 - j;
+    p = jm > j ? xj + xm : (jm == j ? xj : 0.0);
+    q = jm > j ? xj - xm : 0.0;
+  };
+
+  const StripRange sr = xcd_strips(nslab);
+  if (sr.first < sr.end) load(sr.first);
+  for (int s = sr.first; s < sr.end; s += sr.step) {
+    int lo = lane;
+    asm volatile("" : "+v"(lo));
+    lr = lo & 15;
+    lk = lo >> 4;
+    __syncthreads();   // the previous slab's stores have read X (and T is in place)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = w + 8 * i;
+      X[xy_at(row, 2 * lane)] = pf[i].x;
+      X[xy_at(row, 2 * lane + 1)] = pf[i].y;
+    }
+    if (s + sr.step < sr.end) load(s + sr.step);
+    __syncthreads();
+
+    // ---- phase x: rows R0 .. R0 + 15 (rows are independent: a tile's
+    // outputs replace its inputs once its K loop is done)
+    {
+      const int m = a.m1, h = (m + 1) / 2, R0 = 16 * w;
+      d4 acc[4][2];   // [table][q tile]
+#pragma unroll
+      for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+        for (int qt = 0; qt < 2; ++qt) acc[tb][qt] = d4{0, 0, 0, 0};
+      const int row = R0 + lr;
+#pragma unroll 2
+      for (int ks = 0; ks < 8; ++ks) {
+        const int t = 4 * ks + lk;
+        double op[4];
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+          const int j = 2 * t + par;
+          combo(j, m, X[xy_at(row, j)], X[xy_at(row, m - 1 - j)], op[2 * par], op[2 * par + 1]);
+        }
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+          for (int qt = 0; qt < 2; ++qt)
+            acc[tb][qt] = __builtin_amdgcn_mfma_f64_16x16x4f64(op[tb], tfrag(tb, qt, ks),
+                                                              acc[tb][qt], 0, 0, 0);
+      }
+      // lane element v: row R0 + lk + 4 v, quarter index q = 16 qt + lr:
+      // outputs r = 2 q + s2 and m-1-r of that row
+#pragma unroll
+      for (int qt = 0; qt < 2; ++qt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int s2 = 0; s2 < 2; ++s2) {
+            const int orow = R0 + lk + 4 * v;
+            const int r = 2 * lr + 32 * qt + s2, rb = m - 1 - r;
+            const double O = acc[s2][qt][v], E = acc[2 + s2][qt][v];
+            if (r < h) X[xy_at(orow, r)] = O + E;
+            if (r < h && rb > r) X[xy_at(orow, rb)] = O - E;
+          }
+    }
+    __syncthreads();
+    // ---- phase y: columns C0 .. C0 + 15 (columns are independent)
+    {
+      const int m = a.m2, h = (m + 1) / 2, C0 = 16 * w;
+      d4 acc[4][2];   // [table][q tile]
+#pragma unroll
+      for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+        for (int qt = 0; qt < 2; ++qt) acc[tb][qt] = d4{0, 0, 0, 0};
+      const int col = C0 + lr;
+#pragma unroll 2
+      for (int ks = 0; ks < 8; ++ks) {
+        const int t = 4 * ks + lk;
+        double op[4];
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+          const int j = 2 * t + par;
+          combo(j, m, X[xy_at(j, col)], X[xy_at(m - 1 - j, col)], op[2 * par], op[2 * par + 1]);
+        }
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+          for (int qt = 0; qt < 2; ++qt)
+            acc[tb][qt] = __builtin_amdgcn_mfma_f64_16x16x4f64(tfrag(tb, qt, ks), op[tb],
+                                                              acc[tb][qt], 0, 0, 0);
+      }
+      // lane element v: quarter index q = 16 qt + lk + 4 v, column C0 + lr:
+      // output rows r = 2 q + s2 and m-1-r of that column
+#pragma unroll
+      for (int qt = 0; qt < 2; ++qt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int s2 = 0; s2 < 2; ++s2) {
+            const int r = 2 * lk + 32 * qt + 8 * v + s2, rb = m - 1 - r;
+            const double O = acc[s2][qt][v], E = acc[2 + s2][qt][v];
+            if (r < h) X[xy_at(r, col)] = O + E;
+            if (r < h && rb > r) X[xy_at(rb, col)] = O - E;
+          }
+    }
+    __syncthreads();
+    double* db = spec + slab_base(s);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = w + 8 * i;
+      reinterpret_cast<double2*>(db + (int64_t)8 * i * XYP)[loff] =
+          double2{X[xy_at(row, 2 * lane)], X[xy_at(row, 2 * lane + 1)]};
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_dst_xy(double* spec, const double* tab, const SlabArgs& a, hipStream_t s) {
+  if (!spec || !tab || a.nk < 1 || a.m3 < 1 || a.m1 % 2 == 0 || a.m2 % 2 == 0 ||
+      a.m1 <= XYP / 2 || a.m1 > XYP || a.m2 <= XYP / 2 || a.m2 > XYP || a.P1 != XYP ||
+      a.P2 != XYP || a.P3 < a.m3 || a.PS != (int64_t)a.P1 * a.P2 * a.P3)
+    return hipErrorInvalidValue;
+  const int64_t nslab = (int64_t)a.nk * 2 * a.m3;
+  if (nslab > 0x7fffffff) return hipErrorInvalidConfiguration;
+  static const int resident = persistent_grid(k_dst_xy, 512);
+  if (resident < 8) return hipErrorInvalidDeviceFunction;
+  hipLaunchKernelGGL(k_dst_xy, dim3(strip_grid(resident, nslab)), dim3(512), 0, s, spec, tab, a);
+  return hipGetLastError();
+}
+
+}  // namespace aao

@@ -41,6 +41,12 @@ def test_dst_launch_mix_and_flops():
     dense32 = 2.0 * w32.m1 ** 2 * w32.n * (w32.m // w32.m1)
     assert abs(bench.dst_product_flops(w32, "fp32") / dense32 - 0.5) < 0.002
     assert abs(bench.dst_flops_per_launch(w, "fp64") - 2.841e9) < 0.001e9
+    # 127^3 x 256 FP64: x and y in one slab launch each way around the fused
+    # z launch: 3 launches for 6 products; BF16x3 folds every axis separately
+    w3 = W.WORKLOADS["heat3d_127x256"]
+    assert bench.dst_launch_mix(w3, "fp64") == (3, 6)
+    assert bench.dst_launch_mix(w3, "bf16x3") == (6, 6)
+    assert bench.dst_path(w3, "bf16x3") == "fold"
 
 
 def test_record_only_when_checking():

@@ -318,6 +318,8 @@ RECT = [  # (dim, (m1, m2[, m3]), n, eps)
     (3, (13, 9, 5), 8, 0.25),
     (3, (65, 20, 33), 4, 0.2),
     (3, (9, 33, 130), 4, 0.2),   # 3D walk: three z ranges (64 + 64 + 2 planes)
+    (3, (127, 127, 3), 4, 0.2),  # FP64: x and y in one slab launch (P1 = P2 = 128, m1 = m2)
+    (3, (65, 65, 2), 8, 0.15),   # the same at the shortest length accepted there
 ]
 
 
@@ -336,6 +338,24 @@ def test_rect_apply_A_and_Pinv(dim, ms, n, eps):
     v = _rand((n, m), 40 + dim)
     assert rel(host(s.apply_A(dev(v))), heat.apply_L(K, tau, v)) < 1e-12
     assert rel(host(s.apply_Pinv(dev(v))), heat.apply_Pinv(K, tau, eps, v)) < 1e-11
+
+
+@pytest.mark.parametrize("dim,ms,n,eps", [RECT[4], RECT[6], RECT[7]])
+def test_rect_step2(dim, ms, n, eps):
+    """Step 2 alone on rectangular 3D grids (the x-y slab launch with unpacked
+    frequency blocks on RECT[6], RECT[7]) against the oracle's block solves."""
+    K = heat.stiffness_rect(ms)
+    m = K.shape[0]
+    tau = 1.0 / n
+    rng = np.random.default_rng(41)
+    yt = rng.standard_normal((n // 2 + 1, m, 2))
+    yt[0, :, 1] = 0.0
+    yt[-1, :, 1] = 0.0
+    s = rect_solver(dim, ms, n, eps)
+    zt = host(s.step2(dev(yt)))
+    lam = heat.lambdas(n, eps)[: n // 2 + 1]
+    want = heat.step2(K, tau, lam, yt[..., 0] + 1j * yt[..., 1])
+    assert rel(zt[..., 0] + 1j * zt[..., 1], want) <= 1e-11
 
 
 @pytest.mark.parametrize("dim,ms,n,eps", [RECT[1], RECT[4]])
