@@ -23,8 +23,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // E = table 2 + s2: y_r = O + E, y_{m-1-r} = O - E.
 // LDS: the slab (128 KB; element (row, col) at row * 128 + (col ^ (row & 15)),
 // so that 16 rows of one column, as well as 16 columns of one row, fall on
-// distinct banks) and the tables (32 KB, loaded once per block): 160 KB, one
-// block per CU.  No global load in the K loops: a table wait there would also
+// distinct banks) and the tables (32 KB, loaded once per block, swizzled the
+// same way): 160 KB, one block per CU.  No global load in the K loops: a table wait there would also
 // wait for the next slab's prefetch (the vector memory counter is in order).
 // A block of 8 waves (two per SIMD, so that one wave's matrix-core work covers
 // the other's LDS latency) walks slabs (xcd_strips): it stages the slab
@@ -51,7 +51,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int nslab = a.nk * 2 * a.m3;
   const int64_t zs = (int64_t)XYP * XYP;   // one z slab of a plane
 
-  for (int i = tid; i < 4 * XYQ * XYQ; i += 512) T[i] = tab[i];
+  // tables: element (tb, q, t) at (tb XYQ + q) XYQ + (t ^ (q & 15)), so that the
+  // 16 q rows of a fragment read fall on distinct banks
+  for (int i = tid; i < 4 * XYQ * XYQ; i += 512) {
+    const int t = i % XYQ, q = (i / XYQ) % XYQ;
+    T[i - t + (t ^ (q & 15))] = tab[i];
+  }
 
   auto slab_base = [&](int s) -> int64_t {
     const int z = s % a.m3, rest = s / a.m3, pl = rest & 1, k = rest >> 1;
@@ -70,8 +75,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       pf[i] = reinterpret_cast<const double2*>(sb + (int64_t)8 * i * XYP)[loff];
   };
   // table fragment: lane (lr, lk) takes T[tb][q = 16 qt + lr][t = 4 ks + lk]
+  // (q & 15 = lr)
   auto tfrag = [&](int tb, int qt, int ks) {
-    return T[(tb * XYQ + 16 * qt + lr) * XYQ + 4 * ks + lk];
+    return T[(tb * XYQ + 16 * qt + lr) * XYQ + ((4 * ks + lk) ^ lr)];
   };
   // combos of element j with its mirror m-1-j (x_j, x_m: their values)
   auto combo = [](int j, int m, double xj, double xm, double& p, double& q) {
