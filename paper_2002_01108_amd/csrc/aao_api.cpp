@@ -86,6 +86,7 @@ struct aao_ctx {
   // and their transposes [table][t][q] for the fused forward-divide-inverse kernel
   double* Fq64[3] = {nullptr, nullptr, nullptr};
   double* FqT64[3] = {nullptr, nullptr, nullptr};
+  float* FqT32[3] = {nullptr, nullptr, nullptr};   // FqT64 in FP32 (the FP32 slab kernel)
 
   // spectrum workspace (ping-pong), sized for the current precision
   void* specA = nullptr;
@@ -471,12 +472,12 @@ hipError_t fold_product(aao_ctx* c, int d, const void* in, void* out, double* co
                                 d != 0, lam, t1, t2, t3, c->stream);
 }
 
-// Both in-plane products (x, y) of a 3D FP64 spectrum in one in-place launch:
-// P1 = P2 = 128 and m1 = m2 odd (one set of second-fold quarter tables).
+// Both in-plane products (x, y) of a 3D FP64 or FP32 spectrum in one in-place
+// launch: P1 = P2 = 128 and m1 = m2 odd (one set of second-fold quarter tables).
 bool use_xy(const aao_ctx* c) {
   const Geometry& g = c->g;
-  return g.dim == 3 && c->prec == AAO_FP64 && g.P1 == 128 && g.P2 == 128 && g.m1 % 2 == 1 &&
-         g.m1 == g.m2 && c->Fq64[0];
+  return g.dim == 3 && (c->prec == AAO_FP64 || c->prec == AAO_FP32) && g.P1 == 128 &&
+         g.P2 == 128 && g.m1 % 2 == 1 && g.m1 == g.m2 && c->Fq64[0] && c->FqT32[0];
 }
 
 hipError_t xy_product(aao_ctx* c, void* spec, bool real_ends) {
@@ -492,7 +493,8 @@ hipError_t xy_product(aao_ctx* c, void* spec, bool real_ends) {
   a.P1 = g.P1;
   a.P2 = g.P2;
   a.P3 = g.P3;
-  return launch_dst_xy((double*)spec, c->Fq64[0], a, c->stream);
+  if (c->prec == AAO_FP64) return launch_dst_xy((double*)spec, c->Fq64[0], a, c->stream);
+  return launch_dst_xy((float*)spec, c->FqT32[0], a, c->stream);
 }
 
 // One mode product along axis d (0 = x, 1 = y, 2 = z) from `in` to `out`
@@ -1311,6 +1313,8 @@ aao_status aao_setup(int dim, int m1, int m2, int m3, int n, double T, double ep
           for (int t = 0; t < Hq; ++t)
             fqt[((size_t)tb * Hq + t) * Hq + q] = fq[((size_t)tb * Hq + q) * Hq + t];
       if ((st = upload(c, &c->FqT64[d], fqt)) != AAO_OK) return bail(st);
+      std::vector<float> fqt32(fqt.begin(), fqt.end());
+      if ((st = upload(c, &c->FqT32[d], fqt32)) != AAO_OK) return bail(st);
     }
   }
   if ((st = ensure_spec(c)) != AAO_OK) return bail(st);

@@ -187,8 +187,7 @@ hipError_t launch_dst_fold_bf16x3(const float* in, float* out, const uint16_t* c
 
 // Both in-plane DST-I products (x, then y) of every z slab of a 3D spectrum,
 // in place, FP64, P1 = P2 = 128, odd m1, m2 in (64, 128] with the same
-// second-fold quarter tables `tab` ([4][32][32]: A+, A-, B+, B-; equal m1 and
-// m2).  Slabs: the nk frequency blocks' two planes (packed as in FoldArgs)
+// second-fold quarter tables ([4][32][32]: A+, A-, B+, B-; equal m1 and m2).  Slabs: the nk frequency blocks' two planes (packed as in FoldArgs)
 // times z < m3; padding must be zero on input and stays zero.
 struct SlabArgs {
   int64_t PS;     // plane size (P1 P2 P3)
@@ -197,7 +196,10 @@ struct SlabArgs {
   int m1, m2, m3;
   int P1, P2, P3;
 };
-hipError_t launch_dst_xy(double* spec, const double* tab, const SlabArgs& a, hipStream_t s);
+// FP64: tab = the [4][32][32] quarter tables as [tb][q][t]; FP32: the same
+// tables in FP32, transposed to [tb][t][q].
+template <typename F>
+hipError_t launch_dst_xy(F* spec, const F* tab, const SlabArgs& a, hipStream_t s);
 
 // Two-level fold for odd m (P_d a multiple of 128): tabs = [4][Hq][Hq], Hq = P_d/4,
 // the quarter tables A+, A-, B+, B- (rows q: output rows 2q for +, 2q+1 for -;

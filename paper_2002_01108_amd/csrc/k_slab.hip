@@ -9,6 +9,7 @@ namespace aao {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 // Both in-plane products of a 3D spectrum (x and y, P1 = P2 = 128, odd m1 and
 // m2 with the same quarter tables) in one pass: a z slab of one plane
@@ -35,14 +36,59 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // writes only its own rows (columns) within a phase, so one barrier separates
 // the phases.  Padding (rows >= m2, columns >= m1) must be zero on input and
 // stays zero.
+// FP32 (the FP32 preconditioner): the same with v_mfma_f32_16x16x4f32, 80 KB of
+// LDS (two blocks per CU), the slab swizzled by (row & 15) << 3 (64 banks of
+// 32-bit words: the 16 rows of a fragment read land in pairs on 32 banks) and
+// the tables transposed ([tb][t][q], q contiguous, q ^ 16 ((t >> 1) & 1)).
 constexpr int XYP = 128, XYQ = 32;
 
-__device__ __forceinline__ int xy_at(int row, int col) { return row * XYP + (col ^ (row & 15)); }
+template <typename T> struct Slab;
+template <> struct Slab<double> {
+  typedef d4 V;
+  typedef double2 T2;
+  static __device__ __forceinline__ V mfma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of accumulator element v (16x16 FP64 output layout)
+  static __device__ __forceinline__ int orow(int lk, int v) { return lk + 4 * v; }
+  static __device__ __forceinline__ int at(int row, int col) {
+    return row * XYP + (col ^ (row & 15));
+  }
+  // tables stored [tb][q][t ^ (q & 15)] from the [tb][q][t] FP64 quarter tables
+  static __device__ __forceinline__ int tab_at(int tb, int q, int t) {
+    return (tb * XYQ + q) * XYQ + (t ^ (q & 15));
+  }
+  static __device__ __forceinline__ int tab_src(int tb, int q, int t) {
+    return (tb * XYQ + q) * XYQ + t;
+  }
+};
+template <> struct Slab<float> {
+  typedef f4 V;
+  typedef float2 T2;
+  static __device__ __forceinline__ V mfma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int orow(int lk, int v) { return 4 * lk + v; }
+  static __device__ __forceinline__ int at(int row, int col) {
+    return row * XYP + (col ^ ((row & 15) << 3));
+  }
+  // tables stored [tb][t][q ^ 16 ((t >> 1) & 1)] from the [tb][t][q] FP32 ones
+  static __device__ __forceinline__ int tab_at(int tb, int q, int t) {
+    return (tb * XYQ + t) * XYQ + (q ^ (((t >> 1) & 1) << 4));
+  }
+  static __device__ __forceinline__ int tab_src(int tb, int q, int t) {
+    return (tb * XYQ + t) * XYQ + q;
+  }
+};
 
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_dst_xy(
-    double* __restrict__ spec, const double* __restrict__ tab, SlabArgs a) {
-  __shared__ double X[XYP * XYP];
-  __shared__ double T[4 * XYQ * XYQ];
+template <typename F>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(F) == 8 ? 2 : 4)))
+void k_dst_xy(F* __restrict__ spec, const F* __restrict__ tab, SlabArgs a) {
+  using S = Slab<F>;
+  using V = typename S::V;
+  using T2 = typename S::T2;
+  __shared__ F X[XYP * XYP];
+  __shared__ F T[4 * XYQ * XYQ];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   // lane coordinates of the MFMA fragments, renewed opaquely for every slab
   // (below) so that the compiler does not hoist the phases' per-lane
@@ -51,11 +97,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int nslab = a.nk * 2 * a.m3;
   const int64_t zs = (int64_t)XYP * XYP;   // one z slab of a plane
 
-  // tables: element (tb, q, t) at (tb XYQ + q) XYQ + (t ^ (q & 15)), so that the
-  // 16 q rows of a fragment read fall on distinct banks
+  // tables, swizzled so that the 16 q rows of a fragment read fall on distinct banks
   for (int i = tid; i < 4 * XYQ * XYQ; i += 512) {
-    const int t = i % XYQ, q = (i / XYQ) % XYQ;
-    T[i - t + (t ^ (q & 15))] = tab[i];
+    const int tb = i / (XYQ * XYQ), q = (i / XYQ) % XYQ, t = i % XYQ;
+    T[S::tab_at(tb, q, t)] = tab[S::tab_src(tb, q, t)];
   }
 
   auto slab_base = [&](int s) -> int64_t {
@@ -66,24 +111,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   };
   // thread -> rows w + 8 i (i < 16), columns 2 lane, 2 lane + 1: a wave-uniform
   // row address plus one per-lane offset, so no per-row address registers
-  const int loff = w * (XYP / 2) + lane;   // in double2
-  double2 pf[16];
+  const int loff = w * (XYP / 2) + lane;   // in two-element vectors
+  T2 pf[16];
   auto load = [&](int s) {
-    const double* sb = spec + slab_base(s);
+    const F* sb = spec + slab_base(s);
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-      pf[i] = reinterpret_cast<const double2*>(sb + (int64_t)8 * i * XYP)[loff];
+    for (int i = 0; i < 16; ++i) pf[i] = reinterpret_cast<const T2*>(sb + (int64_t)8 * i * XYP)[loff];
   };
-  // table fragment: lane (lr, lk) takes T[tb][q = 16 qt + lr][t = 4 ks + lk]
-  // (q & 15 = lr)
-  auto tfrag = [&](int tb, int qt, int ks) {
-    return T[(tb * XYQ + 16 * qt + lr) * XYQ + ((4 * ks + lk) ^ lr)];
-  };
+  // table fragment: lane (lr, lk) takes table tb at q = 16 qt + lr, t = 4 ks + lk
+  auto tfrag = [&](int tb, int qt, int ks) { return T[S::tab_at(tb, 16 * qt + lr, 4 * ks + lk)]; };
   // combos of element j with its mirror m-1-j (x_j, x_m: their values)
-  auto combo = [](int j, int m, double xj, double xm, double& p, double& q) {
+  auto combo = [](int j, int m, F xj, F xm, F& p, F& q) {
     const int jm = m - 1 - j;
-    p = jm > j ? xj + xm : (jm == j ? xj : 0.0);
-    q = jm > j ? xj - xm : 0.0;
+    p = jm > j ? xj + xm : (jm == j ? xj : F(0));
+    q = jm > j ? xj - xm : F(0);
   };
 
   const StripRange sr = xcd_strips(nslab);
@@ -97,8 +138,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int row = w + 8 * i;
-      X[xy_at(row, 2 * lane)] = pf[i].x;
-      X[xy_at(row, 2 * lane + 1)] = pf[i].y;
+      X[S::at(row, 2 * lane)] = pf[i].x;
+      X[S::at(row, 2 * lane + 1)] = pf[i].y;
     }
     if (s + sr.step < sr.end) load(s + sr.step);
     __syncthreads();
@@ -107,29 +148,27 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // outputs replace its inputs once its K loop is done)
     {
       const int m = a.m1, h = (m + 1) / 2, R0 = 16 * w;
-      d4 acc[4][2];   // [table][q tile]
+      V acc[4][2];   // [table][q tile]
 #pragma unroll
       for (int tb = 0; tb < 4; ++tb)
 #pragma unroll
-        for (int qt = 0; qt < 2; ++qt) acc[tb][qt] = d4{0, 0, 0, 0};
+        for (int qt = 0; qt < 2; ++qt) acc[tb][qt] = V{0, 0, 0, 0};
       const int row = R0 + lr;
 #pragma unroll 2
       for (int ks = 0; ks < 8; ++ks) {
         const int t = 4 * ks + lk;
-        double op[4];
+        F op[4];
 #pragma unroll
         for (int par = 0; par < 2; ++par) {
           const int j = 2 * t + par;
-          combo(j, m, X[xy_at(row, j)], X[xy_at(row, m - 1 - j)], op[2 * par], op[2 * par + 1]);
+          combo(j, m, X[S::at(row, j)], X[S::at(row, m - 1 - j)], op[2 * par], op[2 * par + 1]);
         }
 #pragma unroll
         for (int tb = 0; tb < 4; ++tb)
 #pragma unroll
-          for (int qt = 0; qt < 2; ++qt)
-            acc[tb][qt] = __builtin_amdgcn_mfma_f64_16x16x4f64(op[tb], tfrag(tb, qt, ks),
-                                                              acc[tb][qt], 0, 0, 0);
+          for (int qt = 0; qt < 2; ++qt) acc[tb][qt] = S::mfma(op[tb], tfrag(tb, qt, ks), acc[tb][qt]);
       }
-      // lane element v: row R0 + lk + 4 v, quarter index q = 16 qt + lr:
+      // lane element v: row R0 + orow(lk, v), quarter index q = 16 qt + lr:
       // outputs r = 2 q + s2 and m-1-r of that row
 #pragma unroll
       for (int qt = 0; qt < 2; ++qt)
@@ -137,40 +176,38 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         for (int v = 0; v < 4; ++v)
 #pragma unroll
           for (int s2 = 0; s2 < 2; ++s2) {
-            const int orow = R0 + lk + 4 * v;
+            const int orow = R0 + S::orow(lk, v);
             const int r = 2 * lr + 32 * qt + s2, rb = m - 1 - r;
-            const double O = acc[s2][qt][v], E = acc[2 + s2][qt][v];
-            if (r < h) X[xy_at(orow, r)] = O + E;
-            if (r < h && rb > r) X[xy_at(orow, rb)] = O - E;
+            const F O = acc[s2][qt][v], E = acc[2 + s2][qt][v];
+            if (r < h) X[S::at(orow, r)] = O + E;
+            if (r < h && rb > r) X[S::at(orow, rb)] = O - E;
           }
     }
     __syncthreads();
     // ---- phase y: columns C0 .. C0 + 15 (columns are independent)
     {
       const int m = a.m2, h = (m + 1) / 2, C0 = 16 * w;
-      d4 acc[4][2];   // [table][q tile]
+      V acc[4][2];   // [table][q tile]
 #pragma unroll
       for (int tb = 0; tb < 4; ++tb)
 #pragma unroll
-        for (int qt = 0; qt < 2; ++qt) acc[tb][qt] = d4{0, 0, 0, 0};
+        for (int qt = 0; qt < 2; ++qt) acc[tb][qt] = V{0, 0, 0, 0};
       const int col = C0 + lr;
 #pragma unroll 2
       for (int ks = 0; ks < 8; ++ks) {
         const int t = 4 * ks + lk;
-        double op[4];
+        F op[4];
 #pragma unroll
         for (int par = 0; par < 2; ++par) {
           const int j = 2 * t + par;
-          combo(j, m, X[xy_at(j, col)], X[xy_at(m - 1 - j, col)], op[2 * par], op[2 * par + 1]);
+          combo(j, m, X[S::at(j, col)], X[S::at(m - 1 - j, col)], op[2 * par], op[2 * par + 1]);
         }
 #pragma unroll
         for (int tb = 0; tb < 4; ++tb)
 #pragma unroll
-          for (int qt = 0; qt < 2; ++qt)
-            acc[tb][qt] = __builtin_amdgcn_mfma_f64_16x16x4f64(tfrag(tb, qt, ks), op[tb],
-                                                              acc[tb][qt], 0, 0, 0);
+          for (int qt = 0; qt < 2; ++qt) acc[tb][qt] = S::mfma(tfrag(tb, qt, ks), op[tb], acc[tb][qt]);
       }
-      // lane element v: quarter index q = 16 qt + lk + 4 v, column C0 + lr:
+      // lane element v: quarter index q = 16 qt + orow(lk, v), column C0 + lr:
       // output rows r = 2 q + s2 and m-1-r of that column
 #pragma unroll
       for (int qt = 0; qt < 2; ++qt)
@@ -178,36 +215,41 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         for (int v = 0; v < 4; ++v)
 #pragma unroll
           for (int s2 = 0; s2 < 2; ++s2) {
-            const int r = 2 * lk + 32 * qt + 8 * v + s2, rb = m - 1 - r;
-            const double O = acc[s2][qt][v], E = acc[2 + s2][qt][v];
-            if (r < h) X[xy_at(r, col)] = O + E;
-            if (r < h && rb > r) X[xy_at(rb, col)] = O - E;
+            const int r = 32 * qt + 2 * S::orow(lk, v) + s2, rb = m - 1 - r;
+            const F O = acc[s2][qt][v], E = acc[2 + s2][qt][v];
+            if (r < h) X[S::at(r, col)] = O + E;
+            if (r < h && rb > r) X[S::at(rb, col)] = O - E;
           }
     }
     __syncthreads();
-    double* db = spec + slab_base(s);
+    F* db = spec + slab_base(s);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int row = w + 8 * i;
-      reinterpret_cast<double2*>(db + (int64_t)8 * i * XYP)[loff] =
-          double2{X[xy_at(row, 2 * lane)], X[xy_at(row, 2 * lane + 1)]};
+      reinterpret_cast<T2*>(db + (int64_t)8 * i * XYP)[loff] =
+          T2{X[S::at(row, 2 * lane)], X[S::at(row, 2 * lane + 1)]};
     }
   }
 }
 
 }  // namespace
 
-hipError_t launch_dst_xy(double* spec, const double* tab, const SlabArgs& a, hipStream_t s) {
+template <typename F>
+hipError_t launch_dst_xy(F* spec, const F* tab, const SlabArgs& a, hipStream_t s) {
   if (!spec || !tab || a.nk < 1 || a.m3 < 1 || a.m1 % 2 == 0 || a.m2 % 2 == 0 ||
       a.m1 <= XYP / 2 || a.m1 > XYP || a.m2 <= XYP / 2 || a.m2 > XYP || a.P1 != XYP ||
       a.P2 != XYP || a.P3 < a.m3 || a.PS != (int64_t)a.P1 * a.P2 * a.P3)
     return hipErrorInvalidValue;
   const int64_t nslab = (int64_t)a.nk * 2 * a.m3;
   if (nslab > 0x7fffffff) return hipErrorInvalidConfiguration;
-  static const int resident = persistent_grid(k_dst_xy, 512);
+  static const int resident = persistent_grid(k_dst_xy<F>, 512);
   if (resident < 8) return hipErrorInvalidDeviceFunction;
-  hipLaunchKernelGGL(k_dst_xy, dim3(strip_grid(resident, nslab)), dim3(512), 0, s, spec, tab, a);
+  hipLaunchKernelGGL((k_dst_xy<F>), dim3(strip_grid(resident, nslab)), dim3(512), 0, s, spec, tab,
+                     a);
   return hipGetLastError();
 }
+
+template hipError_t launch_dst_xy<double>(double*, const double*, const SlabArgs&, hipStream_t);
+template hipError_t launch_dst_xy<float>(float*, const float*, const SlabArgs&, hipStream_t);
 
 }  // namespace aao
