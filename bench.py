@@ -89,11 +89,11 @@ def dst_launch_mix(w, prec):
     product per spatial axis each way, 2 dim in all.  On the two-level fold
     path with a last-axis padded length of 128 or 256 the last axis' forward
     product, shifted divide and inverse product run as one launch; in 3D with
-    P1 = P2 = 128 the x and y products run as one launch each way."""
+    P1 = P2 = 128 (FP64 and FP32) the x and y products run as one launch each way."""
     products = 2 * w.dim
     P = -(-w.m1 // 64) * 64
     fused = dst_path(w, prec) == "fold2" and P in (128, 256)
-    slab = dst_path(w, prec) == "fold2" and w.dim == 3 and P == 128
+    slab = prec in ("fp64", "fp32") and w.dim == 3 and P == 128 and w.m1 % 2 == 1
     return products - (1 if fused else 0) - (2 if slab else 0), products
 
 

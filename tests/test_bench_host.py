@@ -46,6 +46,7 @@ def test_dst_launch_mix_and_flops():
     w3 = W.WORKLOADS["heat3d_127x256"]
     assert bench.dst_launch_mix(w3, "fp64") == (3, 6)
     assert bench.dst_launch_mix(w3, "bf16x3") == (6, 6)
+    assert bench.dst_launch_mix(w3, "fp32") == (4, 6)
     assert bench.dst_path(w3, "bf16x3") == "fold"
 
 
