@@ -2077,6 +2077,8 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
   int total = 0, nhist = 0;
   bool converged = false;
   bool first = true;
+  // the last two relative residual estimates (for the store prediction)
+  double last_est = 1.0, prev_est = 1.0;
   while (true) {
     double beta, g0;
     const double* v0 = nullptr;  // W_0 when it is not stored in V
@@ -2148,6 +2150,7 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
       }
     }
     first = false;
+    last_est = prev_est = beta / ref;
     if (total >= maxit) break;
     TRY(set_is2(0, sc[0]));
     std::fill(H.begin(), H.end(), 0.0);
@@ -2184,7 +2187,14 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
       if (fuse) {
         const double* basis[kStencilDotsMax];
         for (int i = 0; i < q; ++i) basis[i] = (i == 0 && v0) ? v0 : c->V + (int64_t)i * nm;
-        TRY(stencil_fused(c, 2, zj, w, nullptr, basis, q, o_h1, is2, probe ? o_w2 : -1));
+        // When the residual estimates so far predict that this step ends the
+        // solve (the last reduction factor applied once more reaches tol), L z
+        // is not stored: the early test below needs only its dots and norm.
+        // If the test then does not stop the solve, the pass is run again
+        // with the store.
+        const bool nostore = probe && last_est * (last_est / prev_est) <= tol;
+        TRY(stencil_fused(c, 2, zj, nostore ? nullptr : w, nullptr, basis, q, o_h1, is2,
+                          probe ? o_w2 : -1));
         if (probe) {
           TRY(fetch_small2(c, o_h1, q, o_w2, 1));
           const double w2 = c->hsmall[o_w2];
@@ -2212,6 +2222,7 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
             }
           }
         }
+        if (nostore) TRY(stencil_fused(c, 2, zj, w, nullptr, basis, q, o_h1, is2));
       } else if (!left) {
         TRY(apply_L(c, zj, w));
       }
@@ -2277,6 +2288,8 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
       sc[j + 1] = wn;
       double csj, snj;
       const double est = givens(j, colv.data(), csj, snj);
+      prev_est = last_est;
+      last_est = est;
       commit(j, colv.data(), csj, snj);
       ++total;
       if (res_hist && nhist < hist_cap) res_hist[nhist] = est;

@@ -106,8 +106,9 @@ hipError_t launch_apply_L_var(const Geometry& g, const double* x, double* y, con
 
 // Fused stencil passes (2D/3D only; AAO dim 1 uses the plain kernel).
 // epi 1: partial sums of (f - L x)^2, one per block, y unused (may be null);
-// epi 2: y = L x and partial dots of y with basis[0..q-1] (q <= kStencilDotsMax),
-// q per block, and (wsq non-null) partial sums of y^2, one per block in wsq.
+// epi 2: y = L x (not stored when y is null) and partial dots of L x with
+// basis[0..q-1] (q <= kStencilDotsMax), q per block, and (wsq non-null)
+// partial sums of (L x)^2, one per block in wsq.
 // Constant coefficient: c1..c3 with ax = null; variable: ax, ay, az face weights.
 // part must hold stencil_partials(g) * q doubles, wsq stencil_partials(g).
 constexpr int kStencilDotsMax = 4;

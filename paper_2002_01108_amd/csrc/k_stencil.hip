@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256) void k_apply_L25(
         continue;
       }
       const bool out_ok = writer && j0 + t < m2;
-      if (EPI != 1 && out_ok) yk[(int64_t)(j0 + t) * m1] = acc;
+      if (EPI != 1 && out_ok && y) yk[(int64_t)(j0 + t) * m1] = acc;
       if (EPI == 1 && out_ok) {
         const double d = eo[0][t] - acc;
         red_acc[0] += d * d;
@@ -435,7 +435,7 @@ __global__ __launch_bounds__(256) void k_apply_L3z(
           acc += r2 * pv2;
         }
         const bool out_ok = writer && j0 + t < m2;
-        if (EPI != 1 && out_ok) y[rowoff + (int64_t)(j0 + t) * m1] = acc;
+        if (EPI != 1 && out_ok && y) y[rowoff + (int64_t)(j0 + t) * m1] = acc;
         if (EPI == 1 && out_ok) {
           const double d = eo[0][t] - acc;
           red_acc[0] += d * d;

@@ -14,6 +14,11 @@ passes of that step.  Checked here:
   error stays within the conditioning bound;
 * at tol = 1e-14 (unreachable by the bound) the solve runs the passes and
   reaches the same solution.
+The step that the estimates predict to be the last runs the stencil without
+storing L z (only its dots and norm are needed if the early test stops there);
+a missed prediction reruns the pass with the store, exercised here by the
+BF16x3 solve to 1e-10 (its third step was predicted to end the solve and
+does not).
 The solves at tol = 1e-8 also take the selective second correction: after the
 first Gram-Schmidt pass the second-pass dots give the cosines of w' with the
 basis, and when all are below 1e-3 tol (here about 1e-12 after the first step)
@@ -86,3 +91,19 @@ def test_reported_convergence_is_true_convergence(case, variant):
     assert info["status"] == 0
     assert info["final_res"] <= 1e-8 * (1 + 1e-6)
     assert float(np.linalg.norm(u - ex) / np.linalg.norm(ex)) <= 1e-7
+
+
+def test_store_prediction_miss_reruns_the_pass(case):
+    """BF16x3 preconditioner, tol 1e-10: residual estimates 3.4e-3, 1.8e-7, ...
+    predict 9.5e-12 for the third step, whose bound (about 5e-10) does not meet
+    tol; the stencil pass is rerun with its store and the solve goes on to a
+    true residual below tol."""
+    from paper_2002_01108_amd import Solver
+    p, rhs, ex = case
+    s = Solver(2, p.m1, p.n, T=1.0, eps=p.eps, precision="bf16x3")
+    u, info = s.solve(torch.from_numpy(rhs).cuda(), tol=1e-10, maxit=20)
+    u = host(u)
+    print("bf16x3 1e-10 hist", info["hist"], "final", info["final_res"], flush=True)
+    assert info["status"] == 0 and info["iters"] >= 4
+    assert info["final_res"] <= 1e-10 * (1 + 1e-6)
+    assert float(np.linalg.norm(u - ex) / np.linalg.norm(ex)) <= 1e-8
