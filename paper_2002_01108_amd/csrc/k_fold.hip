@@ -1310,6 +1310,10 @@ template hipError_t launch_dst_fold2<double>(const double*, double*, const doubl
                                              const FoldArgs&, bool, const double*,
                                              const double*, const double*, const double*,
                                              hipStream_t);
+template hipError_t launch_dst_fold2<float>(const float*, float*, const float*,
+                                            const FoldArgs&, bool, const double*,
+                                            const double*, const double*, const double*,
+                                            hipStream_t);
 
 template hipError_t launch_dst_fold<double>(const double*, double*, const double*, const double*,
                                             const FoldArgs&, bool, const double*, const double*,
