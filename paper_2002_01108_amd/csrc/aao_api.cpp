@@ -85,6 +85,7 @@ struct aao_ctx {
   // two-level fold tables [4][P_d/4][P_d/4] (odd m_d, P_d % 128 == 0), else null,
   // and their transposes [table][t][q] for the fused forward-divide-inverse kernel
   double* Fq64[3] = {nullptr, nullptr, nullptr};
+  double* F3_64[3] = {nullptr, nullptr, nullptr};  // third-fold tables (m_d = 127)
   double* FqT64[3] = {nullptr, nullptr, nullptr};
   float* FqT32[3] = {nullptr, nullptr, nullptr};   // FqT64 in FP32 (the FP32 slab kernel)
   float* Fq32[3] = {nullptr, nullptr, nullptr};    // Fq64 in FP32
@@ -496,7 +497,8 @@ hipError_t xy_product(aao_ctx* c, void* spec, bool real_ends) {
   a.P1 = g.P1;
   a.P2 = g.P2;
   a.P3 = g.P3;
-  if (c->prec == AAO_FP64) return launch_dst_xy((double*)spec, c->Fq64[0], a, c->stream);
+  if (c->prec == AAO_FP64)
+    return launch_dst_xy((double*)spec, c->Fq64[0], a, c->stream, (const double*)c->F3_64[0]);
   return launch_dst_xy((float*)spec, c->FqT32[0], a, c->stream);
 }
 
@@ -1320,6 +1322,32 @@ aao_status aao_setup(int dim, int m1, int m2, int m3, int n, double T, double ep
       if ((st = upload(c, &c->Fq32[d], fq32)) != AAO_OK) return bail(st);
       std::vector<float> fqt32(fqt.begin(), fqt.end());
       if ((st = upload(c, &c->FqT32[d], fqt32)) != AAO_OK) return bail(st);
+    }
+    // third fold (m = 127: m + 1 = 128 is a multiple of 4), symmetries of S:
+    // for odd rows r (r + 1 = 2a) columns j and j' = 62 - j (even j) or 60 - j
+    // (odd j) satisfy S_{r,j'} = (-1)^{a+1} S_{r,j}; for even rows and odd
+    // columns j = 2t + 1, S_{62-r,j} = (-1)^t S_{r,j}.  Tables [q][kappa]:
+    // T0 (32 x 32): S_{2qo, jk} with qo = q (q < 16) or 47 - q, jk = 2 kappa
+    // (kappa < 16) or 94 - 2 kappa; then 16 x 16: S_{4q+1, 2k}, S_{4q+3, 2k},
+    // S_{4q+1, 2k+1}, S_{4q+3, 2k+1}, S_{2q, 4k+1}, S_{2q, 4k+3}, the entries
+    // of self-paired combinations (k = 15 in the 3rd, 4th and 6th) halved.
+    if (md == 127 && P == 128) {
+      std::vector<double> f3((size_t)32 * 32 + 6 * 16 * 16, 0.0);
+      auto Sv = [&](int r, int j) { return S[(size_t)r * P + j]; };
+      for (int q = 0; q < 32; ++q)
+        for (int k = 0; k < 32; ++k)
+          f3[(size_t)q * 32 + k] = Sv(2 * (q < 16 ? q : 47 - q), k < 16 ? 2 * k : 94 - 2 * k);
+      for (int q = 0; q < 16; ++q)
+        for (int k = 0; k < 16; ++k) {
+          double* t = f3.data() + 1024 + q * 16 + k;
+          t[0 * 256] = Sv(4 * q + 1, 2 * k);
+          t[1 * 256] = Sv(4 * q + 3, 2 * k);
+          t[2 * 256] = k < 15 ? Sv(4 * q + 1, 2 * k + 1) : 0.5 * Sv(4 * q + 1, 31);
+          t[3 * 256] = k < 15 ? Sv(4 * q + 3, 2 * k + 1) : 0.5 * Sv(4 * q + 3, 31);
+          t[4 * 256] = Sv(2 * q, 4 * k + 1);
+          t[5 * 256] = k < 15 ? Sv(2 * q, 4 * k + 3) : 0.5 * Sv(2 * q, 63);
+        }
+      if ((st = upload(c, &c->F3_64[d], f3)) != AAO_OK) return bail(st);
     }
   }
   if ((st = ensure_spec(c)) != AAO_OK) return bail(st);

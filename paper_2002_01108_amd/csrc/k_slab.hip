@@ -40,7 +40,28 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // LDS (two blocks per CU), the slab swizzled by (row & 15) << 3 (64 banks of
 // 32-bit words: the 16 rows of a fragment read land in pairs on 32 banks) and
 // the tables transposed ([tb][t][q], q contiguous, q ^ 16 ((t >> 1) & 1)).
+// Third fold (FP64, m1 = m2 = 127, so m + 1 = 128 is a multiple of 4): with
+// the quarter products written over output index q and pair index t (outputs
+// r = 2q + s, elements j = 2t + b), three of the four split again.  For r odd
+// (r + 1 = 2a) the element pairs j <-> 62 - j (b = 0) and j <-> 60 - j (b = 1),
+// i.e. J = j + 1 <-> 64 - J, have S_{r,j'} = (-1)^{a+1} S_{r,j}: the minus
+// combinations q_j = x_j - x_{126-j} fold once more into q_j +- q_{j'}, the
+// sign set by q's parity (16 x 16 products instead of 32 x 32).  For r even
+// and j odd the outputs pair: S_{62-r, j} = (-1)^t S_{r,j} (j = 2t + 1), so
+// the plus product splits into its even-t and odd-t halves Ev, Od with
+// E_r = Ev + Od and E_{62-r} = Ev - Od.  The remaining r even, j even product
+// (a DST-IV of size 32) keeps its 32 x 32 form.  Tables ([q][kappa], built on
+// the host): T0 32 x 32 (A+: rows q < 16 give r = 2q, rows 16 + i give
+// r = 62 - 2i; kappa < 16 takes j = 2 kappa, kappa >= 16 j = 94 - 2 kappa),
+// then six 16 x 16: A- for r = 4q + 1 and 4q + 3 over j = 2 kappa, B- for the
+// same rows over j = 2 kappa + 1 (kappa = 15 is j = 31 paired with itself:
+// halved, its combination comes out doubled), B+ Ev and Od for r = 2q over
+// j = 4 kappa + 1 and 4 kappa + 3 (kappa = 15 is the middle element j = 63:
+// halved likewise).  Lane q (phase x: lane row lr; phase y: output row) then
+// owns r = 2q, 62 - 2q, 4q + 1, 4q + 3 and their mirrors 126 - r.  40 MFMAs per
+// 16 lines and product instead of 64.
 constexpr int XYP = 128, XYQ = 32;
+constexpr int F3N = 32 * 32 + 6 * 16 * 16;   // third-fold table entries
 
 template <typename T> struct Slab;
 template <> struct Slab<double> {
@@ -81,14 +102,15 @@ template <> struct Slab<float> {
   }
 };
 
-template <typename F>
+template <typename F, bool L3>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(F) == 8 ? 2 : 4)))
 void k_dst_xy(F* __restrict__ spec, const F* __restrict__ tab, SlabArgs a) {
+  static_assert(!L3 || sizeof(F) == 8, "the third fold is built for FP64");
   using S = Slab<F>;
   using V = typename S::V;
   using T2 = typename S::T2;
   __shared__ F X[XYP * XYP];
-  __shared__ F T[4 * XYQ * XYQ];
+  __shared__ F T[L3 ? F3N : 4 * XYQ * XYQ];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   // lane coordinates of the MFMA fragments, renewed opaquely for every slab
   // (below) so that the compiler does not hoist the phases' per-lane
@@ -98,10 +120,26 @@ void k_dst_xy(F* __restrict__ spec, const F* __restrict__ tab, SlabArgs a) {
   const int64_t zs = (int64_t)XYP * XYP;   // one z slab of a plane
 
   // tables, swizzled so that the 16 q rows of a fragment read fall on distinct banks
-  for (int i = tid; i < 4 * XYQ * XYQ; i += 512) {
-    const int tb = i / (XYQ * XYQ), q = (i / XYQ) % XYQ, t = i % XYQ;
-    T[S::tab_at(tb, q, t)] = tab[S::tab_src(tb, q, t)];
+  if constexpr (L3) {
+    for (int i = tid; i < F3N; i += 512) {
+      if (i < XYQ * XYQ) {
+        const int q = i / XYQ, k = i % XYQ;
+        T[q * XYQ + (k ^ (q & 15))] = tab[i];
+      } else {
+        const int e = i - XYQ * XYQ, q = (e / 16) % 16, k = e % 16;
+        T[i - k + (k ^ q)] = tab[i];
+      }
+    }
+  } else {
+    for (int i = tid; i < 4 * XYQ * XYQ; i += 512) {
+      const int tb = i / (XYQ * XYQ), q = (i / XYQ) % XYQ, t = i % XYQ;
+      T[S::tab_at(tb, q, t)] = tab[S::tab_src(tb, q, t)];
+    }
   }
+  // third-fold fragments: T0 row q (< 32), column kappa; table tb of the six
+  // 16 x 16 ones, row q (< 16), column kappa
+  auto t0 = [&](int q, int k) { return T[q * XYQ + (k ^ (q & 15))]; };
+  auto t16 = [&](int tb, int q, int k) { return T[XYQ * XYQ + tb * 256 + q * 16 + (k ^ q)]; };
 
   auto slab_base = [&](int s) -> int64_t {
     const int z = s % a.m3, rest = s / a.m3, pl = rest & 1, k = rest >> 1;
@@ -146,7 +184,45 @@ void k_dst_xy(F* __restrict__ spec, const F* __restrict__ tab, SlabArgs a) {
 
     // ---- phase x: rows R0 .. R0 + 15 (rows are independent: a tile's
     // outputs replace its inputs once its K loop is done)
-    {
+    if constexpr (L3) {
+      const int R0 = 16 * w, row = R0 + lr;
+      auto xr = [&](int j) { return X[S::at(row, j)]; };
+      V aP0{0, 0, 0, 0}, aP1{0, 0, 0, 0}, aMe{0, 0, 0, 0}, aMo{0, 0, 0, 0};
+      V bMe{0, 0, 0, 0}, bMo{0, 0, 0, 0}, bEv{0, 0, 0, 0}, bOd{0, 0, 0, 0};
+#pragma unroll 2
+      for (int ks = 0; ks < 4; ++ks) {
+        const int t = 4 * ks + lk;
+        const F xa = xr(2 * t), xb = xr(126 - 2 * t), xc = xr(62 - 2 * t), xd = xr(64 + 2 * t);
+        const F xe = xr(2 * t + 1), xf = xr(125 - 2 * t), xg = xr(61 - 2 * t), xh = xr(65 + 2 * t);
+        const F xi = xr(4 * t + 1), xj = xr(125 - 4 * t), xk = xr(4 * t + 3), xl = xr(123 - 4 * t);
+        const F pA0 = xa + xb, qA0 = xa - xb, pA1 = xc + xd, qA1 = xc - xd;
+        const F qB0 = xe - xf, qB1 = xg - xh;
+        aP0 = S::mfma(pA0, t0(lr, t), aP0);
+        aP1 = S::mfma(pA0, t0(16 + lr, t), aP1);
+        aP0 = S::mfma(pA1, t0(lr, 16 + t), aP0);
+        aP1 = S::mfma(pA1, t0(16 + lr, 16 + t), aP1);
+        aMe = S::mfma(qA0 + qA1, t16(0, lr, t), aMe);
+        aMo = S::mfma(qA0 - qA1, t16(1, lr, t), aMo);
+        bMe = S::mfma(qB0 + qB1, t16(2, lr, t), bMe);
+        bMo = S::mfma(qB0 - qB1, t16(3, lr, t), bMo);
+        bEv = S::mfma(xi + xj, t16(4, lr, t), bEv);
+        bOd = S::mfma(xk + xl, t16(5, lr, t), bOd);
+      }
+      // lane element v: row R0 + orow(lk, v), output rows of q = lr
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int orow = R0 + S::orow(lk, v);
+        const F E0 = bEv[v] + bOd[v], E1 = bEv[v] - bOd[v];
+        X[S::at(orow, 2 * lr)] = aP0[v] + E0;
+        X[S::at(orow, 126 - 2 * lr)] = aP0[v] - E0;
+        X[S::at(orow, 62 - 2 * lr)] = aP1[v] + E1;
+        X[S::at(orow, 64 + 2 * lr)] = aP1[v] - E1;
+        X[S::at(orow, 4 * lr + 1)] = aMe[v] + bMe[v];
+        X[S::at(orow, 125 - 4 * lr)] = aMe[v] - bMe[v];
+        X[S::at(orow, 4 * lr + 3)] = aMo[v] + bMo[v];
+        if (lr < 15) X[S::at(orow, 123 - 4 * lr)] = aMo[v] - bMo[v];
+      }
+    } else {
       const int m = a.m1, h = (m + 1) / 2, R0 = 16 * w;
       V acc[4][2];   // [table][q tile]
 #pragma unroll
@@ -185,7 +261,45 @@ void k_dst_xy(F* __restrict__ spec, const F* __restrict__ tab, SlabArgs a) {
     }
     __syncthreads();
     // ---- phase y: columns C0 .. C0 + 15 (columns are independent)
-    {
+    if constexpr (L3) {
+      const int C0 = 16 * w, col = C0 + lr;
+      auto xr = [&](int j) { return X[S::at(j, col)]; };
+      V aP0{0, 0, 0, 0}, aP1{0, 0, 0, 0}, aMe{0, 0, 0, 0}, aMo{0, 0, 0, 0};
+      V bMe{0, 0, 0, 0}, bMo{0, 0, 0, 0}, bEv{0, 0, 0, 0}, bOd{0, 0, 0, 0};
+#pragma unroll 2
+      for (int ks = 0; ks < 4; ++ks) {
+        const int t = 4 * ks + lk;
+        const F xa = xr(2 * t), xb = xr(126 - 2 * t), xc = xr(62 - 2 * t), xd = xr(64 + 2 * t);
+        const F xe = xr(2 * t + 1), xf = xr(125 - 2 * t), xg = xr(61 - 2 * t), xh = xr(65 + 2 * t);
+        const F xi = xr(4 * t + 1), xj = xr(125 - 4 * t), xk = xr(4 * t + 3), xl = xr(123 - 4 * t);
+        const F pA0 = xa + xb, qA0 = xa - xb, pA1 = xc + xd, qA1 = xc - xd;
+        const F qB0 = xe - xf, qB1 = xg - xh;
+        aP0 = S::mfma(t0(lr, t), pA0, aP0);
+        aP1 = S::mfma(t0(16 + lr, t), pA0, aP1);
+        aP0 = S::mfma(t0(lr, 16 + t), pA1, aP0);
+        aP1 = S::mfma(t0(16 + lr, 16 + t), pA1, aP1);
+        aMe = S::mfma(t16(0, lr, t), qA0 + qA1, aMe);
+        aMo = S::mfma(t16(1, lr, t), qA0 - qA1, aMo);
+        bMe = S::mfma(t16(2, lr, t), qB0 + qB1, bMe);
+        bMo = S::mfma(t16(3, lr, t), qB0 - qB1, bMo);
+        bEv = S::mfma(t16(4, lr, t), xi + xj, bEv);
+        bOd = S::mfma(t16(5, lr, t), xk + xl, bOd);
+      }
+      // lane element v: output rows of q = orow(lk, v), column C0 + lr
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int q = S::orow(lk, v);
+        const F E0 = bEv[v] + bOd[v], E1 = bEv[v] - bOd[v];
+        X[S::at(2 * q, col)] = aP0[v] + E0;
+        X[S::at(126 - 2 * q, col)] = aP0[v] - E0;
+        X[S::at(62 - 2 * q, col)] = aP1[v] + E1;
+        X[S::at(64 + 2 * q, col)] = aP1[v] - E1;
+        X[S::at(4 * q + 1, col)] = aMe[v] + bMe[v];
+        X[S::at(125 - 4 * q, col)] = aMe[v] - bMe[v];
+        X[S::at(4 * q + 3, col)] = aMo[v] + bMo[v];
+        if (q < 15) X[S::at(123 - 4 * q, col)] = aMo[v] - bMo[v];
+      }
+    } else {
       const int m = a.m2, h = (m + 1) / 2, C0 = 16 * w;
       V acc[4][2];   // [table][q tile]
 #pragma unroll
@@ -234,22 +348,33 @@ void k_dst_xy(F* __restrict__ spec, const F* __restrict__ tab, SlabArgs a) {
 
 }  // namespace
 
+template <typename F, bool L3>
+hipError_t launch_xy(F* spec, const F* tab, const SlabArgs& a, hipStream_t s) {
+  const int64_t nslab = (int64_t)a.nk * 2 * a.m3;
+  if (nslab > 0x7fffffff) return hipErrorInvalidConfiguration;
+  static const int resident = persistent_grid(k_dst_xy<F, L3>, 512);
+  if (resident < 8) return hipErrorInvalidDeviceFunction;
+  hipLaunchKernelGGL((k_dst_xy<F, L3>), dim3(strip_grid(resident, nslab)), dim3(512), 0, s, spec,
+                     tab, a);
+  return hipGetLastError();
+}
+
 template <typename F>
-hipError_t launch_dst_xy(F* spec, const F* tab, const SlabArgs& a, hipStream_t s) {
+hipError_t launch_dst_xy(F* spec, const F* tab, const SlabArgs& a, hipStream_t s,
+                         const F* tab3) {
   if (!spec || !tab || a.nk < 1 || a.m3 < 1 || a.m1 % 2 == 0 || a.m2 % 2 == 0 ||
       a.m1 <= XYP / 2 || a.m1 > XYP || a.m2 <= XYP / 2 || a.m2 > XYP || a.P1 != XYP ||
       a.P2 != XYP || a.P3 < a.m3 || a.PS != (int64_t)a.P1 * a.P2 * a.P3)
     return hipErrorInvalidValue;
-  const int64_t nslab = (int64_t)a.nk * 2 * a.m3;
-  if (nslab > 0x7fffffff) return hipErrorInvalidConfiguration;
-  static const int resident = persistent_grid(k_dst_xy<F>, 512);
-  if (resident < 8) return hipErrorInvalidDeviceFunction;
-  hipLaunchKernelGGL((k_dst_xy<F>), dim3(strip_grid(resident, nslab)), dim3(512), 0, s, spec, tab,
-                     a);
-  return hipGetLastError();
+  if constexpr (sizeof(F) == 8) {
+    if (tab3 && a.m1 == XYP - 1 && a.m2 == XYP - 1) return launch_xy<F, true>(spec, tab3, a, s);
+  }
+  return launch_xy<F, false>(spec, tab, a, s);
 }
 
-template hipError_t launch_dst_xy<double>(double*, const double*, const SlabArgs&, hipStream_t);
-template hipError_t launch_dst_xy<float>(float*, const float*, const SlabArgs&, hipStream_t);
+template hipError_t launch_dst_xy<double>(double*, const double*, const SlabArgs&, hipStream_t,
+                                          const double*);
+template hipError_t launch_dst_xy<float>(float*, const float*, const SlabArgs&, hipStream_t,
+                                         const float*);
 
 }  // namespace aao
