@@ -85,7 +85,7 @@ struct aao_ctx {
   // two-level fold tables [4][P_d/4][P_d/4] (odd m_d, P_d % 128 == 0), else null,
   // and their transposes [table][t][q] for the fused forward-divide-inverse kernel
   double* Fq64[3] = {nullptr, nullptr, nullptr};
-  double* F3_64[3] = {nullptr, nullptr, nullptr};  // third-fold tables (m_d = 127)
+  double* F3_64[3] = {nullptr, nullptr, nullptr};  // third-fold tables (x axis, m_1 = 127)
   double* FqT64[3] = {nullptr, nullptr, nullptr};
   float* FqT32[3] = {nullptr, nullptr, nullptr};   // FqT64 in FP32 (the FP32 slab kernel)
   float* Fq32[3] = {nullptr, nullptr, nullptr};    // Fq64 in FP32
@@ -1331,7 +1331,7 @@ aao_status aao_setup(int dim, int m1, int m2, int m3, int n, double T, double ep
     // (kappa < 16) or 94 - 2 kappa; then 16 x 16: S_{4q+1, 2k}, S_{4q+3, 2k},
     // S_{4q+1, 2k+1}, S_{4q+3, 2k+1}, S_{2q, 4k+1}, S_{2q, 4k+3}, the entries
     // of self-paired combinations (k = 15 in the 3rd, 4th and 6th) halved.
-    if (md == 127 && P == 128) {
+    if (d == 0 && md == 127 && P == 128) {   // the slab kernel's x and y products
       std::vector<double> f3((size_t)32 * 32 + 6 * 16 * 16, 0.0);
       auto Sv = [&](int r, int j) { return S[(size_t)r * P + j]; };
       for (int q = 0; q < 32; ++q)
