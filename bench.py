@@ -119,11 +119,23 @@ def dst_product_flops(w, prec):
     return 2.0 * macs * w.n * (w.m // md)
 
 
+def fold3_slab(w, prec):
+    """FP64 3D with m1 = m2 = 127: the slab launch runs the x and y products on
+    the third fold (one 32 x 32 and six 16 x 16 products per vector: 2560
+    multiply-adds against the two-level fold's 4064)."""
+    return prec == "fp64" and w.dim == 3 and w.m1 == 127
+
+
 def dst_flops_per_launch(w, prec):
-    """Average algorithmic flops per launch of the DST class: the products of
-    one P^{-1} spread over its launches (a fused launch runs two)."""
+    """Average flops per launch of the DST class: the products of one P^{-1}
+    spread over its launches (a fused launch runs two), the third-fold slab
+    products at their own multiply-add count."""
     launches, products = dst_launch_mix(w, prec)
-    return dst_product_flops(w, prec) * products / launches
+    per = dst_product_flops(w, prec)
+    total = per * products
+    if fold3_slab(w, prec):
+        total -= 4 * per * (1.0 - 2560.0 / 4064.0)   # x and y, each way
+    return total / launches
 
 
 def time_solver(s, fd, u0d, tol, restart, steps, warmup, prof_classes):
@@ -566,7 +578,8 @@ def dst_roofline(w, prec, prof):
     traffic = measured_traffic(w.name, prec, path) if path != "dense" else None
     launches, products = dst_launch_mix(w, prec)
     mix = (f"{products} DST-I mode products in {launches} launches per P^-1"
-           + (", the last axis' forward, divide and inverse fused" if launches < products else ""))
+           + (", the last axis' forward, divide and inverse fused" if launches < products else "")
+           + (", x and y on a third fold" if fold3_slab(w, prec) else ""))
     achieved = nbytes / avg_s / 1e9 if dst_n else None
     return {"kernel": f"dst_{path}_{prec} ({mix})",
             "bound": "hbm", "achieved": achieved, "peak": PEAKS["hbm_GBs"], "unit": "GB/s",
