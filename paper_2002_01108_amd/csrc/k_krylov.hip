@@ -109,10 +109,7 @@ __global__ __launch_bounds__(KT) void k_axpy(const double* __restrict__ V, int64
       wv.x -= hi * v.x;
       wv.y -= hi * v.y;
     }
-    // streaming store: 2.79 -> 2.51 ms per pass over a 4.2 GB vector (the
-    // same hint on the time FFT, stencil and solution-update stores was slower)
-    __builtin_nontemporal_store(wv.x, &w2[e].x);
-    __builtin_nontemporal_store(wv.y, &w2[e].y);
+    w2[e] = wv;
     if (MODE == 1) {
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
