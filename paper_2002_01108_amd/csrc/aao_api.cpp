@@ -86,6 +86,7 @@ struct aao_ctx {
   // and their transposes [table][t][q] for the fused forward-divide-inverse kernel
   double* Fq64[3] = {nullptr, nullptr, nullptr};
   double* F3_64[3] = {nullptr, nullptr, nullptr};  // third-fold tables (x axis, m_1 = 127)
+  float* F3_32[3] = {nullptr, nullptr, nullptr};   // F3_64 in FP32
   double* FqT64[3] = {nullptr, nullptr, nullptr};
   float* FqT32[3] = {nullptr, nullptr, nullptr};   // FqT64 in FP32 (the FP32 slab kernel)
   float* Fq32[3] = {nullptr, nullptr, nullptr};    // Fq64 in FP32
@@ -499,7 +500,7 @@ hipError_t xy_product(aao_ctx* c, void* spec, bool real_ends) {
   a.P3 = g.P3;
   if (c->prec == AAO_FP64)
     return launch_dst_xy((double*)spec, c->Fq64[0], a, c->stream, (const double*)c->F3_64[0]);
-  return launch_dst_xy((float*)spec, c->FqT32[0], a, c->stream);
+  return launch_dst_xy((float*)spec, c->FqT32[0], a, c->stream, (const float*)c->F3_32[0]);
 }
 
 // One mode product along axis d (0 = x, 1 = y, 2 = z) from `in` to `out`
@@ -1348,6 +1349,8 @@ aao_status aao_setup(int dim, int m1, int m2, int m3, int n, double T, double ep
           t[5 * 256] = k < 15 ? Sv(2 * q, 4 * k + 3) : 0.5 * Sv(2 * q, 63);
         }
       if ((st = upload(c, &c->F3_64[d], f3)) != AAO_OK) return bail(st);
+      std::vector<float> f3f(f3.begin(), f3.end());
+      if ((st = upload(c, &c->F3_32[d], f3f)) != AAO_OK) return bail(st);
     }
   }
   if ((st = ensure_spec(c)) != AAO_OK) return bail(st);

@@ -198,9 +198,10 @@ struct SlabArgs {
   int P1, P2, P3;
 };
 // FP64: tab = the [4][32][32] quarter tables as [tb][q][t]; FP32: the same
-// tables in FP32, transposed to [tb][t][q].  FP64 with m1 = m2 = 127 and tab3
+// tables in FP32, transposed to [tb][t][q].  m1 = m2 = 127 with tab3
 // non-null: the third-fold products instead (tab3 = one 32 x 32 and six
-// 16 x 16 tables, [q][kappa] each, in the order the kernel documents).
+// 16 x 16 tables, [q][kappa] each, in the order the kernel documents; FP64 or
+// FP32 like the spectrum).
 template <typename F>
 hipError_t launch_dst_xy(F* spec, const F* tab, const SlabArgs& a, hipStream_t s,
                          const F* tab3 = nullptr);

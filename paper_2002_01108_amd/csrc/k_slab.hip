@@ -40,7 +40,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // LDS (two blocks per CU), the slab swizzled by (row & 15) << 3 (64 banks of
 // 32-bit words: the 16 rows of a fragment read land in pairs on 32 banks) and
 // the tables transposed ([tb][t][q], q contiguous, q ^ 16 ((t >> 1) & 1)).
-// Third fold (FP64, m1 = m2 = 127, so m + 1 = 128 is a multiple of 4): with
+// Third fold (m1 = m2 = 127, so m + 1 = 128 is a multiple of 4): with
 // the quarter products written over output index q and pair index t (outputs
 // r = 2q + s, elements j = 2t + b), three of the four split again.  For r odd
 // (r + 1 = 2a) the element pairs j <-> 62 - j (b = 0) and j <-> 60 - j (b = 1),
@@ -82,6 +82,12 @@ template <> struct Slab<double> {
   static __device__ __forceinline__ int tab_src(int tb, int q, int t) {
     return (tb * XYQ + q) * XYQ + t;
   }
+  // third-fold tables: T0 row q (< 32), column k; table tb of the six
+  // 16 x 16 ones, row q, column k (16 rows of one column on distinct banks)
+  static __device__ __forceinline__ int t0_at(int q, int k) { return q * XYQ + (k ^ (q & 15)); }
+  static __device__ __forceinline__ int t16_at(int tb, int q, int k) {
+    return XYQ * XYQ + tb * 256 + q * 16 + (k ^ q);
+  }
 };
 template <> struct Slab<float> {
   typedef f4 V;
@@ -100,12 +106,19 @@ template <> struct Slab<float> {
   static __device__ __forceinline__ int tab_src(int tb, int q, int t) {
     return (tb * XYQ + t) * XYQ + q;
   }
+  // third-fold tables, columns XOR-swizzled by multiples of 4 so that a
+  // fragment read (16 rows q x 4 consecutive columns) hits 64 distinct banks
+  static __device__ __forceinline__ int t0_at(int q, int k) {
+    return q * XYQ + (k ^ (4 * ((q >> 1) & 7)));
+  }
+  static __device__ __forceinline__ int t16_at(int tb, int q, int k) {
+    return XYQ * XYQ + tb * 256 + q * 16 + (k ^ (4 * (q >> 2)));
+  }
 };
 
 template <typename F, bool L3>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(F) == 8 ? 2 : 4)))
 void k_dst_xy(F* __restrict__ spec, const F* __restrict__ tab, SlabArgs a) {
-  static_assert(!L3 || sizeof(F) == 8, "the third fold is built for FP64");
   using S = Slab<F>;
   using V = typename S::V;
   using T2 = typename S::T2;
@@ -123,11 +136,10 @@ void k_dst_xy(F* __restrict__ spec, const F* __restrict__ tab, SlabArgs a) {
   if constexpr (L3) {
     for (int i = tid; i < F3N; i += 512) {
       if (i < XYQ * XYQ) {
-        const int q = i / XYQ, k = i % XYQ;
-        T[q * XYQ + (k ^ (q & 15))] = tab[i];
+        T[S::t0_at(i / XYQ, i % XYQ)] = tab[i];
       } else {
-        const int e = i - XYQ * XYQ, q = (e / 16) % 16, k = e % 16;
-        T[i - k + (k ^ q)] = tab[i];
+        const int e = i - XYQ * XYQ;
+        T[S::t16_at(e / 256, (e / 16) % 16, e % 16)] = tab[i];
       }
     }
   } else {
@@ -138,8 +150,8 @@ void k_dst_xy(F* __restrict__ spec, const F* __restrict__ tab, SlabArgs a) {
   }
   // third-fold fragments: T0 row q (< 32), column kappa; table tb of the six
   // 16 x 16 ones, row q (< 16), column kappa
-  auto t0 = [&](int q, int k) { return T[q * XYQ + (k ^ (q & 15))]; };
-  auto t16 = [&](int tb, int q, int k) { return T[XYQ * XYQ + tb * 256 + q * 16 + (k ^ q)]; };
+  auto t0 = [&](int q, int k) { return T[S::t0_at(q, k)]; };
+  auto t16 = [&](int tb, int q, int k) { return T[S::t16_at(tb, q, k)]; };
 
   auto slab_base = [&](int s) -> int64_t {
     const int z = s % a.m3, rest = s / a.m3, pl = rest & 1, k = rest >> 1;
@@ -366,9 +378,7 @@ hipError_t launch_dst_xy(F* spec, const F* tab, const SlabArgs& a, hipStream_t s
       a.m1 <= XYP / 2 || a.m1 > XYP || a.m2 <= XYP / 2 || a.m2 > XYP || a.P1 != XYP ||
       a.P2 != XYP || a.P3 < a.m3 || a.PS != (int64_t)a.P1 * a.P2 * a.P3)
     return hipErrorInvalidValue;
-  if constexpr (sizeof(F) == 8) {
-    if (tab3 && a.m1 == XYP - 1 && a.m2 == XYP - 1) return launch_xy<F, true>(spec, tab3, a, s);
-  }
+  if (tab3 && a.m1 == XYP - 1 && a.m2 == XYP - 1) return launch_xy<F, true>(spec, tab3, a, s);
   return launch_xy<F, false>(spec, tab, a, s);
 }
 
