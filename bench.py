@@ -73,11 +73,11 @@ def parse():
 
 
 def dst_path(w, prec):
-    """Which DST-I product the library runs: 'fold2' (FP64, odd m, padded
-    length a multiple of 128), 'fold' (2D/3D otherwise, BF16x3 included),
-    'dense' (1D)."""
+    """Which DST-I product the library runs: 'fold2' (FP64 and FP32, odd m,
+    padded length a multiple of 128), 'fold' (2D/3D otherwise, BF16x3
+    included), 'dense' (1D)."""
     P = -(-w.m1 // 64) * 64
-    if w.dim >= 2 and prec == "fp64" and w.m1 % 2 == 1 and P % 128 == 0:
+    if w.dim >= 2 and prec in ("fp64", "fp32") and w.m1 % 2 == 1 and P % 128 == 0:
         return "fold2"
     if w.dim >= 2:
         return "fold"

@@ -429,7 +429,9 @@ bool use_rows(const aao_ctx* c) {
 bool use_fused_last(const aao_ctx* c) {
   const int d = c->g.dim - 1;
   const int Ps[3] = {c->g.P1, c->g.P2, c->g.P3};
-  return c->g.dim >= 2 && c->prec == AAO_FP64 && c->FqT64[d] && (Ps[d] == 128 || Ps[d] == 256);
+  const bool tables = c->prec == AAO_FP64 ? c->FqT64[d] != nullptr
+                                          : (c->prec == AAO_FP32 && c->FqT32[d] != nullptr);
+  return c->g.dim >= 2 && tables && (Ps[d] == 128 || Ps[d] == 256);
 }
 
 hipError_t fused_last(aao_ctx* c, const void* in, void* out, double* const* divtm,
@@ -439,9 +441,13 @@ hipError_t fused_last(aao_ctx* c, const void* in, void* out, double* const* divt
   const int d = g.dim - 1;
   FoldArgs f = fold_args(c, d, real_ends);
   f.ndt = f.ndt * 64 / 16;   // 16-column tiles
-  return launch_dst_fold2_fused((const double*)in, (double*)out, c->FqT64[d], f, c->lam,
-                                divtm[0], g.dim >= 2 ? divtm[1] : nullptr,
-                                g.dim >= 3 ? divtm[2] : nullptr, c->stream);
+  double* const t2 = g.dim >= 2 ? divtm[1] : nullptr;
+  double* const t3 = g.dim >= 3 ? divtm[2] : nullptr;
+  if (c->prec == AAO_FP64)
+    return launch_dst_fold2_fused((const double*)in, (double*)out, c->FqT64[d], f, c->lam,
+                                  divtm[0], t2, t3, c->stream);
+  return launch_dst_fold2_fused((const float*)in, (float*)out, c->FqT32[d], f, c->lam, divtm[0],
+                                t2, t3, c->stream);
 }
 
 hipError_t fold_product(aao_ctx* c, int d, const void* in, void* out, double* const* divtm,

@@ -216,12 +216,14 @@ hipError_t launch_dst_fold2(const T* in, T* out, const T* tabs, const FoldArgs& 
                             const double* tmu3, hipStream_t s);
 
 // Forward product, shifted divide and inverse product along one LEFT axis (the
-// last forward axis: y in 2D, z in 3D) in one kernel: FP64, odd m, P_d = 128 or
-// 256, f.ndt = columns / 16.  tt = the two-level fold tables transposed,
-// [4][Hq][Hq] as [table][t][q].  lam and tmu1..tmu3 as for the divide.
-hipError_t launch_dst_fold2_fused(const double* in, double* out, const double* tt,
-                                  const FoldArgs& f, const double* lam, const double* tmu1,
-                                  const double* tmu2, const double* tmu3, hipStream_t s);
+// last forward axis: y in 2D, z in 3D) in one kernel: FP64 or FP32 (the
+// divide then in FP32), odd m, P_d = 128 or 256, f.ndt = columns / 16.  tt =
+// the two-level fold tables transposed, [4][Hq][Hq] as [table][t][q], in the
+// spectrum's type.  lam and tmu1..tmu3 as for the divide.
+template <typename T>
+hipError_t launch_dst_fold2_fused(const T* in, T* out, const T* tt, const FoldArgs& f,
+                                  const double* lam, const double* tmu1, const double* tmu2,
+                                  const double* tmu3, hipStream_t s);
 // Two-level folded product along x (axis 0, no divide) with 16 whole rows per
 // block, FP64, odd m, P1 = 128 or 256; f.ndt counts 16-row tiles per plane.
 hipError_t launch_dst_fold2_rows(const double* in, double* out, const double* tt,

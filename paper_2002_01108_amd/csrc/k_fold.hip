@@ -855,7 +855,7 @@ hipError_t launch_fold2(const T* in, T* out, const T* tabs, const FoldArgs& f, b
 
 // ---------------------------------------------------------------- fused y-fwd, divide, y-inv
 // Along the axis of the shifted divide (y in 2D, z in 3D) the forward product,
-// the divide and the inverse product run in one kernel for FP64 with odd m and
+// the divide and the inverse product run in one kernel (FP64 or FP32) with odd m and
 // P = 4 HQ (two-level fold).  A block owns 16 columns (x, or the flattened
 // (y, x) for z) of one plane pair: it stages the whole column tile in LDS, each
 // wave forms the forward quarter products for 16 quarter indices q, and the
@@ -868,17 +868,18 @@ hipError_t launch_fold2(const T* in, T* out, const T* tabs, const FoldArgs& f, b
 // read consecutive q.
 constexpr int FCF = 16;
 
-template <int HQ>
+template <typename T, int HQ>
 __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(2))) void k_dst_fold2_fused(
-    const double* in, double* out, const double* __restrict__ tt,
+    const T* in, T* out, const T* __restrict__ tt,
     FoldArgs f, const double* __restrict__ lam, const double* __restrict__ tmu1,
     const double* __restrict__ tmu2, const double* __restrict__ tmu3) {
-  using V = d4;
+  using V = typename Mf<T>::V;
+  using T2 = std::conditional_t<sizeof(T) == 8, double2, float2>;
   constexpr int P = 4 * HQ, NT = 64 * (HQ / 16);
   // the operands of one quarter-product pass, Cc[pl][combo][t][c]: combo
   // 2 par + sign holds x_{2t+par} + x_{2t'+par} (sign 0) or - (sign 1); first
   // the forward product's inputs, then the inverse product's
-  __shared__ double Cc[2][4][HQ][FCF];
+  __shared__ T Cc[2][4][HQ][FCF];
   __shared__ double tax[P];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -902,15 +903,15 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
   // LDS store so that their latencies overlap.
   auto mirror = [&](int t, int par) { return par ? h - 2 - t : h - 1 - t; };
   constexpr int NST = 2 * 2 * HQ * (FCF / 2) / NT;   // (pl, par, t, column pair) per thread
-  double2 xa[NST], xb[NST];
+  T2 xa[NST], xb[NST];
 #pragma unroll
   for (int i = 0; i < NST; ++i) {
     const int e = tid + i * NT, c2 = e % (FCF / 2), r = e / (FCF / 2);
     const int t = r % HQ, par = (r / HQ) & 1, pl = r / (2 * HQ);
     const int mir = mirror(t, par), mc = mir > t ? mir : t;   // in range either way
-    const double* src = in + (pl ? base1 : base0) + d0 + 2 * c2;
-    xa[i] = *reinterpret_cast<const double2*>(src + (int64_t)(2 * t + par) * f.R);
-    xb[i] = *reinterpret_cast<const double2*>(src + (int64_t)(2 * mc + par) * f.R);
+    const T* src = in + (pl ? base1 : base0) + d0 + 2 * c2;
+    xa[i] = *reinterpret_cast<const T2*>(src + (int64_t)(2 * t + par) * f.R);
+    xb[i] = *reinterpret_cast<const T2*>(src + (int64_t)(2 * mc + par) * f.R);
   }
 #pragma unroll
   for (int i = 0; i < NST; ++i) {
@@ -920,10 +921,10 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
     // a proper pair gives + and -; the middle (t' = t) keeps x alone in +;
     // beyond the pairs both are zero (those rows are another t's mirrors)
     const bool pair = mir > t, mid = mir == t;
-    Cc[pl][2 * par][t][2 * c2] = pair ? xa[i].x + xb[i].x : (mid ? xa[i].x : 0.0);
-    Cc[pl][2 * par][t][2 * c2 + 1] = pair ? xa[i].y + xb[i].y : (mid ? xa[i].y : 0.0);
-    Cc[pl][2 * par + 1][t][2 * c2] = pair ? xa[i].x - xb[i].x : 0.0;
-    Cc[pl][2 * par + 1][t][2 * c2 + 1] = pair ? xa[i].y - xb[i].y : 0.0;
+    Cc[pl][2 * par][t][2 * c2] = pair ? xa[i].x + xb[i].x : (mid ? xa[i].x : T(0));
+    Cc[pl][2 * par][t][2 * c2 + 1] = pair ? xa[i].y + xb[i].y : (mid ? xa[i].y : T(0));
+    Cc[pl][2 * par + 1][t][2 * c2] = pair ? xa[i].x - xb[i].x : T(0);
+    Cc[pl][2 * par + 1][t][2 * c2 + 1] = pair ? xa[i].y - xb[i].y : T(0);
   }
   {
     const double* ax_tab = f.axis == 1 ? tmu2 : tmu3;
@@ -953,7 +954,7 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
   // fragments come from L2 through a three-slot register ring, loaded two K
   // steps ahead of the matrix-core work (the loop is unrolled so the ring
   // slots are fixed registers and no copy waits for a load in flight)
-  auto load_a = [&](int ks, double (&a)[4]) {
+  auto load_a = [&](int ks, T (&a)[4]) {
     const int t = 4 * ks + lk;
 #pragma unroll
     for (int tb = 0; tb < 4; ++tb) a[tb] = tt[((int64_t)tb * HQ + t) * HQ + q0 + lr];
@@ -961,14 +962,14 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
   auto product = [&]() {
     constexpr int NK = HQ / 4;
     clear();
-    double ring[3][4];
+    T ring[3][4];
     load_a(0, ring[0]);
     load_a(1, ring[1]);
 #pragma unroll
     for (int ks = 0; ks < NK; ++ks) {
       const int t = 4 * ks + lk;
       if (ks + 2 < NK) load_a(ks + 2, ring[(ks + 2) % 3]);
-      double b[2][2][2];   // b[pl][par][sign]
+      T b[2][2][2];   // b[pl][par][sign]
 #pragma unroll
       for (int pl = 0; pl < 2; ++pl)
 #pragma unroll
@@ -980,47 +981,48 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
       for (int tb = 0; tb < 4; ++tb)
 #pragma unroll
         for (int pl = 0; pl < 2; ++pl)
-          acc[tb][pl] = __builtin_amdgcn_mfma_f64_16x16x4f64(ring[ks % 3][tb], b[pl][tb >> 1][tb & 1],
-                                                             acc[tb][pl], 0, 0, 0);
+          acc[tb][pl] = Mf<T>::mfma(ring[ks % 3][tb], b[pl][tb >> 1][tb & 1], acc[tb][pl]);
     }
   };
 
   // ---- forward product
   product();
 
-  auto divide = [&](double& vr, double& vi, int a) {
-    if (!dvalid) { vr = 0.0; vi = 0.0; return; }
+  // in T arithmetic, the FP64 divisor terms rounded to T (as the unfused
+  // FP32 epilogue does)
+  auto divide = [&](T& vr, T& vi, int a) {
+    if (!dvalid) { vr = T(0); vi = T(0); return; }
     const double mu = cst + tax[a];
     if (real_pair) {
-      vr = vr / (lre + mu);
-      vi = vi / (lre1 + mu);
+      vr = vr / (T)(lre + mu);
+      vi = vi / (T)(lre1 + mu);
     } else {
-      const double cc = lre + mu, dd = lim;
-      const double inv = 1.0 / (cc * cc + dd * dd);
-      const double nr = (vr * cc + vi * dd) * inv;
-      const double ni = (vi * cc - vr * dd) * inv;
+      const T cc = (T)(lre + mu), dd = (T)lim;
+      const T inv = T(1) / (cc * cc + dd * dd);
+      const T nr = (vr * cc + vi * dd) * inv;
+      const T ni = (vi * cc - vr * dd) * inv;
       vr = nr;
       vi = ni;
     }
-      if (f.ims_r) {   // Q1 elements: B_k = M (lambda_k I + tau M^{-1} K), sine basis
-        const double ms = f.ims_c[dl] * f.ims_r[a];
-        vr *= ms;
-        vi *= ms;
-      }
-    };
+    if (f.ims_r) {   // Q1 elements: B_k = M (lambda_k I + tau M^{-1} K), sine basis
+      const T ms = (T)(f.ims_c[dl] * f.ims_r[a]);
+      vr *= ms;
+      vi *= ms;
+    }
+  };
   // epilogue -> divide -> inverse inputs, held in registers until the tile is free
-  double cmb[4][2][4];   // [v][plane][combo u+, u-, v+, v-]
+  T cmb[4][2][4];   // [v][plane][combo u+, u-, v+, v-]
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int q = q0 + lk + 4 * v;
+    const int q = q0 + Mf<T>::row(lk, v);
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
       const int r = 2 * q + s2;   // s2 = 0: even pair (u), 1: odd pair (v)
       const int rb = m - 1 - r;
-      double tr = 0.0, ti = 0.0, br = 0.0, bi = 0.0;   // top row r and bottom row rb
+      T tr = T(0), ti = T(0), br = T(0), bi = T(0);   // top row r and bottom row rb
       if (r < h) {
-        const double ore = acc[s2][0][v], ere = acc[2 + s2][0][v];
-        const double oim = acc[s2][1][v], eim = acc[2 + s2][1][v];
+        const T ore = acc[s2][0][v], ere = acc[2 + s2][0][v];
+        const T oim = acc[s2][1][v], eim = acc[2 + s2][1][v];
         tr = ore + ere;
         ti = oim + eim;
         divide(tr, ti, r);
@@ -1032,10 +1034,10 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
       }
       // pair (r, rb): + and -; the middle (rb == r) keeps y_r alone in +
       const bool pair = r < h && rb > r, mid = r < h && rb == r;
-      cmb[v][0][2 * s2] = pair ? tr + br : (mid ? tr : 0.0);
-      cmb[v][0][2 * s2 + 1] = pair ? tr - br : 0.0;
-      cmb[v][1][2 * s2] = pair ? ti + bi : (mid ? ti : 0.0);
-      cmb[v][1][2 * s2 + 1] = pair ? ti - bi : 0.0;
+      cmb[v][0][2 * s2] = pair ? tr + br : (mid ? tr : T(0));
+      cmb[v][0][2 * s2 + 1] = pair ? tr - br : T(0);
+      cmb[v][1][2 * s2] = pair ? ti + bi : (mid ? ti : T(0));
+      cmb[v][1][2 * s2 + 1] = pair ? ti - bi : T(0);
     }
   }
   __syncthreads();   // every wave is done reading the forward operands
@@ -1044,35 +1046,35 @@ __global__ __launch_bounds__(64 * (HQ / 16)) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
     for (int pl = 0; pl < 2; ++pl)
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) Cc[pl][cb][q0 + lk + 4 * v][lr] = cmb[v][pl][cb];
+      for (int cb = 0; cb < 4; ++cb) Cc[pl][cb][q0 + Mf<T>::row(lk, v)][lr] = cmb[v][pl][cb];
   __syncthreads();
 
   // ---- inverse product and output rows
   product();
-  double* ob0 = out + base0;
-  double* ob1 = out + base1;
+  T* ob0 = out + base0;
+  T* ob1 = out + base1;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int q = q0 + lk + 4 * v;
+    const int q = q0 + Mf<T>::row(lk, v);
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
       const int r = 2 * q + s2, rb = m - 1 - r;
       if (r >= h) continue;
-      const double ore = acc[s2][0][v], ere = acc[2 + s2][0][v];
-      const double oim = acc[s2][1][v], eim = acc[2 + s2][1][v];
+      const T ore = acc[s2][0][v], ere = acc[2 + s2][0][v];
+      const T oim = acc[s2][1][v], eim = acc[2 + s2][1][v];
       const int64_t offt = (int64_t)r * f.R + dl, offb = (int64_t)rb * f.R + dl;
-      ob0[offt] = dvalid ? ore + ere : 0.0;
-      ob1[offt] = dvalid ? oim + eim : 0.0;
+      ob0[offt] = dvalid ? ore + ere : T(0);
+      ob1[offt] = dvalid ? oim + eim : T(0);
       if (rb > r) {
-        ob0[offb] = dvalid ? ore - ere : 0.0;
-        ob1[offb] = dvalid ? oim - eim : 0.0;
+        ob0[offb] = dvalid ? ore - ere : T(0);
+        ob1[offb] = dvalid ? oim - eim : T(0);
       }
     }
   }
   // padding rows m .. P-1 of this column tile
   for (int e = tid; e < 2 * (P - m) * FCF; e += NT) {
     const int pl = e / ((P - m) * FCF), rem = e % ((P - m) * FCF);
-    (pl ? ob1 : ob0)[(int64_t)(m + rem / FCF) * f.R + d0 + rem % FCF] = 0.0;
+    (pl ? ob1 : ob0)[(int64_t)(m + rem / FCF) * f.R + d0 + rem % FCF] = T(0);
   }
 }
 
@@ -1252,9 +1254,10 @@ hipError_t launch_dst_fold2(const T* in, T* out, const T* tabs, const FoldArgs& 
   return launch_fold2<T>(in, out, tabs, f, left, lam, tmu1, tmu2, tmu3, s);
 }
 
-hipError_t launch_dst_fold2_fused(const double* in, double* out, const double* tt,
-                                  const FoldArgs& f, const double* lam, const double* tmu1,
-                                  const double* tmu2, const double* tmu3, hipStream_t s) {
+template <typename T>
+hipError_t launch_dst_fold2_fused(const T* in, T* out, const T* tt, const FoldArgs& f,
+                                  const double* lam, const double* tmu1, const double* tmu2,
+                                  const double* tmu3, hipStream_t s) {
   const int P = 2 * f.Hp;
   if (f.m % 2 == 0 || (P != 128 && P != 256) || (f.m + 1) / 2 > f.Hp || f.ndt < 1 ||
       f.nout < 1 || f.nk < 1 || (f.axis != 1 && f.axis != 2) || !lam)
@@ -1262,13 +1265,19 @@ hipError_t launch_dst_fold2_fused(const double* in, double* out, const double* t
   const int64_t nblk = (int64_t)f.ndt * f.nout * f.nk;
   if (nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
   if (P == 256)
-    hipLaunchKernelGGL((k_dst_fold2_fused<64>), dim3((unsigned)nblk), dim3(256), 0, s, in, out, tt,
-                       f, lam, tmu1, tmu2, tmu3);
+    hipLaunchKernelGGL((k_dst_fold2_fused<T, 64>), dim3((unsigned)nblk), dim3(256), 0, s, in, out,
+                       tt, f, lam, tmu1, tmu2, tmu3);
   else
-    hipLaunchKernelGGL((k_dst_fold2_fused<32>), dim3((unsigned)nblk), dim3(128), 0, s, in, out, tt,
-                       f, lam, tmu1, tmu2, tmu3);
+    hipLaunchKernelGGL((k_dst_fold2_fused<T, 32>), dim3((unsigned)nblk), dim3(128), 0, s, in, out,
+                       tt, f, lam, tmu1, tmu2, tmu3);
   return hipGetLastError();
 }
+template hipError_t launch_dst_fold2_fused<double>(const double*, double*, const double*,
+                                                   const FoldArgs&, const double*, const double*,
+                                                   const double*, const double*, hipStream_t);
+template hipError_t launch_dst_fold2_fused<float>(const float*, float*, const float*,
+                                                  const FoldArgs&, const double*, const double*,
+                                                  const double*, const double*, hipStream_t);
 
 hipError_t launch_dst_fold2_rows(const double* in, double* out, const double* tt,
                                  const FoldArgs& f, hipStream_t s) {
