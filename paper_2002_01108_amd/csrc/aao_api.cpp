@@ -1331,8 +1331,8 @@ aao_status aao_setup(int dim, int m1, int m2, int m3, int n, double T, double ep
       if ((st = upload(c, &c->FqT32[d], fqt32)) != AAO_OK) return bail(st);
     }
     // third fold (m = 127: m + 1 = 128 is a multiple of 4), symmetries of S:
-    // for odd rows r (r + 1 = 2a) columns j and j' = 62 - j (even j) or 60 - j
-    // (odd j) satisfy S_{r,j'} = (-1)^{a+1} S_{r,j}; for even rows and odd
+    // for odd rows r (r + 1 = 2a) columns j and j' = 62 - j (either parity)
+    // satisfy S_{r,j'} = (-1)^{a+1} S_{r,j}; for even rows and odd
     // columns j = 2t + 1, S_{62-r,j} = (-1)^t S_{r,j}.  Tables [q][kappa]:
     // T0 (32 x 32): S_{2qo, jk} with qo = q (q < 16) or 47 - q, jk = 2 kappa
     // (kappa < 16) or 94 - 2 kappa; then 16 x 16: S_{4q+1, 2k}, S_{4q+3, 2k},

@@ -37,14 +37,15 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // the phases.  Padding (rows >= m2, columns >= m1) must be zero on input and
 // stays zero.
 // FP32 (the FP32 preconditioner): the same with v_mfma_f32_16x16x4f32, 80 KB of
-// LDS (two blocks per CU), the slab swizzled by (row & 15) << 3 (64 banks of
+// LDS (74 KB on the third fold; two blocks per CU), the slab swizzled by (row & 15) << 3 (64 banks of
 // 32-bit words: the 16 rows of a fragment read land in pairs on 32 banks) and
 // the tables transposed ([tb][t][q], q contiguous, q ^ 16 ((t >> 1) & 1)).
 // Third fold (m1 = m2 = 127, so m + 1 = 128 is a multiple of 4): with
 // the quarter products written over output index q and pair index t (outputs
 // r = 2q + s, elements j = 2t + b), three of the four split again.  For r odd
-// (r + 1 = 2a) the element pairs j <-> 62 - j (b = 0) and j <-> 60 - j (b = 1),
-// i.e. J = j + 1 <-> 64 - J, have S_{r,j'} = (-1)^{a+1} S_{r,j}: the minus
+// (r + 1 = 2a) the element pairs j <-> j' = 62 - j (of either parity b; the
+// odd elements j = 2t + 1 pair with 61 - 2t), i.e. J = j + 1 <-> 64 - J, have
+// S_{r,j'} = (-1)^{a+1} S_{r,j}: the minus
 // combinations q_j = x_j - x_{126-j} fold once more into q_j +- q_{j'}, the
 // sign set by q's parity (16 x 16 products instead of 32 x 32).  For r even
 // and j odd the outputs pair: S_{62-r, j} = (-1)^t S_{r,j} (j = 2t + 1), so
