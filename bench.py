@@ -120,9 +120,10 @@ def dst_product_flops(w, prec):
 
 
 def fold3_slab(w, prec):
-    """FP64 3D with m1 = m2 = 127: the slab launch runs the x and y products on
-    the third fold (one 32 x 32 and six 16 x 16 products per vector: 2560
-    multiply-adds against the two-level fold's 4064)."""
+    """3D with m = 127 on every axis in FP64: the slab launch runs the x and y
+    products and the z pass the z products on the third fold (one 32 x 32 and
+    six 16 x 16 products per vector: 2560 multiply-adds against the two-level
+    fold's 4064)."""
     return prec == "fp64" and w.dim == 3 and w.m1 == 127
 
 
@@ -134,7 +135,7 @@ def dst_flops_per_launch(w, prec):
     per = dst_product_flops(w, prec)
     total = per * products
     if fold3_slab(w, prec):
-        total -= 4 * per * (1.0 - 2560.0 / 4064.0)   # x and y, each way
+        total -= products * per * (1.0 - 2560.0 / 4064.0)   # every axis, each way
     return total / launches
 
 
@@ -579,7 +580,7 @@ def dst_roofline(w, prec, prof):
     launches, products = dst_launch_mix(w, prec)
     mix = (f"{products} DST-I mode products in {launches} launches per P^-1"
            + (", the last axis' forward, divide and inverse fused" if launches < products else "")
-           + (", x and y on a third fold" if fold3_slab(w, prec) else ""))
+           + (", all on a third fold" if fold3_slab(w, prec) else ""))
     achieved = nbytes / avg_s / 1e9 if dst_n else None
     return {"kernel": f"dst_{path}_{prec} ({mix})",
             "bound": "hbm", "achieved": achieved, "peak": PEAKS["hbm_GBs"], "unit": "GB/s",

@@ -272,6 +272,27 @@ def step2(K: sp.spmatrix, tau: float, lam: np.ndarray, yt: np.ndarray,
     return out
 
 
+def step2_sine(ms, tau: float, lam: np.ndarray, yt: np.ndarray,
+               workers: int | None = None) -> np.ndarray:
+    """Step 2 (eq. (blockdiaginv)) for the constant-coefficient finite-difference
+    K_h, in the sine basis that diagonalises it (Section 4: B_k = lambda_k I +
+    tau K_h is diagonalised by the DST-I along every axis):
+    ztilde_k = S diag(1 / (lambda_k + tau mu)) S ytilde_k, S applied to the real
+    and imaginary parts.  Same result as `step2` up to rounding, at a cost that
+    3D grids of 127^3 points allow."""
+    ms = [int(v) for v in ms]
+    shape = tuple(reversed(ms))
+    mu = fd_eigenvalues(ms)
+    out = np.empty(np.shape(yt), dtype=np.complex128)
+    for k in range(yt.shape[0]):
+        b = np.asarray(yt[k]).reshape(shape)
+        sb = sine_transform(b.real, workers) + 1j * sine_transform(b.imag, workers)
+        sb = sb / (lam[k] + tau * mu)
+        z = sine_transform(sb.real, workers) + 1j * sine_transform(sb.imag, workers)
+        out[k] = z.reshape(-1)
+    return out
+
+
 def hermitian_complete(zt_half: np.ndarray, n: int) -> np.ndarray:
     """Rebuild all N blocks from k = 0..N/2 using ztilde^{N-k} = conj(ztilde^k)
     (closing argument of Section 4).  The imaginary parts of blocks k = 0 and

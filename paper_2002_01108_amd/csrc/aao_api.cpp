@@ -85,7 +85,7 @@ struct aao_ctx {
   // two-level fold tables [4][P_d/4][P_d/4] (odd m_d, P_d % 128 == 0), else null,
   // and their transposes [table][t][q] for the fused forward-divide-inverse kernel
   double* Fq64[3] = {nullptr, nullptr, nullptr};
-  double* F3_64[3] = {nullptr, nullptr, nullptr};  // third-fold tables (x axis, m_1 = 127)
+  double* F3_64[3] = {nullptr, nullptr, nullptr};  // third-fold tables (axes with m_d = 127)
   float* F3_32[3] = {nullptr, nullptr, nullptr};   // F3_64 in FP32
   double* FqT64[3] = {nullptr, nullptr, nullptr};
   float* FqT32[3] = {nullptr, nullptr, nullptr};   // FqT64 in FP32 (the FP32 slab kernel)
@@ -509,6 +509,32 @@ hipError_t xy_product(aao_ctx* c, void* spec, bool real_ends) {
   return launch_dst_xy((float*)spec, c->FqT32[0], a, c->stream, (const float*)c->F3_32[0]);
 }
 
+// The z axis of a 3D FP64 spectrum with m3 = 127 and P = 128 on every axis:
+// forward product, shifted divide and inverse product in one in-place pass
+// (both planes of a slice in one block).
+bool use_zdiv(const aao_ctx* c) {
+  const Geometry& g = c->g;
+  return g.dim == 3 && c->prec == AAO_FP64 && g.m3 == 127 && g.P1 == 128 && g.P2 == 128 &&
+         g.P3 == 128 && c->F3_64[2];
+}
+
+hipError_t zdiv_product(aao_ctx* c, void* spec, double* const* divtm, bool real_ends) {
+  ProfScope ps(c, AAO_K_DST);
+  const Geometry& g = c->g;
+  SlabArgs a;
+  a.PS = g.PS;
+  a.nk = real_ends ? g.nh - 1 : g.nh;
+  a.packed = real_ends ? 1 : 0;
+  a.m1 = g.m1;
+  a.m2 = g.m2;
+  a.m3 = g.m3;
+  a.P1 = g.P1;
+  a.P2 = g.P2;
+  a.P3 = g.P3;
+  return launch_dst_zdiv((double*)spec, c->F3_64[2], a, c->lam, divtm[0], divtm[1], divtm[2],
+                         c->stream);
+}
+
 // One mode product along axis d (0 = x, 1 = y, 2 = z) from `in` to `out`
 // as a dense batched GEMM (1D).
 hipError_t mode_product(aao_ctx* c, int d, const void* in, void* out) {
@@ -601,7 +627,9 @@ aao_status dst_solve(aao_ctx* c, void** cur, void** other, bool mean, bool real_
     if (use_xy(c)) {
       // x and y in one in-place launch each way around the z products
       HIPCHK(c, xy_product(c, *cur, real_ends));
-      if (fuse) {
+      if (use_zdiv(c)) {
+        HIPCHK(c, zdiv_product(c, *cur, tm, real_ends));
+      } else if (fuse) {
         HIPCHK(c, fused_last(c, *cur, *other, tm, real_ends));
         std::swap(*cur, *other);
       } else {
@@ -1338,7 +1366,7 @@ aao_status aao_setup(int dim, int m1, int m2, int m3, int n, double T, double ep
     // (kappa < 16) or 94 - 2 kappa; then 16 x 16: S_{4q+1, 2k}, S_{4q+3, 2k},
     // S_{4q+1, 2k+1}, S_{4q+3, 2k+1}, S_{2q, 4k+1}, S_{2q, 4k+3}, the entries
     // of self-paired combinations (k = 15 in the 3rd, 4th and 6th) halved.
-    if (d == 0 && md == 127 && P == 128) {   // the slab kernel's x and y products
+    if (md == 127 && P == 128) {   // slab x and y products; the z pass
       std::vector<double> f3((size_t)32 * 32 + 6 * 16 * 16, 0.0);
       auto Sv = [&](int r, int j) { return S[(size_t)r * P + j]; };
       for (int q = 0; q < 32; ++q)

@@ -205,6 +205,15 @@ struct SlabArgs {
 template <typename F>
 hipError_t launch_dst_xy(F* spec, const F* tab, const SlabArgs& a, hipStream_t s,
                          const F* tab3 = nullptr);
+// The last axis of a 3D FP64 spectrum (P1 = P2 = P3 = 128, m3 = 127) in one
+// in-place pass on the third fold: forward product, shifted divide by
+// lambda_k + tmu1[x] + tmu2[y] + tmu3[z] (lam as for launch_dst_fold), inverse
+// product.  tab3 as for launch_dst_xy (the z axis' tables).  Slices: the nk
+// blocks (packed as in SlabArgs) times y < m2 times two x halves; y rows
+// >= m2 are not touched, padding elsewhere is zero on input and on output.
+hipError_t launch_dst_zdiv(double* spec, const double* tab3, const SlabArgs& a,
+                           const double* lam, const double* tmu1, const double* tmu2,
+                           const double* tmu3, hipStream_t s);
 
 // Two-level fold for odd m (P_d a multiple of 128): tabs = [4][Hq][Hq], Hq = P_d/4,
 // the quarter tables A+, A-, B+, B- (rows q: output rows 2q for +, 2q+1 for -;

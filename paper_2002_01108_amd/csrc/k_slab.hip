@@ -359,6 +359,191 @@ void k_dst_xy(F* __restrict__ spec, const F* __restrict__ tab, SlabArgs a) {
   }
 }
 
+
+// Last-axis forward product, shifted divide and inverse product of a 3D
+// spectrum in one in-place pass (P3 = 128, m3 = 127, on the third fold): a
+// block owns, for one frequency block k, one y row and one half of the x range
+// (64 columns), the (z, x) slices of both planes (2 x 128 x 64 elements: 128 KB
+// FP64, 64 KB FP32) in LDS, so the complex divide finds the real and imaginary
+// part of every element in the block.  Wave w runs plane w / 4 on columns
+// 16 (w % 4) .. + 15 with the phase-y code of the slab kernel (the table as
+// the MFMA A operand, the data as B); between the products one pass over the
+// slices divides by lambda_k + tau (mu_x + mu_y + mu_z).  Persistent like the
+// slab kernel: the next slice pair is prefetched into registers while the
+// current one is computed.  Rows (z) >= m3 and columns (x) >= m1 are padding:
+// zero on input, zero on output; y rows >= m2 are not visited (zero stays zero).
+template <typename F>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+void k_dst_zdiv(F* __restrict__ spec, const F* __restrict__ tab, SlabArgs a,
+                const double* __restrict__ lam, const double* __restrict__ tmu1,
+                const double* __restrict__ tmu2, const double* __restrict__ tmu3) {
+  // FP64 only: in FP32 the four k rows an operand read touches would share
+  // 32-bit banks in this unswizzled layout
+  static_assert(sizeof(F) == 8, "the z pass is built for FP64");
+  using S = Slab<F>;
+  using V = typename S::V;
+  using T2 = typename S::T2;
+  constexpr int XW = 64;                 // columns per slice
+  __shared__ F X[2][XYP * XW];           // [plane][z * 64 + x]
+  __shared__ F T[F3N];
+  __shared__ double tax[XYP];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int pw = w >> 2, cg = w & 3;     // plane and column group of this wave
+  int lr = lane & 15, lk = lane >> 4;
+  const int nslab = a.nk * a.m2 * 2;
+
+  for (int i = tid; i < F3N; i += 512) {
+    if (i < XYQ * XYQ) {
+      T[S::t0_at(i / XYQ, i % XYQ)] = tab[i];
+    } else {
+      const int e = i - XYQ * XYQ;
+      T[S::t16_at(e / 256, (e / 16) % 16, e % 16)] = tab[i];
+    }
+  }
+  for (int i = tid; i < XYP; i += 512) tax[i] = tmu3[i];
+  auto t0 = [&](int q, int k) { return T[S::t0_at(q, k)]; };
+  auto t16 = [&](int tb, int q, int k) { return T[S::t16_at(tb, q, k)]; };
+
+  // slice s: x half xh, y row, frequency block k; plane bases as in the DST
+  // products (the packed block pairs the real planes of k = 0 and n/2)
+  struct Slice {
+    int xh, y, k;
+    int64_t b0, b1;
+  };
+  auto slice = [&](int s) {
+    Slice c;
+    c.xh = s & 1;
+    s >>= 1;
+    c.y = s % a.m2;
+    c.k = s / a.m2;
+    const int64_t off = (int64_t)c.y * XYP + c.xh * XW;
+    c.b0 = (int64_t)c.k * 2 * a.PS + off;
+    c.b1 = ((a.packed && c.k == 0) ? (int64_t)a.nk * 2 * a.PS : c.b0 - off + a.PS) + off;
+    return c;
+  };
+  // thread -> (plane, z row, column pair): 32 column pairs per row; load i
+  // covers rows 16 i + tid / 32 of plane 0 (i < 8) or plane 1 (i >= 8)
+  const int cp = tid & 31, rz = tid >> 5;
+  const int64_t zs = (int64_t)XYP * XYP;   // z row stride
+  T2 pf[16];
+  auto load = [&](int s) {
+    const Slice c = slice(s);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const F* b = spec + (i < 8 ? c.b0 : c.b1) + (int64_t)(16 * (i & 7) + rz) * zs;
+      pf[i] = reinterpret_cast<const T2*>(b)[cp];
+    }
+  };
+
+  // one product of plane pw on columns 16 cg .. + 15, outputs back into X
+  auto product = [&]() {
+    const int col = 16 * cg + lr;
+    F* xp = X[pw];
+    auto xr = [&](int j) { return xp[j * XW + col]; };
+    V aP0{0, 0, 0, 0}, aP1{0, 0, 0, 0}, aMe{0, 0, 0, 0}, aMo{0, 0, 0, 0};
+    V bMe{0, 0, 0, 0}, bMo{0, 0, 0, 0}, bEv{0, 0, 0, 0}, bOd{0, 0, 0, 0};
+#pragma unroll 2
+    for (int ks = 0; ks < 4; ++ks) {
+      const int t = 4 * ks + lk;
+      const F xa = xr(2 * t), xb = xr(126 - 2 * t), xc = xr(62 - 2 * t), xd = xr(64 + 2 * t);
+      const F xe = xr(2 * t + 1), xf = xr(125 - 2 * t), xg = xr(61 - 2 * t), xh = xr(65 + 2 * t);
+      const F xi = xr(4 * t + 1), xj = xr(125 - 4 * t), xk = xr(4 * t + 3), xl = xr(123 - 4 * t);
+      const F pA0 = xa + xb, qA0 = xa - xb, pA1 = xc + xd, qA1 = xc - xd;
+      const F qB0 = xe - xf, qB1 = xg - xh;
+      aP0 = S::mfma(t0(lr, t), pA0, aP0);
+      aP1 = S::mfma(t0(16 + lr, t), pA0, aP1);
+      aP0 = S::mfma(t0(lr, 16 + t), pA1, aP0);
+      aP1 = S::mfma(t0(16 + lr, 16 + t), pA1, aP1);
+      aMe = S::mfma(t16(0, lr, t), qA0 + qA1, aMe);
+      aMo = S::mfma(t16(1, lr, t), qA0 - qA1, aMo);
+      bMe = S::mfma(t16(2, lr, t), qB0 + qB1, bMe);
+      bMo = S::mfma(t16(3, lr, t), qB0 - qB1, bMo);
+      bEv = S::mfma(t16(4, lr, t), xi + xj, bEv);
+      bOd = S::mfma(t16(5, lr, t), xk + xl, bOd);
+    }
+    // a wave reads and writes only its own columns of its own plane
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int q = S::orow(lk, v);
+      const F E0 = bEv[v] + bOd[v], E1 = bEv[v] - bOd[v];
+      xp[(2 * q) * XW + col] = aP0[v] + E0;
+      xp[(126 - 2 * q) * XW + col] = aP0[v] - E0;
+      xp[(62 - 2 * q) * XW + col] = aP1[v] + E1;
+      xp[(64 + 2 * q) * XW + col] = aP1[v] - E1;
+      xp[(4 * q + 1) * XW + col] = aMe[v] + bMe[v];
+      xp[(125 - 4 * q) * XW + col] = aMe[v] - bMe[v];
+      xp[(4 * q + 3) * XW + col] = aMo[v] + bMo[v];
+      if (q < 15) xp[(123 - 4 * q) * XW + col] = aMo[v] - bMo[v];
+    }
+  };
+
+  const StripRange sr = xcd_strips(nslab);
+  if (sr.first < sr.end) load(sr.first);
+  for (int s = sr.first; s < sr.end; s += sr.step) {
+    const Slice c = slice(s);
+    int lo = lane;
+    asm volatile("" : "+v"(lo));
+    lr = lo & 15;
+    lk = lo >> 4;
+    __syncthreads();   // the previous slice's stores have read X (and T, tax are in place)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      F* xp = X[i < 8 ? 0 : 1] + (16 * (i & 7) + rz) * XW;
+      xp[2 * cp] = pf[i].x;
+      xp[2 * cp + 1] = pf[i].y;
+    }
+    if (s + sr.step < sr.end) load(s + sr.step);
+    __syncthreads();
+
+    // ---- forward product along z
+    product();
+    __syncthreads();
+
+    // ---- shifted divide: thread -> column tid % 64, rows tid / 64 + 8 i
+    {
+      const int x = tid & (XW - 1), xg = c.xh * XW + x;
+      const bool valid = xg < a.m1;
+      const double cst = tmu1[xg] + tmu2[c.y];
+      const bool real_pair = a.packed && c.k == 0;
+      const double lre = lam[2 * c.k], lim = lam[2 * c.k + 1];
+      const double lre1 = real_pair ? lam[2 * a.nk] : 0.0;
+      for (int r = tid / XW; r < a.m3; r += 512 / XW) {
+        F vr = X[0][r * XW + x], vi = X[1][r * XW + x];
+        if (!valid) {
+          vr = F(0);
+          vi = F(0);
+        } else {
+          const double mu = cst + tax[r];
+          if (real_pair) {
+            vr = vr / (F)(lre + mu);
+            vi = vi / (F)(lre1 + mu);
+          } else {
+            const F cc = (F)(lre + mu), dd = (F)lim;
+            const F inv = F(1) / (cc * cc + dd * dd);
+            const F nr = (vr * cc + vi * dd) * inv;
+            const F ni = (vi * cc - vr * dd) * inv;
+            vr = nr;
+            vi = ni;
+          }
+        }
+        X[0][r * XW + x] = vr;
+        X[1][r * XW + x] = vi;
+      }
+    }
+    __syncthreads();
+
+    // ---- inverse product along z, then the slices back in place
+    product();
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const F* xp = X[i < 8 ? 0 : 1] + (16 * (i & 7) + rz) * XW;
+      F* b = spec + (i < 8 ? c.b0 : c.b1) + (int64_t)(16 * (i & 7) + rz) * zs;
+      reinterpret_cast<T2*>(b)[cp] = T2{xp[2 * cp], xp[2 * cp + 1]};
+    }
+  }
+}
+
 }  // namespace
 
 template <typename F, bool L3>
@@ -381,6 +566,22 @@ hipError_t launch_dst_xy(F* spec, const F* tab, const SlabArgs& a, hipStream_t s
     return hipErrorInvalidValue;
   if (tab3 && a.m1 == XYP - 1 && a.m2 == XYP - 1) return launch_xy<F, true>(spec, tab3, a, s);
   return launch_xy<F, false>(spec, tab, a, s);
+}
+
+hipError_t launch_dst_zdiv(double* spec, const double* tab3, const SlabArgs& a,
+                           const double* lam, const double* tmu1, const double* tmu2,
+                           const double* tmu3, hipStream_t s) {
+  if (!spec || !tab3 || !lam || !tmu1 || !tmu2 || !tmu3 || a.nk < 1 || a.m3 != XYP - 1 ||
+      a.m1 < 1 || a.m1 > XYP || a.m2 < 1 || a.m2 > XYP || a.P1 != XYP || a.P2 != XYP ||
+      a.P3 != XYP || a.PS != (int64_t)XYP * XYP * XYP)
+    return hipErrorInvalidValue;
+  const int64_t nslab = (int64_t)a.nk * a.m2 * 2;
+  if (nslab > 0x7fffffff) return hipErrorInvalidConfiguration;
+  static const int resident = persistent_grid(k_dst_zdiv<double>, 512);
+  if (resident < 8) return hipErrorInvalidDeviceFunction;
+  hipLaunchKernelGGL((k_dst_zdiv<double>), dim3(strip_grid(resident, nslab)), dim3(512), 0, s,
+                     spec, tab3, a, lam, tmu1, tmu2, tmu3);
+  return hipGetLastError();
 }
 
 template hipError_t launch_dst_xy<double>(double*, const double*, const SlabArgs&, hipStream_t,

@@ -51,13 +51,13 @@ def test_dst_launch_mix_and_flops():
     assert bench.dst_launch_mix(w3, "bf16x3") == (6, 6)
     assert bench.dst_launch_mix(w3, "fp32") == (3, 6)
     assert bench.dst_path(w3, "bf16x3") == "fold"
-    # the slab launch's x and y products on the third fold: 2560 of the
-    # two-level fold's 4064 multiply-adds per vector (h = 64: 32^2 + 32^2 +
-    # 32 * 32 + 32 * 31), so four of the six products are cheaper
+    # every product on the third fold (the slab launch's x and y, the z
+    # pass): 2560 of the two-level fold's 4064 multiply-adds per vector
+    # (h = 64: 32^2 + 32^2 + 32 * 32 + 32 * 31)
     assert bench.fold3_slab(w3, "fp64") and not bench.fold3_slab(w3, "fp32")
     per = bench.dst_product_flops(w3, "fp64")
     assert per == 2.0 * 4064 * w3.n * (w3.m // w3.m1)
-    expect = (2 * per + 4 * per * 2560 / 4064) / 3
+    expect = 6 * per * 2560 / 4064 / 3
     assert abs(bench.dst_flops_per_launch(w3, "fp64") / expect - 1) < 1e-12
 
 

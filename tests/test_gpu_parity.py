@@ -370,6 +370,29 @@ def test_rect_solve_matches_sequential_be(dim, ms, n, eps):
     assert rel(host(u), heat.sequential_be(K, tau, rhs)) < 1e-10
 
 
+def test_pinv_127_cubed_elementwise():
+    """127^3 x 4 (m + 1 = 128 on every axis): the x-y slab launch and the
+    in-place z pass (forward product, divide, inverse product) on the third
+    fold, against the oracle's three steps with Step 2 in the sine basis,
+    element by element; FP32 (its own z kernel) by the backward error."""
+    ms, n, eps = (127, 127, 127), 4, 0.2
+    m = 127 ** 3
+    tau = 1.0 / n
+    v = _rand((n, m), 70)
+    lam = heat.lambdas(n, eps)[: n // 2 + 1]
+    want = heat.step3(heat.step2_sine(ms, tau, lam, heat.step1(v, eps), workers=8), eps, n)
+    s = rect_solver(3, ms, n, eps)
+    z = host(s.apply_Pinv(dev(v)))
+    err = rel(z, want)
+    mx = float(np.abs(z - want).max() / np.abs(want).max())
+    print(f"127^3 x 4 P^-1: rel {err:.2e}, max-abs {mx:.2e}", flush=True)
+    assert err < 1e-11 and mx < 1e-11
+    s32 = rect_solver(3, ms, n, eps, precision="fp32")
+    z32 = host(s32.apply_Pinv(dev(v)))
+    back = rel(heat.apply_P(heat.stiffness_rect(ms), tau, eps, z32), v)
+    assert 1e-9 <= back < 5e-5
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("dim,ms,n,eps", RECT)
 def test_rect_reduced_Pinv(dim, ms, n, eps, precision):

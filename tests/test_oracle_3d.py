@@ -109,3 +109,19 @@ def test_sine_stepping_1d_2d(ms, n):
     b = heat.sequential_be(K, tau, rhs)
     assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-13
     assert np.abs(a - b).max() / np.abs(b).max() < 1e-13
+
+
+@pytest.mark.parametrize("ms,n", [((7, 5, 6), 4), ((9, 8), 6), ((11,), 8)])
+def test_step2_sine_equals_sparse_lu_step2(ms, n):
+    """Step 2 in the sine basis against the sparse complex LU of every block
+    B_k = lambda_k I + tau K_h (the oracle's plain Step 2) on rectangular grids:
+    the same linear solves, so agreement to rounding."""
+    K = heat.stiffness_rect(ms)
+    tau, eps = 1.0 / n, 0.2
+    lam = heat.lambdas(n, eps)[: n // 2 + 1]
+    rng = np.random.default_rng(5)
+    yt = rng.standard_normal((n // 2 + 1, K.shape[0])) + 1j * rng.standard_normal(
+        (n // 2 + 1, K.shape[0]))
+    want = heat.step2(K, tau, lam, yt)
+    got = heat.step2_sine(ms, tau, lam, yt)
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-13
