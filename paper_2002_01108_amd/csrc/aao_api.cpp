@@ -1110,22 +1110,28 @@ int64_t nm_of(const aao_ctx* c) { return (int64_t)c->g.n * c->g.m; }
 bool fused_stencil(const aao_ctx* c, int q) { return c->g.dim >= 2 && q <= kStencilDotsMax; }
 
 // wslot >= 0 (epi 2): ||L x||^2 is reduced into dsmall[wslot] as well.
+// w0slot >= 0 (epi 2, q = 1): ||basis[0]||^2 into dsmall[w0slot] as well
 aao_status stencil_fused(aao_ctx* c, int epi, const double* x, double* y, const double* f,
                          const double* const* basis, int q, int slot, const double* scale,
-                         int wslot = -1) {
+                         int wslot = -1, int w0slot = -1) {
   ProfScope ps(c, AAO_K_KRYLOV);
   const int64_t nb = stencil_partials(c->g);
   const int nq = epi == 2 ? q : 1;
   const bool wsq = epi == 2 && wslot >= 0;
-  TRY(ensure_part(c, (size_t)nb * (nq + (wsq ? 1 : 0))));
+  const bool w0sq = epi == 2 && q == 1 && w0slot >= 0;
+  TRY(ensure_part(c, (size_t)nb * (nq + (wsq ? 1 : 0) + (w0sq ? 1 : 0))));
   double* wpart = wsq ? c->part + nb * nq : nullptr;
+  double* w0part = w0sq ? c->part + nb * (nq + (wsq ? 1 : 0)) : nullptr;
   const double* wx = c->var ? c->wface[0] : nullptr;
-  HIPCHK(c, launch_apply_L_epi(c->g, epi, x, y, f, basis, q, c->part, wpart, c->cst[0],
+  HIPCHK(c, launch_apply_L_epi(c->g, epi, x, y, f, basis, q, c->part, wpart, w0part, c->cst[0],
                                c->cst[1], c->cst[2], wx, c->var ? c->wface[1] : nullptr,
                                c->var ? c->wface[2] : nullptr, c->stream));
   HIPCHK(c, launch_reduce_partials(c->part, (int)nb, nq, c->dsmall + slot, 0, scale, c->stream));
   if (wsq)
     HIPCHK(c, launch_reduce_partials(wpart, (int)nb, 1, c->dsmall + wslot, 0, nullptr,
+                                     c->stream));
+  if (w0sq)
+    HIPCHK(c, launch_reduce_partials(w0part, (int)nb, 1, c->dsmall + w0slot, 0, nullptr,
                                      c->stream));
   return AAO_OK;
 }
@@ -2050,22 +2056,61 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
   const int R = restart;
   // small scratch (doubles): [0] norm, [1..R+1] c1, [R+2..2R+2] c2, [2R+3] norm2,
   // [2R+4..3R+4] y, [3R+5..4R+5] 1/s_i^2, [4R+6] the constant 1 (restart
-  // residuals), [4R+7] ||L z||^2 of the fused stencil (early convergence test).  The host writes a slot only when no queued copy still reads it:
-  // y is rewritten after the next synchronising fetch, and the constant is
-  // written once per solve, so a restart never overwrites y while its copy waits.
+  // residuals), [4R+7] ||L z||^2 of the fused stencil (early convergence test),
+  // [4R+8] ||rhs||^2 from the first fused stencil.  The host writes a slot only
+  // when no queued copy still reads it: y is rewritten after the next
+  // synchronising fetch, and the constant is written once per solve, so a
+  // restart never overwrites y while its copy waits.
   const int o_nrm = 0, o_h1 = 1, o_h2 = R + 2, o_n2 = 2 * R + 3, o_y = 2 * R + 4;
-  const int o_is2 = 3 * R + 5, o_one = 4 * R + 6, o_w2 = 4 * R + 7;
-  TRY(ensure_small(c, (size_t)(4 * R + 8)));
+  const int o_is2 = 3 * R + 5, o_one = 4 * R + 6, o_w2 = 4 * R + 7, o_b2 = 4 * R + 8;
+  TRY(ensure_small(c, (size_t)(4 * R + 9)));
   c->hsmall[o_one] = 1.0;
   HIPCHK(c, hipMemcpyAsync(c->dsmall + o_one, c->hsmall + o_one, sizeof(double),
                            hipMemcpyHostToDevice, c->stream));
   const int nb = krylov_blocks(nm);
   TRY(ensure_part(c, std::max((size_t)nb * (R + 2), (size_t)stencil_partials(c->g) * 8)));
 
-  // ||rhs|| and finiteness
-  TRY(sqnorm_dev(c, rhs, nullptr, o_nrm));
-  TRY(fetch_small(c, o_nrm, 1));
-  const double bnorm2 = c->hsmall[o_nrm];
+  const bool left = c->side == AAO_LEFT;
+  // Early convergence test on large systems with the fused stencil: the
+  // stencil also returns ||w||^2, so ||w - W c1||^2 = ||w||^2 - sum_i (c1_i s_i)^2
+  // (W_i orthogonal) bounds h_{j+1,j} from above once a rounding allowance is
+  // added; if even that bound meets tol the step is the last one, and neither
+  // Gram-Schmidt pass over w is needed.  One extra synchronisation per step.
+  const bool probe = !left && tol > 0.0 && nm >= ((int64_t)1 << 22);
+  // z_j = P^{-1} W_j; flexible GMRES takes a different preconditioner per
+  // step: the first steps in the scheduled (reduced) precision, the later
+  // ones in the context's
+  auto pinv_step = [&](int step, const double* wj, double* zj) -> aao_status {
+    if (!(sched && step < c->sched_steps)) return apply_pinv(c, wj, zj);
+    const aao_precision keep = c->prec;
+    c->prec = c->sched_prec;
+    const aao_status st = apply_pinv(c, wj, zj);
+    c->prec = keep;
+    return st;
+  };
+
+  // ||rhs|| and finiteness.  A zero-guess solve on a large system takes the
+  // norm from its first step instead of a pass of its own: W_0 = rhs, and the
+  // fused stencil of that step (w = L z_0, z_0 = P^{-1} rhs) reads W_0 for its
+  // projection anyway.  That step runs before the norm is known, with the
+  // projection unscaled (1/s_0^2 = 1), and the Arnoldi loop resumes after it.
+  bool pre = probe && !use_guess && fused_stencil(c, 1);
+  double bnorm2;
+  if (pre) {
+    c->hsmall[o_is2] = 1.0;
+    HIPCHK(c, hipMemcpyAsync(c->dsmall + o_is2, c->hsmall + o_is2, sizeof(double),
+                             hipMemcpyHostToDevice, c->stream));
+    TRY(pinv_step(0, rhs, c->Z));
+    const double* basis0[1] = {rhs};
+    TRY(stencil_fused(c, 2, c->Z, c->V + nm, nullptr, basis0, 1, o_h1, c->dsmall + o_is2, o_w2,
+                      o_b2));
+    TRY(fetch_small2(c, o_h1, 1, o_w2, 2));
+    bnorm2 = c->hsmall[o_b2];
+  } else {
+    TRY(sqnorm_dev(c, rhs, nullptr, o_nrm));
+    TRY(fetch_small(c, o_nrm, 1));
+    bnorm2 = c->hsmall[o_nrm];
+  }
   if (!isfinite(bnorm2)) return fail(c, AAO_ENAN, "right-hand side is not finite");
   const double bnorm = sqrt(bnorm2);
   if (bnorm == 0.0) {
@@ -2097,11 +2142,14 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
     return AAO_OK;
   };
 
+  // a norm outside the range where 1/s^2 is representable: the loop starts
+  // over from W_0 rescaled (the first step is repeated)
+  if (pre && !in_range(bnorm)) pre = false;
+
   // Left preconditioning (Section 3, eq. (preconditionedsystem)): GMRES on
   // P^{-1} L u = P^{-1} rhs, stopping on the preconditioned residual relative
   // to that of the zero guess, ||P^{-1} rhs|| (Section 5).  The basis W then
   // holds preconditioned residuals and u is updated from W, not from Z.
-  const bool left = c->side == AAO_LEFT;
   double ref = bnorm;
   if (left) {
     TRY(apply_pinv(c, rhs, c->V));
@@ -2138,12 +2186,6 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
     gv[j + 1] = -snj * gv[j];
     gv[j] = csj * gv[j];
   };
-  // Early convergence test on large systems with the fused stencil: the
-  // stencil also returns ||w||^2, so ||w - W c1||^2 = ||w||^2 - sum_i (c1_i s_i)^2
-  // (W_i orthogonal) bounds h_{j+1,j} from above once a rounding allowance is
-  // added; if even that bound meets tol the step is the last one, and neither
-  // Gram-Schmidt pass over w is needed.  One extra synchronisation per step.
-  const bool probe = !left && tol > 0.0 && nm >= ((int64_t)1 << 22);
   int total = 0, nhist = 0;
   bool converged = false;
   bool first = true;
@@ -2239,20 +2281,13 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
       // first projection's dots come out of the stencil pass that forms
       // w = L z (2D/3D, q <= 4); with left preconditioning w = P^{-1} L W_j.
       const bool fuse = !left && fused_stencil(c, q);
+      // the first step already ran before the loop (its dots in hsmall, unscaled)
+      const bool done = pre && j == 0;
       if (left) {
         TRY(apply_L(c, wj, c->tmp));
         TRY(apply_pinv(c, c->tmp, w));
-      } else if (sched && total < c->sched_steps) {
-        // flexible GMRES takes a different preconditioner per step: the first
-        // steps in the scheduled (reduced) precision, the later ones in the
-        // context's
-        const aao_precision keep = c->prec;
-        c->prec = c->sched_prec;
-        const aao_status st = apply_pinv(c, wj, zj);
-        c->prec = keep;
-        TRY(st);
-      } else {
-        TRY(apply_pinv(c, wj, zj));
+      } else if (!done) {
+        TRY(pinv_step(total, wj, zj));
       }
       if (fuse) {
         const double* basis[kStencilDotsMax];
@@ -2262,11 +2297,20 @@ aao_status aao_solve(aao_ctx* c, const double* rhs, double* u, int use_guess, do
         // is not stored: the early test below needs only its dots and norm.
         // If the test then does not stop the solve, the pass is run again
         // with the store.
-        const bool nostore = probe && last_est * (last_est / prev_est) <= tol;
-        TRY(stencil_fused(c, 2, zj, nostore ? nullptr : w, nullptr, basis, q, o_h1, is2,
-                          probe ? o_w2 : -1));
+        const bool nostore = !done && probe && last_est * (last_est / prev_est) <= tol;
+        if (done) {
+          // c1 = (W_0^T w) / s_0^2 with the scale now known, as the reduction
+          // would have applied it; the Gram-Schmidt pass reads it on the device
+          c->hsmall[o_h1] *= c->hsmall[o_is2];
+          HIPCHK(c, hipMemcpyAsync(c->dsmall + o_h1, c->hsmall + o_h1, sizeof(double),
+                                   hipMemcpyHostToDevice, c->stream));
+          pre = false;
+        } else {
+          TRY(stencil_fused(c, 2, zj, nostore ? nullptr : w, nullptr, basis, q, o_h1, is2,
+                            probe ? o_w2 : -1));
+        }
         if (probe) {
-          TRY(fetch_small2(c, o_h1, q, o_w2, 1));
+          if (!done) TRY(fetch_small2(c, o_h1, q, o_w2, 1));
           const double w2 = c->hsmall[o_w2];
           double proj2 = 0.0;
           for (int i = 0; i < q; ++i) {

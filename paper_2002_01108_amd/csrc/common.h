@@ -107,16 +107,18 @@ hipError_t launch_apply_L_var(const Geometry& g, const double* x, double* y, con
 // Fused stencil passes (2D/3D only; AAO dim 1 uses the plain kernel).
 // epi 1: partial sums of (f - L x)^2, one per block, y unused (may be null);
 // epi 2: y = L x (not stored when y is null) and partial dots of L x with
-// basis[0..q-1] (q <= kStencilDotsMax), q per block, and (wsq non-null)
-// partial sums of (L x)^2, one per block in wsq.
+// basis[0..q-1] (q <= kStencilDotsMax), q per block, (wsq non-null) partial
+// sums of (L x)^2, one per block in wsq, and (w0sq non-null, q = 1 only)
+// partial sums of basis[0]^2, one per block in w0sq.
 // Constant coefficient: c1..c3 with ax = null; variable: ax, ay, az face weights.
-// part must hold stencil_partials(g) * q doubles, wsq stencil_partials(g).
+// part must hold stencil_partials(g) * q doubles, wsq and w0sq stencil_partials(g).
 constexpr int kStencilDotsMax = 4;
 int64_t stencil_partials(const Geometry& g);
 hipError_t launch_apply_L_epi(const Geometry& g, int epi, const double* x, double* y,
                               const double* f, const double* const* basis, int q, double* part,
-                              double* wsq, double c1, double c2, double c3, const double* ax,
-                              const double* ay, const double* az, hipStream_t s);
+                              double* wsq, double* w0sq, double c1, double c2, double c3,
+                              const double* ax, const double* ay, const double* az,
+                              hipStream_t s);
 
 // Step 1: Gamma_eps scaling + forward time DFT (theta = e^{+2 pi i/n}) of a real
 // [n][m] array into split re/im planes spec[k][2][PS], k = 0..n/2.

@@ -121,6 +121,7 @@ struct StencilEpi {
   const double* w[4];     // EPI 2: basis vectors
   double* part;
   double* wsq;            // EPI 2, optional: partial sums of (L x)^2 per block
+  double* w0sq;           // EPI 2 with Q = 1, optional: partial sums of w[0]^2 per block
 };
 
 // Q1: 2D finite elements on a uniform grid (Section 5): L = R (x) M + tau I (x) K with
@@ -134,7 +135,8 @@ struct Q1W {
   double m0, m1, m2, k0, k1;
 };
 
-template <int DIM, bool VAR, int TY, int TC, int EPI, int Q, bool TWO, bool FE = false>
+template <int DIM, bool VAR, int TY, int TC, int EPI, int Q, bool TWO, bool FE = false,
+          bool SQ = false>
 __global__ __launch_bounds__(256) void k_apply_L25(
     const double* __restrict__ x, double* __restrict__ y, int n, int m1, int m2, int m3, int nxt,
     int nyt, int nct, double c1, double c2, double c3, const double* __restrict__ ax,
@@ -155,7 +157,9 @@ __global__ __launch_bounds__(256) void k_apply_L25(
   // a wave past the last row has nothing to do, but stays for the block reduction
   const bool wave_on = j0 < m2;
   constexpr int NQ = EPI == 2 ? Q : 1;
-  constexpr int NR = EPI == 2 ? Q + 1 : 1;   // EPI 2 also sums (L x)^2
+  // EPI 2 also sums (L x)^2 and (SQ, one basis vector) that vector's squares
+  constexpr bool SQ0 = SQ && EPI == 2 && Q == 1;
+  constexpr int NR = EPI == 2 ? Q + 1 + (SQ0 ? 1 : 0) : 1;
   double red_acc[NR];
 #pragma unroll
   for (int i = 0; i < NR; ++i) red_acc[i] = 0.0;
@@ -276,7 +280,8 @@ __global__ __launch_bounds__(256) void k_apply_L25(
       if (EPI == 2 && out_ok) {
 #pragma unroll
         for (int i = 0; i < NQ; ++i) red_acc[i] += eo[i][t] * acc;
-        red_acc[NR - 1] += acc * acc;
+        red_acc[NQ] += acc * acc;
+        if (SQ0) red_acc[NR - 1] += eo[0][t] * eo[0][t];
       }
       if (TWO) prev2[TWO ? t : 0] = prev[t];
       prev[t] = FE ? mx : c;
@@ -298,8 +303,10 @@ __global__ __launch_bounds__(256) void k_apply_L25(
           red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
       if (threadIdx.x < NQ)
         ep.part[(int64_t)blockIdx.x * NQ + threadIdx.x] = v;
-      else if (ep.wsq)
+      else if (threadIdx.x == NQ && ep.wsq)
         ep.wsq[blockIdx.x] = v;
+      else if (SQ0 && threadIdx.x == NQ + 1 && ep.w0sq)
+        ep.w0sq[blockIdx.x] = v;
     }
   }
 }
@@ -317,7 +324,7 @@ __global__ __launch_bounds__(256) void k_apply_L25(
 // 2.85 ms for the 2.5D walk.
 constexpr int TYZ = 4, TCZ = 2, ZBZ = 32;
 
-template <bool VAR, int EPI, int Q, bool TWO>
+template <bool VAR, int EPI, int Q, bool TWO, bool SQ = false>
 __global__ __launch_bounds__(256) void k_apply_L3z(
     const double* __restrict__ x, double* __restrict__ y, int n, int m1, int m2, int m3, int nxt,
     int nyt, int nzt, int nct, double c1, double c2, double c3, const double* __restrict__ ax,
@@ -341,7 +348,9 @@ __global__ __launch_bounds__(256) void k_apply_L3z(
   const int kn = j0 < m2 ? min(n, k0 + TC) - k0 : 0;
   const int z0 = bz * ZBZ, z1 = min(m3, z0 + ZBZ);
   constexpr int NQ = EPI == 2 ? Q : 1;
-  constexpr int NR = EPI == 2 ? Q + 1 : 1;   // EPI 2 also sums (L x)^2
+  // EPI 2 also sums (L x)^2 and (SQ, one basis vector) that vector's squares
+  constexpr bool SQ0 = SQ && EPI == 2 && Q == 1;
+  constexpr int NR = EPI == 2 ? Q + 1 + (SQ0 ? 1 : 0) : 1;
   double red_acc[NR];
 #pragma unroll
   for (int i = 0; i < NR; ++i) red_acc[i] = 0.0;
@@ -443,7 +452,8 @@ __global__ __launch_bounds__(256) void k_apply_L3z(
         if (EPI == 2 && out_ok) {
 #pragma unroll
           for (int i = 0; i < NQ; ++i) red_acc[i] += eo[i][t] * acc;
-          red_acc[NR - 1] += acc * acc;
+          red_acc[NQ] += acc * acc;
+          if (SQ0) red_acc[NR - 1] += eo[0][t] * eo[0][t];
         }
       }
     }
@@ -474,8 +484,10 @@ __global__ __launch_bounds__(256) void k_apply_L3z(
           red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
       if (threadIdx.x < NQ)
         ep.part[(int64_t)blockIdx.x * NQ + threadIdx.x] = v;
-      else if (ep.wsq)
+      else if (threadIdx.x == NQ && ep.wsq)
         ep.wsq[blockIdx.x] = v;
+      else if (SQ0 && threadIdx.x == NQ + 1 && ep.w0sq)
+        ep.w0sq[blockIdx.x] = v;
     }
   }
 }
@@ -512,35 +524,63 @@ hipError_t launch25(const Geometry& g, const double* x, double* y, double c1, do
   const int nct = (g.n + TC25 - 1) / TC25;
   const int64_t nblk = blocks25(g);
   if (nblk <= 0 || nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
+  // the variants that also sum the basis vector's squares exist for one basis
+  // vector only and run only when asked for (their extra accumulator costs the
+  // 2D kernel a wave per SIMD)
+  constexpr bool SQOK = EPI == 2 && Q == 1;
+  const bool sq = ep.w0sq != nullptr;
+  if (sq && !SQOK) return hipErrorInvalidValue;
   if constexpr (DIM == 3) {
     if (use3z(g)) {
       const Grid3z gz = grid3z(g);
-      if (two)
-        hipLaunchKernelGGL((k_apply_L3z<VAR, EPI, Q, true>), dim3((unsigned)nblk), dim3(256), 0,
-                           s, x, y, g.n, g.m1, g.m2, g.m3, gz.nxt, gz.nyt, gz.nzt, gz.nct, c1, c2,
-                           c3, ax, ay, az, ep, g.r0, g.r1, g.r2);
-      else
-        hipLaunchKernelGGL((k_apply_L3z<VAR, EPI, Q, false>), dim3((unsigned)nblk), dim3(256), 0,
-                           s, x, y, g.n, g.m1, g.m2, g.m3, gz.nxt, gz.nyt, gz.nzt, gz.nct, c1, c2,
-                           c3, ax, ay, az, ep, g.r0, g.r1, g.r2);
+#define L3Z_LAUNCH(TW, S)                                                                     \
+  hipLaunchKernelGGL((k_apply_L3z<VAR, EPI, Q, TW, S>), dim3((unsigned)nblk), dim3(256), 0, s, \
+                     x, y, g.n, g.m1, g.m2, g.m3, gz.nxt, gz.nyt, gz.nzt, gz.nct, c1, c2, c3, ax, \
+                     ay, az, ep, g.r0, g.r1, g.r2)
+      if (sq) {
+        if constexpr (SQOK) {
+          if (two) L3Z_LAUNCH(true, true);
+          else L3Z_LAUNCH(false, true);
+        }
+      } else if (two) {
+        L3Z_LAUNCH(true, false);
+      } else {
+        L3Z_LAUNCH(false, false);
+      }
+#undef L3Z_LAUNCH
       return hipGetLastError();
     }
   }
-#define L25_LAUNCH(TW, F)                                                                   \
-  hipLaunchKernelGGL((k_apply_L25<DIM, VAR, TY25, TC25, EPI, Q, TW, F>), dim3((unsigned)nblk), \
-                     dim3(256), 0, s, x, y, g.n, g.m1, g.m2, g.m3, nxt, nyt, nct, c1, c2, c3,  \
-                     ax, ay, az, ep, g.r0, g.r1, g.r2, qw)
-  if (g.q1) {
+#define L25_LAUNCH(TW, F, S)                                                                   \
+  hipLaunchKernelGGL((k_apply_L25<DIM, VAR, TY25, TC25, EPI, Q, TW, F, S>),                     \
+                     dim3((unsigned)nblk), dim3(256), 0, s, x, y, g.n, g.m1, g.m2, g.m3, nxt, nyt, \
+                     nct, c1, c2, c3, ax, ay, az, ep, g.r0, g.r1, g.r2, qw)
+  if (sq) {
+    if constexpr (SQOK) {
+      if (g.q1) {
+        if constexpr (DIM == 2 && !VAR) {
+          if (two) L25_LAUNCH(true, true, true);
+          else L25_LAUNCH(false, true, true);
+        } else {
+          return hipErrorInvalidValue;
+        }
+      } else if (two) {
+        L25_LAUNCH(true, false, true);
+      } else {
+        L25_LAUNCH(false, false, true);
+      }
+    }
+  } else if (g.q1) {
     if constexpr (DIM == 2 && !VAR) {
-      if (two) L25_LAUNCH(true, true);
-      else L25_LAUNCH(false, true);
+      if (two) L25_LAUNCH(true, true, false);
+      else L25_LAUNCH(false, true, false);
     } else {
       return hipErrorInvalidValue;   // Q1 elements: 2D constant coefficient only
     }
   } else if (two) {
-    L25_LAUNCH(true, false);
+    L25_LAUNCH(true, false, false);
   } else {
-    L25_LAUNCH(false, false);
+    L25_LAUNCH(false, false, false);
   }
 #undef L25_LAUNCH
   return hipGetLastError();
@@ -582,15 +622,18 @@ int64_t stencil_partials(const Geometry& g) { return g.dim >= 2 ? blocks25(g) : 
 
 hipError_t launch_apply_L_epi(const Geometry& g, int epi, const double* x, double* y,
                               const double* f, const double* const* basis, int q, double* part,
-                              double* wsq, double c1, double c2, double c3, const double* ax,
-                              const double* ay, const double* az, hipStream_t s) {
+                              double* wsq, double* w0sq, double c1, double c2, double c3,
+                              const double* ax, const double* ay, const double* az,
+                              hipStream_t s) {
   if (g.dim < 2 || (epi == 2 && (q < 1 || q > kStencilDotsMax)) || (epi != 1 && epi != 2))
     return hipErrorInvalidValue;
+  if (w0sq && !(epi == 2 && q == 1)) return hipErrorInvalidValue;
   StencilEpi ep{};
   ep.f = f;
   for (int i = 0; i < 4; ++i) ep.w[i] = (epi == 2 && i < q) ? basis[i] : nullptr;
   ep.part = part;
   ep.wsq = epi == 2 ? wsq : nullptr;
+  ep.w0sq = w0sq;
   const bool var = ax != nullptr;
 #define L25(D, V, E, Q) launch25<D, V, E, Q>(g, x, y, c1, c2, c3, ax, ay, az, ep, s)
 #define DOTS(D, V)                        \

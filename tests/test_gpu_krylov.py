@@ -19,6 +19,13 @@ storing L z (only its dots and norm are needed if the early test stops there);
 a missed prediction reruns the pass with the store, exercised here by the
 BF16x3 solve to 1e-10 (its third step was predicted to end the solve and
 does not).
+On these large systems a zero-guess solve takes ||rhs|| from its first step's
+fused stencil (which reads rhs as the first basis vector) instead of a pass of
+its own; the first projection is computed unscaled and rescaled on the host.
+Checked here besides the accuracy above: a right-hand side scaled so far that
+1/||rhs||^2 is not representable (the solve then starts over with the basis
+vector rescaled) gives the scaled solution with the same iterations, a
+non-finite right-hand side is refused, and a zero one gives u = 0.
 The solves at tol = 1e-8 also take the selective second correction: after the
 first Gram-Schmidt pass the second-pass dots give the cosines of w' with the
 basis, and when all are below 1e-3 tol (here about 1e-12 after the first step)
@@ -107,3 +114,30 @@ def test_store_prediction_miss_reruns_the_pass(case):
     assert info["status"] == 0 and info["iters"] >= 4
     assert info["final_res"] <= 1e-10 * (1 + 1e-6)
     assert float(np.linalg.norm(u - ex) / np.linalg.norm(ex)) <= 1e-8
+
+
+@pytest.mark.parametrize("scale", [1e140, 1e-140])
+def test_first_step_norm_out_of_range(case, scale):
+    p, rhs, ex = case
+    u, info = solve(p, rhs, "fp64", 1e-8)
+    us, infos = solve(p, rhs * scale, "fp64", 1e-8)
+    print(scale, "iters", info["iters"], infos["iters"], "final", infos["final_res"], flush=True)
+    assert infos["status"] == 0 and infos["iters"] == info["iters"]
+    assert infos["final_res"] <= 1e-8
+    assert rel(us / scale, u) <= 1e-12
+
+
+def test_first_step_norm_nan_and_zero(case):
+    from paper_2002_01108_amd import AaoError, Solver
+    p, rhs, _ = case
+    s = Solver(2, p.m1, p.n, T=1.0, eps=p.eps, precision="fp64")
+    bad = rhs.copy()
+    bad[70, 1234] = np.nan
+    with pytest.raises(AaoError) as e:
+        s.solve(torch.from_numpy(bad).cuda(), tol=1e-8, maxit=20)
+    assert e.value.status == -4
+    u = torch.full((p.n, p.m), 7.0, dtype=torch.float64, device="cuda")
+    u, info = s.solve(torch.zeros((p.n, p.m), dtype=torch.float64, device="cuda"), tol=1e-8,
+                      maxit=20, u=u)
+    assert info["iters"] == 0 and info["final_res"] == 0.0
+    assert bool(torch.all(u == 0))
