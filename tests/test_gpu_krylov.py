@@ -180,3 +180,23 @@ def test_zero_guess_start_matches_general_start(op):
     assert i1["iters"] == i2["iters"]
     assert i1["final_res"] <= 1e-10 and i2["final_res"] <= 1e-10
     assert d <= 1e-12
+
+
+@pytest.mark.parametrize("restart", [1, 2])
+def test_zero_guess_start_with_restarts(case, restart):
+    """Short restart cycles: the loop resumes after the first step taken before
+    it, then restarts from the explicit residual; the general start gives the
+    same iterates."""
+    from paper_2002_01108_amd import Solver
+    p, rhs, ex = case
+    s = Solver(2, p.m1, p.n, T=1.0, eps=p.eps, precision="fp64")
+    r = torch.from_numpy(rhs).cuda()
+    u1, i1 = s.solve(r, tol=1e-10, maxit=40, restart=restart)
+    u2, i2 = s.solve(r, tol=1e-10, maxit=40, restart=restart, u=torch.zeros_like(r),
+                     use_guess=True)
+    d = float(((u1 - u2).norm() / u2.norm()).item())
+    print(restart, "iters", i1["iters"], i2["iters"], "final", i1["final_res"], "diff", d,
+          flush=True)
+    assert i1["status"] == 0 and i2["status"] == 0 and i1["iters"] == i2["iters"]
+    assert i1["final_res"] <= 1e-10 and d <= 1e-12
+    assert rel(host(u1), ex) <= 1e-9
