@@ -168,6 +168,39 @@ __global__ void k_multi_axpy(const double* __restrict__ Z, int64_t ldz, int q,
   }
 }
 
+// The same for Q <= 4 vectors known at compile time, two elements per thread
+// and access (Z, x and the row stride 16-byte aligned): all loads of an element
+// pair are issued together.  Same summation order as k_multi_axpy.
+template <int Q>
+__global__ void k_multi_axpy2(const double* __restrict__ Z, int64_t ldz,
+                              const double* __restrict__ c, double* __restrict__ x, int64_t len,
+                              int set) {
+  double ci[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) ci[i] = c[i];
+  const int64_t npair = len >> 1;
+  double2* x2 = reinterpret_cast<double2*>(x);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < npair;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double2 z[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) z[i] = reinterpret_cast<const double2*>(Z + i * ldz)[e];
+    double2 s = set ? double2{0.0, 0.0} : x2[e];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      s.x += ci[i] * z[i].x;
+      s.y += ci[i] * z[i].y;
+    }
+    x2[e] = s;
+  }
+  if ((len & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double s = set ? 0.0 : x[len - 1];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) s += ci[i] * Z[i * ldz + len - 1];
+    x[len - 1] = s;
+  }
+}
+
 // part[b] = partial ||a - b||^2 (b null -> ||a||^2); non-finite values propagate
 __global__ __launch_bounds__(KT) void k_diffnorm(const double* __restrict__ a,
                                                  const double* __restrict__ b, int64_t len,
@@ -285,6 +318,26 @@ hipError_t launch_scale_host(const double* x, double* y, int64_t len, double alp
 
 hipError_t launch_multi_axpy(const double* Z, int64_t ldz, int q, const double* c, double* x,
                              int64_t len, int set, hipStream_t s) {
+  const bool vec = q >= 1 && q <= 4 && ((uintptr_t)Z % 16 == 0) && ((uintptr_t)x % 16 == 0) &&
+                   (ldz % 2 == 0);
+  if (vec) {
+    const unsigned g = simple_grid((len + 1) / 2);
+    switch (q) {
+      case 1:
+        hipLaunchKernelGGL((k_multi_axpy2<1>), dim3(g), dim3(256), 0, s, Z, ldz, c, x, len, set);
+        break;
+      case 2:
+        hipLaunchKernelGGL((k_multi_axpy2<2>), dim3(g), dim3(256), 0, s, Z, ldz, c, x, len, set);
+        break;
+      case 3:
+        hipLaunchKernelGGL((k_multi_axpy2<3>), dim3(g), dim3(256), 0, s, Z, ldz, c, x, len, set);
+        break;
+      default:
+        hipLaunchKernelGGL((k_multi_axpy2<4>), dim3(g), dim3(256), 0, s, Z, ldz, c, x, len, set);
+        break;
+    }
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_multi_axpy, dim3(simple_grid(len)), dim3(256), 0, s, Z, ldz, q, c, x, len,
                      set);
   return hipGetLastError();
