@@ -323,6 +323,11 @@ __global__ __launch_bounds__(256) void k_apply_L25(
 // ZBZ 32..128) TYZ = 4, TCZ = 2, ZBZ = 32 was fastest: 2.52 ms for L v against
 // 2.85 ms for the 2.5D walk.
 constexpr int TYZ = 4, TCZ = 2, ZBZ = 32;
+// Time chunks are ordered in groups of CGZ just inside the x tiles, so that
+// the chunks of one patch that follow each other in time run at the same time
+// on one XCD: the level before a chunk, which the previous chunk of the group
+// loads as its own, then usually comes from L2 (when the chunk count allows it).
+constexpr int CGZ = 4;
 
 template <bool VAR, int EPI, int Q, bool TWO, bool SQ = false>
 __global__ __launch_bounds__(256) void k_apply_L3z(
@@ -333,10 +338,12 @@ __global__ __launch_bounds__(256) void k_apply_L3z(
   constexpr int TY = TYZ, TC = TCZ;
   const int nblk = nxt * nyt * nzt * nct;
   int b = xcd_remap(blockIdx.x, nblk);
+  const int cg = nct % CGZ == 0 ? CGZ : 1;
   const int bx = b % nxt; b /= nxt;
+  const int cl = b % cg; b /= cg;
   const int by = b % nyt; b /= nyt;
   const int bz = b % nzt;
-  const int bc = b / nzt;
+  const int bc = (b / nzt) * cg + cl;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i1 = bx * XW - 1 + lane;
   const bool inx = i1 >= 0 && i1 < m1;
