@@ -572,12 +572,11 @@ hipError_t launch_fold_bf3_fr(const float* in, float* out, const fu16* const* T,
 // combinations: O_r = A^{+-}[q] . u^{+-},  E_r = B^{+-}[q] . v^{+-}, four
 // quarter-size products (tables [4][Hq][Hq], Hq = P/4: A+, A-, B+, B-) in
 // place of the two half-size ones, then y_r = O_r + E_r, y_{m-1-r} = O_r - E_r
-// as before.  Block tile: 32 quarter indices (64 rows r) x 64 columns; the
-// four +- combinations of a K slice are formed in registers and staged in one
-// LDS buffer (register prefetch of the next slice).
-constexpr int FQ = 32;
-
-template <typename T, bool LEFT, bool DIVIDE>
+// as before.  Block tile: FQ quarter indices (2 FQ rows r) x 64 columns, FQ = 32
+// (FP64) or 64 (FP32 with Hq a multiple of 64: half the blocks re-read a data
+// tile); the four +- combinations of a K slice are formed in registers and
+// staged in one LDS buffer (register prefetch of the next slice).
+template <typename T, bool LEFT, bool DIVIDE, int FQ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_dst_fold2(
     const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ tabs, FoldArgs f,
     const double* __restrict__ lam, const double* __restrict__ tmu1,
@@ -614,13 +613,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // covers (plane, row) = g + 16 e.
   const int d_pl = w >> 1;
   const int r_c = tid & 15, r_g = tid >> 4;
-  T xa[8], xb[8], rt_[4];
-  const int t_tab = tid >> 6, t_q = (tid & 63) >> 1, t_t = (tid & 1) * 4;
+  // table staging: 64 threads per table, TPQ of them per quarter index, TE
+  // consecutive t each
+  constexpr int TPQ = 64 / FQ, TE = FBK / TPQ;
+  T xa[8], xb[8], rt_[TE];
+  const int t_tab = tid >> 6, t_q = (tid & 63) / TPQ, t_t = ((tid & 63) % TPQ) * TE;
 
   auto mirror = [&](int t, int par) { return par ? h - 2 - t : h - 1 - t; };
   auto fetch = [&](int t0) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
+    for (int e = 0; e < TE; ++e)
       rt_[e] = tabs[((int64_t)t_tab * Hq + q0 + t_q) * Hq + t0 + t_t + e];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -670,7 +672,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     // combine: + and - of each pair; the middle keeps x alone in +, beyond-
     // the-pairs indices contribute zero (their table columns are zero too)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) Ts[t_tab][t_t + e][t_q] = rt_[e];
+    for (int e = 0; e < TE; ++e) Ts[t_tab][t_t + e][t_q] = rt_[e];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       int lt, par, pl, pos;
@@ -826,30 +828,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
 }
 
-template <typename T>
-hipError_t launch_fold2(const T* in, T* out, const T* tabs, const FoldArgs& f, bool left,
-                        const double* lam, const double* tmu1, const double* tmu2,
-                        const double* tmu3, hipStream_t s) {
+template <typename T, int FQ>
+hipError_t launch_fold2_fq(const T* in, T* out, const T* tabs, const FoldArgs& f, bool left,
+                           const double* lam, const double* tmu1, const double* tmu2,
+                           const double* tmu3, hipStream_t s) {
   const int64_t nblk = (int64_t)(f.Hp / 2 / FQ) * f.ndt * f.nout * f.nk;
   if (nblk > 0x7fffffff || nblk < 1) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)nblk), blk(256);
   const bool div = lam != nullptr;
   if (left) {
     if (div)
-      hipLaunchKernelGGL((k_dst_fold2<T, true, true>), grid, blk, 0, s, in, out, tabs, f, lam,
+      hipLaunchKernelGGL((k_dst_fold2<T, true, true, FQ>), grid, blk, 0, s, in, out, tabs, f, lam,
                          tmu1, tmu2, tmu3);
     else
-      hipLaunchKernelGGL((k_dst_fold2<T, true, false>), grid, blk, 0, s, in, out, tabs, f, lam,
-                         tmu1, tmu2, tmu3);
+      hipLaunchKernelGGL((k_dst_fold2<T, true, false, FQ>), grid, blk, 0, s, in, out, tabs, f,
+                         lam, tmu1, tmu2, tmu3);
   } else {
     if (div)
-      hipLaunchKernelGGL((k_dst_fold2<T, false, true>), grid, blk, 0, s, in, out, tabs, f, lam,
-                         tmu1, tmu2, tmu3);
+      hipLaunchKernelGGL((k_dst_fold2<T, false, true, FQ>), grid, blk, 0, s, in, out, tabs, f,
+                         lam, tmu1, tmu2, tmu3);
     else
-      hipLaunchKernelGGL((k_dst_fold2<T, false, false>), grid, blk, 0, s, in, out, tabs, f, lam,
-                         tmu1, tmu2, tmu3);
+      hipLaunchKernelGGL((k_dst_fold2<T, false, false, FQ>), grid, blk, 0, s, in, out, tabs, f,
+                         lam, tmu1, tmu2, tmu3);
   }
   return hipGetLastError();
+}
+
+// FP32 takes 64 quarter indices per block where Hq allows it (196-217 VGPRs,
+// no spills): at 511^2 x 512 the products take 517-582 us against 571-595 us
+// with 32 (FP64 with 64 would not fit the registers)
+constexpr int FQ32 = 64;
+template <typename T>
+hipError_t launch_fold2(const T* in, T* out, const T* tabs, const FoldArgs& f, bool left,
+                        const double* lam, const double* tmu1, const double* tmu2,
+                        const double* tmu3, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if ((f.Hp / 2) % FQ32 == 0)
+      return launch_fold2_fq<T, FQ32>(in, out, tabs, f, left, lam, tmu1, tmu2, tmu3, s);
+  }
+  return launch_fold2_fq<T, 32>(in, out, tabs, f, left, lam, tmu1, tmu2, tmu3, s);
 }
 
 

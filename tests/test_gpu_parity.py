@@ -245,8 +245,11 @@ def test_zero_rhs():
 # ------------------------------------------------------------------ FP32 preconditioner
 
 @pytest.mark.parametrize("dim,m1,n,eps", [(1, 63, 64, 0.125), (2, 100, 128, 1.0 / 11),
-                                          (3, 20, 64, 0.125), (2, 65, 512, 0.05)])
+                                          (3, 20, 64, 0.125), (2, 65, 512, 0.05),
+                                          (2, 255, 8, 0.1), (2, 511, 4, 0.1)])
 def test_fp32_steps(dim, m1, n, eps):
+    """FP32 Steps 1 and P^{-1} against the oracle; 255^2 and 511^2 reach the
+    two-level fold with 64 quarter indices per block (P = 256, 512)."""
     p = heat.Problem(m1, dim, n, eps=eps)
     s = solver(dim, m1, n, eps, precision="fp32")
     y = _rand((n, p.m), 10)
