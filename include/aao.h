@@ -329,7 +329,9 @@ aao_status aao_step3(aao_ctx *ctx, const double *zt, double *z);
  * Returns AAO_OK on convergence (a breakdown h_{j+1,j} = 0 is convergence),
  * AAO_NOT_CONVERGED if maxit was reached, AAO_ENAN for a non-finite rhs,
  * AAO_EINVAL for tol < 0, maxit < 1, restart < 1, null vectors or rhs and u
- * overlapping. */
+ * overlapping.  A non-finite rhs is found from ||rhs||, which a zero-guess solve
+ * of a large system (n*m >= 2^22, tol > 0, right preconditioning) takes from its
+ * first Arnoldi step: P^-1 and L have then run once; u is left unchanged. */
 aao_status aao_solve(aao_ctx *ctx, const double *rhs, double *u, int use_guess, double tol,
                      int maxit, int restart, int *iters, double *res_hist, int hist_cap,
                      int *hist_len, double *final_res);
